@@ -1,0 +1,250 @@
+/*
+ * fcat -- polyenergetic cone-beam projector for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libfcat.so.  The projector computes, for every projection angle
+ * and detector pixel, the fastCAT detected signal (O'Connell and
+ * Bazalova-Carter, "FastCAT: Fast Cone Beam CT (CBCT) Simulation",
+ * arXiv 2011.04736):
+ *
+ *   L_m      = length of the source-to-pixel-centre ray inside material m
+ *              (Sec. II.F: a projection is the line integral of the
+ *              attenuation along the ray; Sec. II.C: the phantom is an array
+ *              of integer material labels 0..n-1, so mu(E, x) = mu_label(x)(E));
+ *   P_e      = sum_m mu[m][e] L_m                        (one projection per energy, Sec. II.F)
+ *   Y_g      = sum_{e in group g} phi_e eta_e (I0 exp(-P_e) + s_e S)
+ *              (Eq. 3, with the scatter map S added to the primary intensity
+ *              profiles before the spectrum x response weighting, Sec. II.F)
+ *   out      = sum_g K_g (*) Y_g                         (Sec. II.G: each profile is
+ *              convolved with its optical spread function, Eq. 1, and summed)
+ *
+ * Geometry conventions (the paper fixes none of them; these are this
+ * library's): world z is the rotation axis and the isocentre is the origin;
+ * the source is at (SID cos t, SID sin t, 0); the detector centre at
+ * -(SDD - SID)(cos t, sin t, 0); the detector u axis is (-sin t, cos t, 0)
+ * and v axis (0, 0, 1); pixel (iv, iu) has its centre at
+ * c + ((iu - (Nu-1)/2) du + off_u) u + ((iv - (Nv-1)/2) dv + off_v) v;
+ * t_a = 2 pi a / A unless explicit angles are given.  Voxel (ix, iy, iz) is
+ * the half-open box [x0 + ix dx, x0 + (ix+1) dx) x ... with
+ * x0 = cx - Nx dx / 2.  Lengths are in mm, attenuation in mm^-1.
+ *
+ * Memory and ordering rules for every entry point:
+ *  - Descriptors are host structs, read during the call only.
+ *  - Every array pointer is caller-owned DEVICE memory unless its comment
+ *    says HOST.  The library never allocates, frees or retains device
+ *    memory; scratch comes only from the caller's workspace (256-byte
+ *    aligned, at least the size the matching *_workspace_bytes returns).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *    and is asynchronous with respect to the host, except fcat_check_inputs,
+ *    which synchronises its stream.  Calls on different streams must use
+ *    different workspaces.
+ *  - Arguments are validated on the host before anything is launched; on a
+ *    non-OK status nothing has been enqueued and outputs are untouched.
+ *    fcat_last_error() then gives a description.  Device-side failures of
+ *    earlier work surface as FCAT_E_DEVICE from a later call.
+ *  - Labels outside 0..n_mat-1 are never used as an index: such voxels add
+ *    no path length to any material.  fcat_check_inputs reports them.
+ */
+#ifndef FCAT_H
+#define FCAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCAT_VERSION 1
+
+/* Largest supported sizes. */
+#define FCAT_MAX_MATERIALS 32   /* n_mat */
+#define FCAT_MAX_GROUPS 32      /* n_groups */
+#define FCAT_MAX_ENERGIES 4096  /* n_energy */
+#define FCAT_MAX_PSF 31         /* psf k (odd) */
+
+typedef enum fcat_status {
+    FCAT_OK = 0,
+    FCAT_E_INVALID_ARG = 1,  /* null pointer, bad size, SDD <= SID, even k, bad group map ... */
+    FCAT_E_WORKSPACE = 2,    /* workspace missing, misaligned or too small */
+    FCAT_E_LABEL_RANGE = 3,  /* fcat_check_inputs: a label is outside 0..n_mat-1 */
+    FCAT_E_NONFINITE = 4,    /* fcat_check_inputs: NaN or Inf in a float table */
+    FCAT_E_DEVICE = 5,       /* a HIP runtime error (text in fcat_last_error) */
+    FCAT_E_UNSUPPORTED = 6   /* a valid request this build does not implement */
+} fcat_status;
+
+typedef enum fcat_mode {
+    FCAT_MODE_PLAIN = 0,       /* FP32 traversal and FP32 spectral sum */
+    FCAT_MODE_SPLIT_BF16 = 1,  /* L . mu on matrix cores, BF16 hi/lo split, FP32 accumulate */
+    FCAT_MODE_SURROGATE = 2    /* learned per-group attenuation with exact fallback */
+} fcat_mode;
+
+/* Circular cone-beam geometry (Sec. II: SAD 1.00 m, SDD 1.52 m by default). */
+typedef struct fcat_geometry_t {
+    double sid_mm;            /* source to isocentre, > 0 */
+    double sdd_mm;            /* source to detector, > sid_mm */
+    int32_t nu, nv;           /* detector columns (u, fastest) and rows, >= 1 */
+    double du_mm, dv_mm;      /* pixel pitch, > 0 */
+    double off_u_mm, off_v_mm;/* detector shift along u and v */
+    int32_t n_angles;         /* >= 1 */
+    const double *angles_rad; /* DEVICE [n_angles] radians, or NULL for 2 pi a / n_angles */
+} fcat_geometry_t;
+
+/* Labelled voxel phantom (Sec. II.C). */
+typedef struct fcat_phantom_t {
+    int32_t nx, ny, nz;       /* >= 1 each */
+    double dx_mm, dy_mm, dz_mm;
+    double cx_mm, cy_mm, cz_mm; /* centre of the grid */
+    const int8_t *labels;     /* DEVICE [nz][ny][nx], x fastest */
+} fcat_phantom_t;
+
+/* Attenuation tables, spectrum and detector response (Sec. II.A-C, Eq. 3). */
+typedef struct fcat_spectral_t {
+    int32_t n_mat;            /* 1..FCAT_MAX_MATERIALS */
+    int32_t n_energy;         /* 1..FCAT_MAX_ENERGIES */
+    int32_t n_groups;         /* 1..min(n_energy, FCAT_MAX_GROUPS) */
+    const float *mu;          /* DEVICE [n_mat][n_energy], mm^-1 */
+    const float *phi;         /* DEVICE [n_energy] fluence spectrum */
+    const float *eta;         /* DEVICE [n_energy] energy deposition efficiency */
+    const float *flood;       /* DEVICE [nv][nu] flood intensity I0, or NULL for 1 */
+    const int32_t *group_of_bin; /* HOST [n_energy], non-decreasing, each group non-empty,
+                                    or NULL for floor(e * n_groups / n_energy) */
+} fcat_spectral_t;
+
+/* Pre-tabulated scatter (Sec. II.E), added to the primary profiles. */
+typedef struct fcat_scatter_t {
+    const float *maps;        /* DEVICE [n_angles][nv][nu] */
+    const float *s_bin;       /* DEVICE [n_energy] per-bin scale, or NULL for 1 */
+} fcat_scatter_t;
+
+/* Optical spread kernels per energy group (Eq. 1, Sec. II.G). */
+typedef struct fcat_psf_t {
+    int32_t k;                /* odd, 1..FCAT_MAX_PSF */
+    const float *kernels;     /* DEVICE [n_groups][k][k]; out = sum_g K_g (*) Y_g, true
+                                 convolution, zero outside the detector, centre (k-1)/2 */
+} fcat_psf_t;
+
+/*
+ * Learned replacement of the primary spectral sum (MLP with SiLU).
+ * For a ray with path lengths L (n_in = n_mat values):
+ *   x_m  = L_m * in_scale[m]
+ *   z_g  = sum_m lin[g][m] L_m + MLP(x)_g
+ *   Y_g  = I0 W_g exp(-z_g) + Ws_g S          with W_g = sum_{e in g} phi_e eta_e
+ * MLP: h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), MLP(x) = W3 h2 + b3, with
+ * weights rounded to BF16 and FP32 accumulation.  The exact spectral sum is
+ * used instead wherever the ray falls outside the validated domain: the ray
+ * misses, some x_m > 1, log10(sum_m L_m) is outside [cell_lo, cell_hi), or
+ * cell_ok[dominant material * 16 + log-length bin] is 0.
+ */
+#define FCAT_MLP_HIDDEN 64
+#define FCAT_MLP_CELLS 16
+typedef struct fcat_surrogate_t {
+    int32_t n_in;             /* == n_mat, <= 16 */
+    int32_t n_out;            /* == n_groups, <= 16 */
+    const float *params;      /* DEVICE FP32: W1[64][n_in], b1[64], W2[64][64], b2[64],
+                                 W3[n_out][64], b3[n_out] */
+    const float *in_scale;    /* DEVICE [n_in] */
+    const float *lin;         /* DEVICE [n_out][n_in] */
+    const uint8_t *cell_ok;   /* DEVICE [n_in * 16] */
+    float cell_lo, cell_hi;   /* log10(mm) range of the 16 length bins */
+} fcat_surrogate_t;
+
+/* ---------------------------------------------------------------- status */
+
+/* Static description of a status code. */
+const char *fcat_status_string(fcat_status s);
+/* Detail of the last non-OK status returned on the calling thread ("" if none). */
+const char *fcat_last_error(void);
+/* FCAT_VERSION of the built library. */
+int fcat_version(void);
+
+/* ------------------------------------------------------------ projector */
+
+/*
+ * Workspace needed by fcat_project.  angles_per_chunk = 0 lets the library
+ * choose (group signals of at most ~64 MiB per chunk); a larger workspace
+ * passed to fcat_project lets it process more angles per chunk.  Returns 0 if
+ * the descriptors are invalid.
+ */
+size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                    const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                                    const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk);
+
+/*
+ * Full projector: out[a][v][u] (DEVICE float [n_angles][nv][nu]) for every
+ * angle and pixel.  scatter NULL turns the scatter term off; psf NULL turns
+ * the optical spread off (out = sum_g Y_g).  surrogate is required for
+ * FCAT_MODE_SURROGATE and ignored otherwise.
+ */
+fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                         const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                         const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
+                         float *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Per-material path lengths (Sec. II.F line integral, Sec. II.C labels) of
+ * every pixel of angles a_begin <= a < a_end:
+ * L = DEVICE float [a_end - a_begin][nv][nu][n_mat].  No workspace.
+ */
+fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                             int32_t n_mat, int32_t a_begin, int32_t a_end, float *L, void *stream);
+
+/* Workspace needed by fcat_spectral. */
+size_t fcat_spectral_workspace_bytes(const fcat_spectral_t *spectral);
+
+/*
+ * Eq. 3 for a list of rays: Y[g][r] (DEVICE float [n_groups][n]) from
+ * L (DEVICE float [n][n_mat]).  i0 (DEVICE [n]) NULL means 1; S (DEVICE [n])
+ * NULL means no scatter; s_bin (DEVICE [n_energy]) NULL means 1.
+ * spectral->flood is ignored (pass i0).  mode PLAIN or SPLIT_BF16.
+ */
+fcat_status fcat_spectral(const float *L, int64_t n, const fcat_spectral_t *spectral,
+                          const float *i0, const float *S, const float *s_bin, fcat_mode mode,
+                          float *Y, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Optical spread and group sum (Sec. II.G): out[a][v][u] =
+ * sum_g sum_{p,q} K[g][p][q] Y[a][g][v-p+c][u-q+c], zero outside, c = (k-1)/2.
+ * Y DEVICE float [n_ang][n_groups][nv][nu], out DEVICE float [n_ang][nv][nu].
+ */
+fcat_status fcat_psf(const float *Y, int32_t n_ang, int32_t n_groups, int32_t nv, int32_t nu,
+                     const fcat_psf_t *psf, float *out, void *stream);
+
+/*
+ * Device-data validation (synchronises `stream`): labels in 0..n_mat-1 and
+ * every float table finite.  Any descriptor but phantom and spectral may be
+ * NULL.  Needs 256 bytes of workspace.  Returns FCAT_E_LABEL_RANGE or
+ * FCAT_E_NONFINITE on a violation.
+ */
+fcat_status fcat_check_inputs(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                              const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                              const fcat_psf_t *psf, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* ---------------------------------------------------------- kernel timing */
+
+/* Kernel stages whose launches the timing facility tells apart. */
+typedef enum fcat_stage {
+    FCAT_STAGE_PREP = 0,   /* spectral table preparation */
+    FCAT_STAGE_TRACE = 1,  /* fused traversal + contraction + spectral sum (+ scatter) */
+    FCAT_STAGE_PSF = 2,    /* optical spread + group sum */
+    FCAT_STAGE_MLP = 3,    /* surrogate training / inference kernels run on their own */
+    FCAT_STAGE_COUNT = 4
+} fcat_stage;
+
+/*
+ * For benchmarks and profiling.  While enabled (process-wide), every kernel
+ * that fcat_project, fcat_spectral and fcat_psf launch is bracketed by two
+ * HIP events recorded on the same stream.  fcat_timing_read waits for the
+ * recorded events, adds the elapsed milliseconds and launch counts per
+ * stage into ms[n_stages] and launches[n_stages] (HOST arrays, either may be
+ * NULL) and, if reset is non-zero, forgets them.  Events are created with
+ * hipEventCreate and reused.
+ */
+fcat_status fcat_timing_enable(int enable);
+fcat_status fcat_timing_read(double *ms, int64_t *launches, int32_t n_stages, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCAT_H */

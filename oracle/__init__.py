@@ -241,7 +241,7 @@ def psf(Y, kernels, n_threads: int = 0) -> np.ndarray:
 
 
 def project(cfg, angle_idx: Sequence[int], with_groups: bool = False, scatter: bool = True,
-            use_psf: bool = True, n_threads: int = 0):
+            use_psf: bool = True, n_threads: int = 0, scatter_maps=None):
     """FP64 projections out[n_ang][nv][nu] of the listed angles of a configuration.
 
     With ``with_groups`` also returns the group signals Y[n_ang][G][nv][nu]
@@ -258,7 +258,7 @@ def project(cfg, angle_idx: Sequence[int], with_groups: bool = False, scatter: b
     S = None
     sb = None
     if scatter and cfg.scatter is not None:
-        S = _f64(cfg.scatter.maps(ai))
+        S = _f64(cfg.scatter.maps(ai) if scatter_maps is None else scatter_maps)
         sb = _f64(cfg.scatter.s_bin)
     K = None
     k = 1

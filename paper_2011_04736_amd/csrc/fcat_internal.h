@@ -1,0 +1,74 @@
+// Internal declarations shared by the C-ABI layer and the gfx950 kernels of
+// libfcat.so.  Not part of the public interface (include/fcat.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/fcat.h"
+
+namespace fcat {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per workgroup (4 waves)
+constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Ray geometry of one launch, everything a lane needs to build its ray in
+// FP64.  lo/h/n describe the voxel grid; cu/cv are the detector centre
+// indices (N-1)/2.
+struct TraceGeom {
+    double sid, back;              // SID and SDD - SID
+    double du, dv, off_u, off_v;
+    double cu, cv;
+    double lo[3], h[3], inv_h[3];
+    int n[3];
+    int nu, nv, n_angles;
+    const double *angles;          // device, or null for 2 pi a / A
+};
+
+// Spectral tables prepared on the device (in the workspace) from mu, phi,
+// eta and s_bin.  gstart is host-derived from the group map.
+struct SpecTables {
+    const float *muT;              // [E][mp]  (mp = padded material count, zeros past n_mat)
+    const float *w;                // [E]      phi * eta
+    const float *Wg;               // [G]      sum of w over the group
+    const float *Wsg;              // [G]      sum of w * s_bin over the group
+    int E, M, G, mp;
+    int gstart[FCAT_MAX_GROUPS + 1];
+};
+
+// Launch helpers (fcat_kernels.hip).  All are stream-ordered and return the
+// hipError_t of the launch.
+hipError_t launch_prep_tables(const float *mu, const float *phi, const float *eta,
+                              const float *s_bin, const SpecTables &t, float *muT, float *w,
+                              float *Wg, float *Wsg, hipStream_t stream);
+
+// Fused traversal + spectral sum for angles [a0, a0 + n_ang).  When Y is
+// non-null the group signals go to Y[a - a0][g][v][u]; otherwise
+// out[a][v][u] receives their sum.
+hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const SpecTables &t,
+                               const float *flood, const float *scatter, int a0, int n_ang,
+                               float *Y, float *out, hipStream_t stream);
+
+// Same as launch_project_rows with the L . mu contraction on matrix cores
+// (BF16 hi/lo split, FP32 accumulate).
+hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, const SpecTables &t,
+                                     const float *flood, const float *scatter, int a0, int n_ang,
+                                     float *Y, float *out, hipStream_t stream);
+
+hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0,
+                              int n_ang, float *L, hipStream_t stream);
+
+hipError_t launch_spectral(const float *L, int64_t n, const SpecTables &t, const float *i0,
+                           const float *S, bool split, float *Y, hipStream_t stream);
+
+hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const float *kernels,
+                      int k, float *out, hipStream_t stream);
+
+hipError_t launch_check_labels(const int8_t *labels, int64_t n, int n_mat, int *flag,
+                               hipStream_t stream);
+hipError_t launch_check_finite(const float *x, int64_t n, int *flag, hipStream_t stream);
+hipError_t launch_zero_ints(int *p, int n, hipStream_t stream);
+
+}  // namespace fcat

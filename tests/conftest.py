@@ -18,3 +18,23 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def rel_err(x, ref):
+    """Per-pixel relative error |x - ref| / max(|ref|, 1e-12 max|ref|)."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    floor = 1e-12 * max(float(np.abs(ref).max()), 1e-300)
+    return np.abs(x - ref) / np.maximum(np.abs(ref), floor)
+
+
+@pytest.fixture(scope="session")
+def fc():
+    """The HIP library binding (built in-tree if nothing is built yet)."""
+    import paper_2011_04736_amd as fcat
+    if not os.path.exists(fcat.lib_path()):
+        from paper_2011_04736_amd import _build
+        _build.build()
+    fcat.load()
+    return fcat

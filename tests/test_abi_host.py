@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI (no GPU work is launched).
+
+The library must load, export every entry point that include/fcat.h
+declares, and reject invalid arguments on the host before any launch.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(fcat_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol(fc):
+    lib = fc.load()
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
+    assert fc.fcat_version() == 1
+
+
+def test_status_strings(fc):
+    for s in range(7):
+        assert fc.fcat_status_string(s) and fc.fcat_status_string(s) != "unknown status"
+    assert fc.fcat_status_string(99) == "unknown status"
+
+
+def _descs(fc, nu=16, nv=4, A=3, M=3, E=5, G=2, k=15):
+    geo = fc._CGeometry(1000.0, 1500.0, nu, nv, 1.0, 1.0, 0.0, 0.0, A, None)
+    ph = fc._CPhantom(8, 8, 4, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0x1000)
+    sp = fc._CSpectral(M, E, G, 0x2000, 0x3000, 0x4000, None, C.POINTER(C.c_int32)())
+    ps = fc._CPsf(k, 0x5000)
+    return geo, ph, sp, ps
+
+
+def test_workspace_size_query(fc):
+    lib = fc.load()
+    geo, ph, sp, ps = _descs(fc, nu=1024, nv=64, A=360, M=8, E=200, G=8)
+    nops = lib.fcat_project_workspace_bytes(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, 0)
+    withpsf = lib.fcat_project_workspace_bytes(C.byref(geo), C.byref(ph), C.byref(sp), None, C.byref(ps), 0, 0)
+    one = lib.fcat_project_workspace_bytes(C.byref(geo), C.byref(ph), C.byref(sp), None, C.byref(ps), 0, 1)
+    per_angle = 8 * 64 * 1024 * 4
+    assert one - nops == per_angle
+    assert withpsf - nops == 32 * per_angle          # default: 64 MiB of group signal per chunk
+    assert nops > 200 * 8 * 4 and nops % 256 == 0
+    bad = fc._CGeometry(1000.0, 900.0, 16, 4, 1.0, 1.0, 0.0, 0.0, 3, None)
+    assert lib.fcat_project_workspace_bytes(C.byref(bad), C.byref(ph), C.byref(sp), None, None, 0, 0) == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("sid_mm", 0.0), ("sdd_mm", 900.0), ("nu", 0), ("nv", -1), ("du_mm", float("nan")),
+    ("n_angles", 0), ("off_u_mm", float("inf")),
+])
+def test_project_rejects_bad_geometry(fc, field, value):
+    lib = fc.load()
+    geo, ph, sp, ps = _descs(fc)
+    setattr(geo, field, value)
+    out = np.full(4, 7.0, np.float32)
+    st = lib.fcat_project(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, None,
+                          out.ctypes.data, 0x10000, 1 << 20, None)
+    assert st == 1 and lib.fcat_last_error()
+    assert np.all(out == 7.0)
+
+
+def test_project_rejects_bad_descriptors(fc):
+    lib = fc.load()
+    out = np.zeros(4, np.float32)
+
+    def call(geo, ph, sp, ps=None, mode=0, ws=0x10000, wsb=1 << 26):
+        return lib.fcat_project(C.byref(geo), C.byref(ph), C.byref(sp), None,
+                                C.byref(ps) if ps is not None else None, mode, None,
+                                out.ctypes.data, ws, wsb, None)
+
+    geo, ph, sp, ps = _descs(fc)
+    ph.nx = 0
+    assert call(geo, ph, sp) == 1
+    geo, ph, sp, ps = _descs(fc)
+    ph.labels = None
+    assert call(geo, ph, sp) == 1
+    geo, ph, sp, ps = _descs(fc, M=40)
+    assert call(geo, ph, sp) == 1                     # too many materials
+    geo, ph, sp, ps = _descs(fc, G=6, E=5)
+    assert call(geo, ph, sp) == 1                     # more groups than bins
+    geo, ph, sp, ps = _descs(fc, k=14)
+    assert call(geo, ph, sp, ps) == 1                 # even psf
+    geo, ph, sp, ps = _descs(fc)
+    assert call(geo, ph, sp, mode=7) == 1             # unknown mode
+    geo, ph, sp, ps = _descs(fc)
+    for gob in ([0, 0, 1, 0, 1], [0, 0, 0, 0, 0], [0, 2, 2, 2, 2], [0, 0, 1, 1, 5]):
+        arr = np.array(gob, np.int32)
+        sp.group_of_bin = arr.ctypes.data_as(C.POINTER(C.c_int32))
+        assert call(geo, ph, sp) == 1, gob
+    geo, ph, sp, ps = _descs(fc)
+    assert call(geo, ph, sp, ps, ws=0) == 2           # missing workspace
+    assert call(geo, ph, sp, ps, ws=0x10001) == 2     # misaligned workspace
+    assert call(geo, ph, sp, ps, wsb=1024) == 2       # too small
+    assert np.all(out == 0.0)
+
+
+def test_other_entry_points_reject_bad_args(fc):
+    lib = fc.load()
+    geo, ph, sp, ps = _descs(fc)
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 2, 2, 0x1000, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 4, 0x1000, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 0, 0, 1, 0x1000, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 1, None, None) == 1
+    assert lib.fcat_spectral(0x1000, -1, C.byref(sp), None, None, None, 0, 0x2000, 0x10000, 1 << 20, None) == 1
+    assert lib.fcat_spectral(0x1000, 10, C.byref(sp), None, None, None, 2, 0x2000, 0x10000, 1 << 20, None) == 1
+    assert lib.fcat_spectral(0x1000, 10, C.byref(sp), None, None, None, 0, 0x2000, 0, 0, None) == 2
+    bad = fc._CPsf(4, 0x1000)
+    assert lib.fcat_psf(0x1000, 1, 2, 4, 4, C.byref(bad), 0x2000, None) == 1
+    assert lib.fcat_psf(0x1000, 1, 2, 4, 4, None, 0x2000, None) == 1
+    assert lib.fcat_psf(0x1000, 0, 2, 4, 4, C.byref(ps), 0x2000, None) == 1
+    assert lib.fcat_check_inputs(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, 0, None) == 2
+    assert lib.fcat_spectral_workspace_bytes(C.byref(sp)) > 0
