@@ -161,7 +161,7 @@ int fcat_version(void);
 
 /*
  * Workspace needed by fcat_project.  angles_per_chunk = 0 lets the library
- * choose (group signals of at most ~64 MiB per chunk); a larger workspace
+ * choose (group signals of at most 1 GiB per chunk); a larger workspace
  * passed to fcat_project lets it process more angles per chunk.  Returns 0 if
  * the descriptors are invalid.
  */
@@ -180,13 +180,17 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
                          const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
                          float *out, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Workspace needed by fcat_pathlengths (the brick map of the labels). */
+size_t fcat_pathlengths_workspace_bytes(const fcat_phantom_t *phantom);
+
 /*
  * Per-material path lengths (Sec. II.F line integral, Sec. II.C labels) of
  * every pixel of angles a_begin <= a < a_end:
- * L = DEVICE float [a_end - a_begin][nv][nu][n_mat].  No workspace.
+ * L = DEVICE float [a_end - a_begin][nv][nu][n_mat].
  */
 fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
-                             int32_t n_mat, int32_t a_begin, int32_t a_end, float *L, void *stream);
+                             int32_t n_mat, int32_t a_begin, int32_t a_end, float *L, void *workspace,
+                             size_t workspace_bytes, void *stream);
 
 /* Workspace needed by fcat_spectral. */
 size_t fcat_spectral_workspace_bytes(const fcat_spectral_t *spectral);

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "FcatError", "MODES", "Geometry", "Phantom", "Spectral", "Scatter", "Psf", "Problem", "upload",
     "fcat_version", "fcat_status_string", "fcat_last_error", "fcat_project_workspace_bytes",
-    "fcat_project", "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_psf",
+    "fcat_project", "fcat_pathlengths_workspace_bytes", "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_psf",
     "fcat_check_inputs", "fcat_timing_enable", "fcat_timing_read", "STAGES", "lib_path", "load",
 ]
 
@@ -108,7 +108,9 @@ def load() -> C.CDLL:
     L.fcat_project_workspace_bytes.restype = sz
     L.fcat_project.argtypes = [gp, pp, sp, scp, psp, st, sup, vp, vp, sz, vp]
     L.fcat_project.restype = st
-    L.fcat_pathlengths.argtypes = [gp, pp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+    L.fcat_pathlengths_workspace_bytes.argtypes = [pp]
+    L.fcat_pathlengths_workspace_bytes.restype = sz
+    L.fcat_pathlengths.argtypes = [gp, pp, C.c_int32, C.c_int32, C.c_int32, vp, vp, sz, vp]
     L.fcat_pathlengths.restype = st
     L.fcat_spectral_workspace_bytes.argtypes = [sp]
     L.fcat_spectral_workspace_bytes.restype = sz
@@ -318,18 +320,26 @@ def fcat_project(pb: Problem, mode: str = "plain", surrogate=None, out=None, wor
     return out
 
 
+def fcat_pathlengths_workspace_bytes(phantom: Phantom) -> int:
+    cp = phantom.c()
+    return int(load().fcat_pathlengths_workspace_bytes(C.byref(cp)))
+
+
 def fcat_pathlengths(pb: Problem, n_mat: int, a_begin: int = 0, a_end: Optional[int] = None,
-                     out=None, stream=None):
+                     out=None, workspace=None, stream=None):
     """L[a][v][u][m] for angles a_begin <= a < a_end."""
     torch = _require_gpu()
     g = pb.geometry
     a_end = g.n_angles if a_end is None else a_end
+    dev = pb.phantom.labels.device
     if out is None:
-        out = torch.empty((max(a_end - a_begin, 0), g.nv, g.nu, n_mat), dtype=torch.float32,
-                          device=pb.phantom.labels.device)
+        out = torch.empty((max(a_end - a_begin, 0), g.nv, g.nu, n_mat), dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = _workspace(fcat_pathlengths_workspace_bytes(pb.phantom), dev)
     cg, cp = g.c(), pb.phantom.c()
     _check(load().fcat_pathlengths(C.byref(cg), C.byref(cp), int(n_mat), int(a_begin), int(a_end),
-                                   _ptr(out), _stream(stream)))
+                                   _ptr(out), _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                                   _stream(stream)))
     return out
 
 

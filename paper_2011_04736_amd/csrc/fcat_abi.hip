@@ -116,6 +116,16 @@ fcat_status check_psf(const fcat_psf_t *p)
     return FCAT_OK;
 }
 
+// Edge of the cubic bricks of the label map used by the two-level walk.
+constexpr int kBrick = 8;
+
+size_t brick_bytes(const fcat_phantom_t *p)
+{
+    const size_t nb = (size_t)((p->nx + kBrick - 1) / kBrick) * ((p->ny + kBrick - 1) / kBrick) *
+                      ((p->nz + kBrick - 1) / kBrick);
+    return nb;
+}
+
 TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 {
     TraceGeom G{};
@@ -140,15 +150,18 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
     G.nv = g->nv;
     G.n_angles = g->n_angles;
     G.angles = g->angles_rad;
+    G.B = kBrick;
+    for (int ax = 0; ax < 3; ++ax) G.nb[ax] = (n[ax] + kBrick - 1) / kBrick;
+    G.bricks = nullptr;
     return G;
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, Y, fixed;
+    size_t flags, muT, w, Wg, Wsg, bricks, Y, fixed;
     size_t per_angle;  // bytes of group signal per angle (0 without psf)
 };
 
-Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf)
+Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size_t nbricks = 0)
 {
     Layout L{};
     size_t o = 0;
@@ -162,13 +175,15 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf)
     o += align_up((size_t)t.G * sizeof(float));
     L.Wsg = o;
     o += align_up((size_t)t.G * sizeof(float));
+    L.bricks = o;
+    o += align_up(nbricks);
     L.Y = o;
     L.fixed = o;
     L.per_angle = (with_psf && g) ? align_up((size_t)t.G * g->nu * g->nv * sizeof(float)) : 0;
     return L;
 }
 
-constexpr size_t kDefaultChunkBytes = (size_t)64 << 20;
+constexpr size_t kDefaultChunkBytes = (size_t)1 << 30;
 
 int default_chunk(const Layout &L, int n_angles)
 {
@@ -297,7 +312,7 @@ size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_
     if (check_geometry(geometry) || check_phantom(phantom) || check_spectral(spectral, false, t) ||
         check_psf(psf))
         return 0;
-    Layout L = layout(t, geometry, psf != nullptr);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom));
     int chunk = angles_per_chunk > 0 ? angles_per_chunk : default_chunk(L, geometry->n_angles);
     if (chunk > geometry->n_angles) chunk = geometry->n_angles;
     return L.fixed + (size_t)chunk * L.per_angle;
@@ -320,14 +335,21 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     if (mode != FCAT_MODE_PLAIN && mode != FCAT_MODE_SPLIT_BF16 && mode != FCAT_MODE_SURROGATE)
         return fail(FCAT_E_INVALID_ARG, "unknown mode %d", (int)mode);
     if (mode != FCAT_MODE_PLAIN) return fail(FCAT_E_UNSUPPORTED, "mode %d is not built yet", (int)mode);
-    Layout L = layout(t, geometry, psf != nullptr);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom));
     const size_t need = L.fixed + L.per_angle;  // at least one angle per chunk
     if ((s = check_workspace(workspace, workspace_bytes, need))) return s;
     if ((s = check_pending())) return s;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
 
     if ((s = prep_tables(spectral, scatter ? scatter->s_bin : nullptr, t, L, workspace, stream))) return s;
-    const TraceGeom G = make_geom(geometry, phantom);
+    TraceGeom G = make_geom(geometry, phantom);
+    G.bricks = at<int8_t>(workspace, L.bricks);
+    {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        hipError_t e0 = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, G.B,
+                                            at<int8_t>(workspace, L.bricks), stream);
+        if (e0 != hipSuccess) return device_fail(e0, "build_bricks");
+    }
     const float *S = scatter ? scatter->maps : nullptr;
     const int A = geometry->n_angles;
     const int64_t plane = (int64_t)geometry->nu * geometry->nv;
@@ -357,8 +379,15 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     return FCAT_OK;
 }
 
+size_t fcat_pathlengths_workspace_bytes(const fcat_phantom_t *phantom)
+{
+    if (check_phantom(phantom)) return 0;
+    return align_up(brick_bytes(phantom));
+}
+
 fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom, int32_t n_mat,
-                             int32_t a_begin, int32_t a_end, float *L, void *stream)
+                             int32_t a_begin, int32_t a_end, float *L, void *workspace, size_t workspace_bytes,
+                             void *stream_)
 {
     g_last_error.clear();
     fcat_status s;
@@ -368,10 +397,22 @@ fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom
     if (a_begin < 0 || a_end > geometry->n_angles || a_begin >= a_end)
         return fail(FCAT_E_INVALID_ARG, "need 0 <= a_begin < a_end <= n_angles");
     if (!L) return fail(FCAT_E_INVALID_ARG, "L is NULL");
+    if ((s = check_workspace(workspace, workspace_bytes, align_up(brick_bytes(phantom))))) return s;
     if ((s = check_pending())) return s;
-    const TraceGeom G = make_geom(geometry, phantom);
-    hipError_t e = launch_pathlengths(G, phantom->labels, n_mat, a_begin, a_end - a_begin, L,
-                                      static_cast<hipStream_t>(stream));
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    TraceGeom G = make_geom(geometry, phantom);
+    G.bricks = static_cast<int8_t *>(workspace);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, G.B,
+                                static_cast<int8_t *>(workspace), stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "build_bricks");
+    {
+        StageTimer tm(FCAT_STAGE_TRACE, stream);
+        e = launch_pathlengths(G, phantom->labels, n_mat, a_begin, a_end - a_begin, L, stream);
+    }
     if (e != hipSuccess) return device_fail(e, "pathlengths");
     return FCAT_OK;
 }

@@ -25,6 +25,11 @@ struct TraceGeom {
     int n[3];
     int nu, nv, n_angles;
     const double *angles;          // device, or null for 2 pi a / A
+    // Brick map of the labels: B x B x B bricks, nb[] per axis, bricks[]
+    // ([nb2][nb1][nb0]) holds the common label of a uniform brick or -1.
+    int B;
+    int nb[3];
+    const int8_t *bricks;
 };
 
 // Spectral tables prepared on the device (in the workspace) from mu, phi,
@@ -56,6 +61,10 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
 hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, const SpecTables &t,
                                      const float *flood, const float *scatter, int a0, int n_ang,
                                      float *Y, float *out, hipStream_t stream);
+
+// Brick map of B x B x B bricks (see TraceGeom::bricks).
+hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int B, int8_t *bricks,
+                               hipStream_t stream);
 
 hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0,
                               int n_ang, float *L, hipStream_t stream);

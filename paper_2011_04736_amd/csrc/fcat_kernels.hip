@@ -8,10 +8,11 @@
 // Ray traversal (Sec. II.F: a projection is the line integral of the
 // attenuation along the ray; Sec. II.C: the phantom holds material labels,
 // so the integral is sum_m mu_m(E) L_m): entry and exit are found in FP64 by
-// the slab method, the ray is re-based at its entry point and the voxels are
-// then walked in FP32 distance from there (incremental form of Siddon's
-// exact method).  Each plane crossing is t0 + k * dt evaluated with one
-// rounding, so the error does not grow with the number of voxels.  Path
+// the slab method, the ray is re-based at its entry point and then walked
+// in FP32 distance from there (incremental form of Siddon's exact method),
+// over bricks of voxels first and over single voxels only inside bricks
+// whose labels differ.  Each plane crossing is t0 + k dt evaluated with one
+// rounding, so the error does not grow with the number of planes.  Path
 // length is charged to a material only when the label changes, with
 // compensated (Kahan) summation, so its error scales with the number of
 // material transitions rather than with the number of voxels.
@@ -34,17 +35,23 @@ __device__ __forceinline__ int xcd_block(int nblk_padded)
     return (b % kXcds) * per + b / kXcds;
 }
 
+// Per-ray constants of the two-level walk.  Distances t are measured in mm
+// from the point where the ray enters the grid.
 struct Ray {
-    float t_end;       // exit distance from the entry point, mm
-    float t0[3];       // distance of the first plane crossing per axis (inf if parallel)
-    float dt[3];       // distance between crossings per axis
-    int lin;           // linear index of the entry voxel
-    int dlin[3];       // linear index step per axis crossing
+    float t_end;        // exit distance
+    float t0[3];        // first voxel-plane crossing per axis (inf if parallel)
+    float dt[3];        // distance between voxel-plane crossings
+    float inv_dt[3];    // 1 / dt (0 if parallel)
+    float tc0[3];       // first brick-plane crossing per axis (inf if parallel)
+    float dtc[3];       // distance between brick-plane crossings
+    int i0[3];          // entry voxel
+    int sgn[3];         // direction of travel per axis: +1, -1, or 0 if parallel
 };
 
-// FP64 set-up of the ray from the source to the centre of pixel (iv, iu).
-__device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double st, int iv, int iu,
-                                          Ray &r)
+// FP64 set-up of the ray from the source to the centre of pixel (iv, iu):
+// entry and exit by the slab method, then everything re-based at the entry
+// point and rounded once to FP32.
+__device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double st, int iv, int iu, Ray &r)
 {
     const double pu = ((double)iu - G.cu) * G.du + G.off_u;
     const double pv = ((double)iv - G.cv) * G.dv + G.off_v;
@@ -72,52 +79,86 @@ __device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double 
     if (!inside || !(amax > amin)) return false;
     const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     r.t_end = (float)((amax - amin) * len);
-    int idx[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const double q = (s[ax] + amin * d[ax] - G.lo[ax]) * G.inv_h[ax];
         // entering through a plane: the voxel beyond it in the direction of travel
         int i = d[ax] < 0.0 ? (int)ceil(q) - 1 : (int)floor(q);
         i = min(max(i, 0), G.n[ax] - 1);
-        idx[ax] = i;
+        r.i0[ax] = i;
         if (d[ax] != 0.0) {
             const int plane = d[ax] > 0.0 ? i + 1 : i;
             const double ap = (G.lo[ax] + plane * G.h[ax] - s[ax]) * inv[ax];
+            const double step = G.h[ax] * len * fabs(inv[ax]);
             r.t0[ax] = (float)fmax((ap - amin) * len, 0.0);
-            r.dt[ax] = (float)(G.h[ax] * len * fabs(inv[ax]));
+            r.dt[ax] = (float)step;
+            r.inv_dt[ax] = (float)(1.0 / step);
+            const int b = i / G.B;
+            const int bplane = (d[ax] > 0.0 ? b + 1 : b) * G.B;
+            const double bp = (G.lo[ax] + bplane * G.h[ax] - s[ax]) * inv[ax];
+            r.tc0[ax] = (float)fmax((bp - amin) * len, 0.0);
+            r.dtc[ax] = (float)(step * G.B);
+            r.sgn[ax] = d[ax] > 0.0 ? 1 : -1;
         } else {
             r.t0[ax] = INFINITY;
             r.dt[ax] = 0.0f;
+            r.inv_dt[ax] = 0.0f;
+            r.tc0[ax] = INFINITY;
+            r.dtc[ax] = 0.0f;
+            r.sgn[ax] = 0;
         }
     }
-    const int nx = G.n[0], nxy = G.n[0] * G.n[1];
-    r.lin = (idx[2] * G.n[1] + idx[1]) * nx + idx[0];
-    r.dlin[0] = d[0] > 0.0 ? 1 : -1;
-    r.dlin[1] = d[1] > 0.0 ? nx : -nx;
-    r.dlin[2] = d[2] > 0.0 ? nxy : -nxy;
     return true;
 }
 
+// Compensated add of x to material m (compare-select over the padded
+// material count, so the register arrays are never indexed dynamically).
+// Labels outside 0..MP-1 match nothing and add nothing.
 template <int MP>
 __device__ __forceinline__ void kahan_add(float (&L)[MP], float (&C)[MP], int m, float x)
 {
+    float l = 0.0f, c = 0.0f;
 #pragma unroll
     for (int k = 0; k < MP; ++k) {
-        if (k == m) {
-            const float y = x - C[k];
-            const float t = L[k] + y;
-            C[k] = (t - L[k]) - y;
-            L[k] = t;
-        }
+        l = (k == m) ? L[k] : l;
+        c = (k == m) ? C[k] : c;
+    }
+    const float y = x - c;
+    const float t = l + y;
+    c = (t - l) - y;
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        L[k] = (k == m) ? t : L[k];
+        C[k] = (k == m) ? c : C[k];
     }
 }
 
-// Voxel walk.  The walk runs two voxels ahead of the label comparison so
-// that each label load has two iterations to arrive.  Loads past the exit
-// (at most a rounding sliver before t_end) are clamped into the volume.
+// Number of crossings of one axis at or before distance T: the k with
+// t0 + (k-1) dt <= T < t0 + k dt, evaluated with the same rounded formula
+// the walk uses, so that a walk resumed at T stays consistent with one that
+// had stepped through every plane.
+__device__ __forceinline__ float crossings_before(float T, float t0, float dt, float inv_dt)
+{
+    if (!(T >= t0)) return 0.0f;
+    float k = floorf((T - t0) * inv_dt) + 1.0f;
+    if (k > 0.0f && fmaf(k - 1.0f, dt, t0) > T) k -= 1.0f;
+    if (fmaf(k, dt, t0) <= T) k += 1.0f;
+    return k;
+}
+
+// Two-level exact walk (Siddon's path lengths, found hierarchically).
+//
+// The grid is tiled into B x B x B bricks; bricks[] holds the label of a
+// brick whose voxels all share one label, or -1.  The coarse walk crosses
+// brick planes; a uniform brick contributes its whole segment to its label
+// in one step, and only inside mixed bricks does the fine walk cross the
+// individual voxel planes.  Crossing k + 1 of an axis lies at t0 + k dt (one
+// rounding from its exact value) for both levels; path length is charged to
+// a material only when the label changes, with compensated summation.
 template <int MP>
-__device__ __forceinline__ void trace(const Ray &r, const int8_t *__restrict__ labels, int nvox,
-                                      int max_iter, float (&L)[MP])
+__device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const TraceGeom &G,
+                                             const int8_t *__restrict__ labels,
+                                             const int8_t *__restrict__ bricks, float (&L)[MP])
 {
     float C[MP];
 #pragma unroll
@@ -125,49 +166,90 @@ __device__ __forceinline__ void trace(const Ray &r, const int8_t *__restrict__ l
         L[m] = 0.0f;
         C[m] = 0.0f;
     }
+    if (!hit) return;
     const float t_end = r.t_end;
-    const float t0x = r.t0[0], t0y = r.t0[1], t0z = r.t0[2];
-    const float dtx = r.dt[0], dty = r.dt[1], dtz = r.dt[2];
-    float kx = 0.0f, ky = 0.0f, kz = 0.0f;
-    float tx = t0x, ty = t0y, tz = t0z;
-    int lin = r.lin;
-    int cur = labels[lin];
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int nbx = G.nb[0], nby = G.nb[1];
+    const int last_vox = nx * ny * nz - 1;
+    const int last_brick = G.nb[0] * G.nb[1] * G.nb[2] - 1;
+    const int vstride[3] = {1, nx, nx * ny};
+    const int bstride[3] = {1, nbx, nbx * nby};
+
+    float kc[3] = {0.0f, 0.0f, 0.0f};
+    float tc[3] = {r.tc0[0], r.tc0[1], r.tc0[2]};
+    const int db[3] = {r.sgn[0] * bstride[0], r.sgn[1] * bstride[1], r.sgn[2] * bstride[2]};
+    const int dv[3] = {r.sgn[0] * vstride[0], r.sgn[1] * vstride[1], r.sgn[2] * vstride[2]};
+    int blin = (r.i0[2] / G.B * nby + r.i0[1] / G.B) * nbx + r.i0[0] / G.B;
+    int bl = bricks[blin];
+    int cur = -1;
     float run = 0.0f;
-
-    auto advance = [&](float &t_new, int &lab_new) {
-        const float t = fminf(tx, fminf(ty, tz));
-        const bool bx = (tx == t);
-        const bool by = !bx && (ty == t);
-        const bool bz = !bx && !by;
-        lin += bx ? r.dlin[0] : (by ? r.dlin[1] : r.dlin[2]);
-        kx += bx ? 1.0f : 0.0f;
-        ky += by ? 1.0f : 0.0f;
-        kz += bz ? 1.0f : 0.0f;
-        tx = fmaf(kx, dtx, t0x);
-        ty = fmaf(ky, dty, t0y);
-        tz = fmaf(kz, dtz, t0z);
-        t_new = t;
-        lab_new = labels[min(max(lin, 0), nvox - 1)];
-    };
-
-    float ta, tb;
-    int la, lb;
-    advance(ta, la);
-    advance(tb, lb);
-    for (int it = 0; it < max_iter; ++it) {
-        if (ta >= t_end) break;
-        float tc;
-        int lc;
-        advance(tc, lc);
-        if (la != cur) {
-            kahan_add<MP>(L, C, cur, ta - run);
-            cur = la;
-            run = ta;
+    float T_in = 0.0f;
+    int budget = G.nb[0] + G.nb[1] + G.nb[2] + 4;
+    bool active = true;
+    while (active) {
+        const float tco = fminf(tc[0], fminf(tc[1], tc[2]));
+        const bool last = !(tco < t_end) || --budget < 0;
+        const float T_out = last ? t_end : tco;
+        if (bl >= 0) {
+            if (bl != cur) {
+                kahan_add<MP>(L, C, cur, T_in - run);
+                cur = bl;
+                run = T_in;
+            }
+        } else {
+            // fine walk over [T_in, T_out): resume the voxel counters at T_in
+            float k[3], t[3];
+            int lin = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                k[a] = r.sgn[a] ? crossings_before(T_in, r.t0[a], r.dt[a], r.inv_dt[a]) : 0.0f;
+                t[a] = r.sgn[a] ? fmaf(k[a], r.dt[a], r.t0[a]) : INFINITY;
+                const int ia = min(max(r.i0[a] + r.sgn[a] * (int)k[a], 0), G.n[a] - 1);
+                lin += ia * vstride[a];
+            }
+            int lab = labels[lin];
+            if (lab != cur) {
+                kahan_add<MP>(L, C, cur, T_in - run);
+                cur = lab;
+                run = T_in;
+            }
+            for (int f = 0; f < 3 * G.B + 3; ++f) {
+                const float tn = fminf(t[0], fminf(t[1], t[2]));
+                if (!(tn < T_out)) break;
+                const bool bx = (t[0] == tn);
+                const bool by = !bx && (t[1] == tn);
+                const bool bz = !bx && !by;
+                lin += (bx ? dv[0] : 0) + (by ? dv[1] : 0) + (bz ? dv[2] : 0);
+                k[0] += bx ? 1.0f : 0.0f;
+                k[1] += by ? 1.0f : 0.0f;
+                k[2] += bz ? 1.0f : 0.0f;
+                t[0] = r.sgn[0] ? fmaf(k[0], r.dt[0], r.t0[0]) : INFINITY;
+                t[1] = r.sgn[1] ? fmaf(k[1], r.dt[1], r.t0[1]) : INFINITY;
+                t[2] = r.sgn[2] ? fmaf(k[2], r.dt[2], r.t0[2]) : INFINITY;
+                lab = labels[min(max(lin, 0), last_vox)];
+                if (lab != cur) {
+                    kahan_add<MP>(L, C, cur, tn - run);
+                    cur = lab;
+                    run = tn;
+                }
+            }
         }
-        ta = tb;
-        la = lb;
-        tb = tc;
-        lb = lc;
+        if (last) {
+            active = false;
+        } else {
+            const bool bx = (tc[0] == tco);
+            const bool by = !bx && (tc[1] == tco);
+            const bool bz = !bx && !by;
+            blin += (bx ? db[0] : 0) + (by ? db[1] : 0) + (bz ? db[2] : 0);
+            kc[0] += bx ? 1.0f : 0.0f;
+            kc[1] += by ? 1.0f : 0.0f;
+            kc[2] += bz ? 1.0f : 0.0f;
+            tc[0] = r.sgn[0] ? fmaf(kc[0], r.dtc[0], r.tc0[0]) : INFINITY;
+            tc[1] = r.sgn[1] ? fmaf(kc[1], r.dtc[1], r.tc0[1]) : INFINITY;
+            tc[2] = r.sgn[2] ? fmaf(kc[2], r.dtc[2], r.tc0[2]) : INFINITY;
+            T_in = tco;
+            bl = bricks[min(max(blin, 0), last_brick)];
+        }
     }
     kahan_add<MP>(L, C, cur, t_end - run);
 }
@@ -216,14 +298,9 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
     double st, ct;
     sincos(angle_of(G, a), &st, &ct);
     float L[MP];
-    Ray r;
+    Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
-    if (hit) {
-        trace<MP>(r, labels, G.n[0] * G.n[1] * G.n[2], G.n[0] + G.n[1] + G.n[2] + 2, L);
-    } else {
-#pragma unroll
-        for (int m = 0; m < MP; ++m) L[m] = 0.0f;
-    }
+    trace_bricks<MP>(r, hit, G, labels, G.bricks, L);
     const bool any_hit = __ballot(hit) != 0;
     if (!valid) return;
 
@@ -261,13 +338,9 @@ __global__ __launch_bounds__(kBlock) void k_pathlengths(TraceGeom G, const int8_
     double st, ct;
     sincos(angle_of(G, a0 + al), &st, &ct);
     float L[MP];
-    Ray r;
-    if (setup_ray(G, ct, st, iv, iu, r)) {
-        trace<MP>(r, labels, G.n[0] * G.n[1] * G.n[2], G.n[0] + G.n[1] + G.n[2] + 2, L);
-    } else {
-#pragma unroll
-        for (int m = 0; m < MP; ++m) L[m] = 0.0f;
-    }
+    Ray r{};
+    const bool hit = setup_ray(G, ct, st, iv, iu, r);
+    trace_bricks<MP>(r, hit, G, labels, G.bricks, L);
     float *dst = Lout + (((int64_t)al * G.nv + iv) * G.nu + iu) * n_mat;
 #pragma unroll
     for (int m = 0; m < MP; ++m)
@@ -462,6 +535,27 @@ __global__ __launch_bounds__(kBlock) void k_psf_generic(const float *__restrict_
     }
 }
 
+// bricks[bz][by][bx] = the label shared by every voxel of the B x B x B brick
+// (clipped at the grid edge), or -1 if they differ or the label is negative.
+__global__ __launch_bounds__(kBlock) void k_build_bricks(const int8_t *__restrict__ labels, int nx, int ny,
+                                                         int nz, int B, int nbx, int nby, int nbz,
+                                                         int8_t *__restrict__ bricks)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= nbx * nby * nbz) return;
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int x0 = bx * B, y0 = by * B, z0 = bz * B;
+    const int x1 = min(x0 + B, nx), y1 = min(y0 + B, ny), z1 = min(z0 + B, nz);
+    const int first = labels[((int64_t)z0 * ny + y0) * nx + x0];
+    bool uniform = first >= 0;
+    for (int z = z0; z < z1 && uniform; ++z)
+        for (int y = y0; y < y1 && uniform; ++y) {
+            const int8_t *row = labels + ((int64_t)z * ny + y) * nx;
+            for (int x = x0; x < x1; ++x) uniform = uniform && row[x] == first;
+        }
+    bricks[b] = uniform ? (int8_t)first : (int8_t)-1;
+}
+
 int padded_blocks(int64_t waves)
 {
     const int64_t nblk = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
@@ -504,6 +598,16 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int B, int8_t *bricks,
+                               hipStream_t stream)
+{
+    const int nbx = (nx + B - 1) / B, nby = (ny + B - 1) / B, nbz = (nz + B - 1) / B;
+    const int nb = nbx * nby * nbz;
+    hipLaunchKernelGGL(k_build_bricks, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, labels, nx,
+                       ny, nz, B, nbx, nby, nbz, bricks);
     return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ def test_workspace_size_query(fc):
     one = lib.fcat_project_workspace_bytes(C.byref(geo), C.byref(ph), C.byref(sp), None, C.byref(ps), 0, 1)
     per_angle = 8 * 64 * 1024 * 4
     assert one - nops == per_angle
-    assert withpsf - nops == 32 * per_angle          # default: 64 MiB of group signal per chunk
+    assert withpsf - nops == 360 * per_angle         # default: up to 1 GiB of group signal per chunk
     assert nops > 200 * 8 * 4 and nops % 256 == 0
     bad = fc._CGeometry(1000.0, 900.0, 16, 4, 1.0, 1.0, 0.0, 0.0, 3, None)
     assert lib.fcat_project_workspace_bytes(C.byref(bad), C.byref(ph), C.byref(sp), None, None, 0, 0) == 0
@@ -113,10 +113,13 @@ def test_project_rejects_bad_descriptors(fc):
 def test_other_entry_points_reject_bad_args(fc):
     lib = fc.load()
     geo, ph, sp, ps = _descs(fc)
-    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 2, 2, 0x1000, None) == 1
-    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 4, 0x1000, None) == 1
-    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 0, 0, 1, 0x1000, None) == 1
-    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 1, None, None) == 1
+    W = 0x10000
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 2, 2, 0x1000, W, 4096, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 4, 0x1000, W, 4096, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 0, 0, 1, 0x1000, W, 4096, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 1, None, W, 4096, None) == 1
+    assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 1, 0x1000, None, 0, None) == 2
+    assert lib.fcat_pathlengths_workspace_bytes(C.byref(ph)) == 256
     assert lib.fcat_spectral(0x1000, -1, C.byref(sp), None, None, None, 0, 0x2000, 0x10000, 1 << 20, None) == 1
     assert lib.fcat_spectral(0x1000, 10, C.byref(sp), None, None, None, 2, 0x2000, 0x10000, 1 << 20, None) == 1
     assert lib.fcat_spectral(0x1000, 10, C.byref(sp), None, None, None, 0, 0x2000, 0, 0, None) == 2

@@ -101,3 +101,28 @@ def test_axis_aligned_and_parallel_rays(fc):
     Lref = oracle.pathlengths(geo, ph, 3, range(4))
     np.testing.assert_allclose(L, Lref, rtol=1e-6, atol=3e-5)
     assert Lref[0, 1, 2, 1] > 5.9                     # central ray runs inside layer z in [0, 1)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_blocky_phantom_brick_walk(fc, seed):
+    """Piecewise-constant blocks of random sizes (most 8^3 bricks uniform, some
+    mixed, partial bricks at the grid edge) with random noise patches: the
+    two-level walk must match the exact path lengths everywhere."""
+    rng = np.random.default_rng(40 + seed)
+    nx, ny, nz = 61, 45, 27                         # not multiples of the brick edge
+    labels = np.zeros((nz, ny, nx), np.int8)
+    for _ in range(25):
+        x0, y0, z0 = rng.integers(0, [nx, ny, nz])
+        sx, sy, sz = rng.integers(3, 20, size=3)
+        labels[z0:z0 + sz, y0:y0 + sy, x0:x0 + sx] = rng.integers(0, 7)
+    for _ in range(6):
+        x0, y0, z0 = rng.integers(0, [nx - 4, ny - 4, nz - 4])
+        labels[z0:z0 + 4, y0:y0 + 4, x0:x0 + 4] = rng.integers(0, 7, size=(4, 4, 4))
+    ph = Phantom(dx=0.5, dy=0.5, dz=0.5, labels=labels, cx=0.3, cy=-0.2, cz=0.1)
+    geo = Geometry(sid=150.0, sdd=250.0, nu=157, nv=61, du=0.35, dv=0.35, n_angles=12)
+    pb = _upload_geo_phantom(fc, geo, ph)
+    L = fc.fcat_pathlengths(pb, 7).cpu().numpy()
+    Lref = oracle.pathlengths(geo, ph, 7, range(12))
+    err = np.abs(L - Lref)
+    print(f"blocky seed {seed}: max |dL| {err.max():.3e}")
+    assert np.all(err <= _tol(Lref))
