@@ -116,15 +116,14 @@ fcat_status check_psf(const fcat_psf_t *p)
     return FCAT_OK;
 }
 
-// Edge of the cubic bricks of the label map used by the two-level walk.
-constexpr int kBrick = 8;
-
-size_t brick_bytes(const fcat_phantom_t *p)
+size_t brick_count(const fcat_phantom_t *p)
 {
-    const size_t nb = (size_t)((p->nx + kBrick - 1) / kBrick) * ((p->ny + kBrick - 1) / kBrick) *
-                      ((p->nz + kBrick - 1) / kBrick);
-    return nb;
+    return (size_t)((p->nx + kBrickEdge - 1) / kBrickEdge) * ((p->ny + kBrickEdge - 1) / kBrickEdge) *
+           ((p->nz + kBrickEdge - 1) / kBrickEdge);
 }
+
+// brick map + brick-major label copy
+size_t brick_bytes(const fcat_phantom_t *p) { return align_up(brick_count(p)) + brick_count(p) * kBrickVox; }
 
 TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 {
@@ -150,18 +149,32 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
     G.nv = g->nv;
     G.n_angles = g->n_angles;
     G.angles = g->angles_rad;
-    G.B = kBrick;
-    for (int ax = 0; ax < 3; ++ax) G.nb[ax] = (n[ax] + kBrick - 1) / kBrick;
+    for (int ax = 0; ax < 3; ++ax) G.nb[ax] = (n[ax] + kBrickEdge - 1) / kBrickEdge;
     G.bricks = nullptr;
+    G.labels_bm = nullptr;
     return G;
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, bricks, Y, fixed;
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, bricks, Y, fixed;
     size_t per_angle;  // bytes of group signal per angle (0 without psf)
 };
 
-Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size_t nbricks = 0)
+// Host part of the split-precision tables: group-aligned tiles of 16 bins.
+void split_host(const SpecTables &t, SplitTables &sp)
+{
+    int T = 0;
+    for (int g = 0; g < t.G; ++g) {
+        sp.gtile[g] = T;
+        T += (t.gstart[g + 1] - t.gstart[g] + 15) / 16;
+    }
+    for (int g = t.G; g <= FCAT_MAX_GROUPS; ++g) sp.gtile[g] = T;
+    sp.T = T;
+    sp.nkb = (3 * t.M + 31) / 32;
+}
+
+Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size_t nbricks = 0,
+              const SplitTables *sp = nullptr)
 {
     Layout L{};
     size_t o = 0;
@@ -175,6 +188,10 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     o += align_up((size_t)t.G * sizeof(float));
     L.Wsg = o;
     o += align_up((size_t)t.G * sizeof(float));
+    L.afrag = o;
+    if (sp) o += align_up((size_t)sp->T * sp->nkb * kWave * 16);
+    L.wtile = o;
+    if (sp) o += align_up((size_t)sp->T * 16 * sizeof(float));
     L.bricks = o;
     o += align_up(nbricks);
     L.Y = o;
@@ -270,6 +287,22 @@ fcat_status prep_tables(const fcat_spectral_t *s, const float *s_bin, SpecTables
 }
 
 
+fcat_status prep_split(const fcat_spectral_t *s, const SpecTables &t, SplitTables &sp, const Layout &L, void *ws,
+                       hipStream_t stream)
+{
+    uint4 *afrag = at<uint4>(ws, L.afrag);
+    float *wtile = at<float>(ws, L.wtile);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        e = launch_prep_split(s->mu, t, sp, afrag, wtile, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "prep_split");
+    sp.afrag = afrag;
+    sp.wtile = wtile;
+    return FCAT_OK;
+}
+
 fcat_status check_pending()
 {
     hipError_t e = hipGetLastError();
@@ -307,12 +340,13 @@ size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_
                                     const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk)
 {
     (void)scatter;
-    (void)mode;
     SpecTables t{};
     if (check_geometry(geometry) || check_phantom(phantom) || check_spectral(spectral, false, t) ||
         check_psf(psf))
         return 0;
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom));
+    SplitTables sp{};
+    split_host(t, sp);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), mode == FCAT_MODE_SPLIT_BF16 ? &sp : nullptr);
     int chunk = angles_per_chunk > 0 ? angles_per_chunk : default_chunk(L, geometry->n_angles);
     if (chunk > geometry->n_angles) chunk = geometry->n_angles;
     return L.fixed + (size_t)chunk * L.per_angle;
@@ -334,29 +368,39 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     if (scatter && !scatter->maps) return fail(FCAT_E_INVALID_ARG, "scatter maps is NULL");
     if (mode != FCAT_MODE_PLAIN && mode != FCAT_MODE_SPLIT_BF16 && mode != FCAT_MODE_SURROGATE)
         return fail(FCAT_E_INVALID_ARG, "unknown mode %d", (int)mode);
-    if (mode != FCAT_MODE_PLAIN) return fail(FCAT_E_UNSUPPORTED, "mode %d is not built yet", (int)mode);
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom));
+    if (mode == FCAT_MODE_SURROGATE) return fail(FCAT_E_UNSUPPORTED, "surrogate mode is not built yet");
+    const bool split = mode == FCAT_MODE_SPLIT_BF16;
+    SplitTables sp{};
+    split_host(t, sp);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), split ? &sp : nullptr);
     const size_t need = L.fixed + L.per_angle;  // at least one angle per chunk
     if ((s = check_workspace(workspace, workspace_bytes, need))) return s;
     if ((s = check_pending())) return s;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
 
     if ((s = prep_tables(spectral, scatter ? scatter->s_bin : nullptr, t, L, workspace, stream))) return s;
+    if (split && (s = prep_split(spectral, t, sp, L, workspace, stream))) return s;
     TraceGeom G = make_geom(geometry, phantom);
     G.bricks = at<int8_t>(workspace, L.bricks);
+    G.labels_bm = G.bricks + align_up(brick_count(phantom));
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
-        hipError_t e0 = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, G.B,
-                                            at<int8_t>(workspace, L.bricks), stream);
+        hipError_t e0 = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz,
+                                            const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm),
+                                            stream);
         if (e0 != hipSuccess) return device_fail(e0, "build_bricks");
     }
     const float *S = scatter ? scatter->maps : nullptr;
     const int A = geometry->n_angles;
     const int64_t plane = (int64_t)geometry->nu * geometry->nv;
     hipError_t e;
+    auto rows = [&](int a0, int n, float *Yc, float *outc) {
+        return split ? launch_project_rows_split(G, phantom->labels, t, sp, spectral->flood, S, a0, n, Yc, outc, stream)
+                     : launch_project_rows(G, phantom->labels, t, spectral->flood, S, a0, n, Yc, outc, stream);
+    };
     if (!psf) {
         StageTimer tm(FCAT_STAGE_TRACE, stream);
-        e = launch_project_rows(G, phantom->labels, t, spectral->flood, S, 0, A, nullptr, out, stream);
+        e = rows(0, A, nullptr, out);
         if (e != hipSuccess) return device_fail(e, "project_rows");
         return FCAT_OK;
     }
@@ -366,7 +410,7 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
         const int n = std::min(chunk, A - a0);
         {
             StageTimer tm(FCAT_STAGE_TRACE, stream);
-            e = launch_project_rows(G, phantom->labels, t, spectral->flood, S, a0, n, Y, nullptr, stream);
+            e = rows(a0, n, Y, nullptr);
         }
         if (e != hipSuccess) return device_fail(e, "project_rows");
         {
@@ -401,12 +445,14 @@ fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom
     if ((s = check_pending())) return s;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     TraceGeom G = make_geom(geometry, phantom);
-    G.bricks = static_cast<int8_t *>(workspace);
+    int8_t *bricks = static_cast<int8_t *>(workspace);
+    int8_t *labels_bm = bricks + align_up(brick_count(phantom));
+    G.bricks = bricks;
+    G.labels_bm = labels_bm;
     hipError_t e;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
-        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, G.B,
-                                static_cast<int8_t *>(workspace), stream);
+        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks, labels_bm, stream);
     }
     if (e != hipSuccess) return device_fail(e, "build_bricks");
     {
@@ -421,7 +467,9 @@ size_t fcat_spectral_workspace_bytes(const fcat_spectral_t *spectral)
 {
     SpecTables t{};
     if (check_spectral(spectral, false, t)) return 0;
-    return layout(t, nullptr, false).fixed;
+    SplitTables sp{};
+    split_host(t, sp);
+    return layout(t, nullptr, false, 0, &sp).fixed;   // enough for either mode
 }
 
 fcat_status fcat_spectral(const float *Lin, int64_t n, const fcat_spectral_t *spectral, const float *i0,
@@ -436,17 +484,20 @@ fcat_status fcat_spectral(const float *Lin, int64_t n, const fcat_spectral_t *sp
     if (n > 0 && (!Lin || !Y)) return fail(FCAT_E_INVALID_ARG, "L and Y must not be NULL");
     if (mode != FCAT_MODE_PLAIN && mode != FCAT_MODE_SPLIT_BF16)
         return fail(FCAT_E_INVALID_ARG, "fcat_spectral takes PLAIN or SPLIT_BF16");
-    Layout L = layout(t, nullptr, false);
+    const bool split = mode == FCAT_MODE_SPLIT_BF16;
+    SplitTables sp{};
+    split_host(t, sp);
+    Layout L = layout(t, nullptr, false, 0, split ? &sp : nullptr);
     if ((s = check_workspace(workspace, workspace_bytes, L.fixed))) return s;
     if (n == 0) return FCAT_OK;
     if ((s = check_pending())) return s;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
-    if (mode == FCAT_MODE_SPLIT_BF16) return fail(FCAT_E_UNSUPPORTED, "split mode is not built yet");
     if ((s = prep_tables(spectral, s_bin, t, L, workspace, stream))) return s;
+    if (split && (s = prep_split(spectral, t, sp, L, workspace, stream))) return s;
     hipError_t e;
     {
         StageTimer tm(FCAT_STAGE_TRACE, stream);
-        e = launch_spectral(Lin, n, t, i0, S, mode == FCAT_MODE_SPLIT_BF16, Y, stream);
+        e = split ? launch_spectral_split(Lin, n, t, sp, i0, S, Y, stream) : launch_spectral(Lin, n, t, i0, S, Y, stream);
     }
     if (e != hipSuccess) return device_fail(e, "spectral");
     return FCAT_OK;

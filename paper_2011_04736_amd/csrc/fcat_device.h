@@ -1,0 +1,304 @@
+// Device functions shared by the gfx950 kernels of the polyenergetic
+// cone-beam projector: ray set-up, the two-level voxel walk and the plain
+// spectral group sum.
+//
+// One lane follows one ray (one detector pixel of one angle); one wavefront
+// covers 64 consecutive detector columns of one row, so its rays are
+// neighbours in space (they share voxel cache lines), have nearly equal
+// lengths (little divergence) and write their results with coalesced stores.
+//
+// Ray traversal (Sec. II.F: a projection is the line integral of the
+// attenuation along the ray; Sec. II.C: the phantom holds material labels,
+// so the integral is sum_m mu_m(E) L_m): entry and exit are found in FP64 by
+// the slab method, the ray is re-based at its entry point and then walked
+// in FP32 distance from there (incremental form of Siddon's exact method),
+// over bricks of voxels first and over single voxels only inside bricks
+// whose labels differ.  Each plane crossing is t0 + k dt evaluated with one
+// rounding, so the error does not grow with the number of planes.  Path
+// length is charged to a material only when the label changes, with
+// compensated (Kahan) summation, so its error scales with the number of
+// material transitions rather than with the number of voxels.
+#pragma once
+
+#include "fcat_internal.h"
+
+#include <cmath>
+
+namespace fcat {
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Hardware hands consecutive workgroups to the 8 XCDs in turn.  Remap so that
+// each XCD (and its L2) works through one contiguous range of rays.  The
+// grid is padded to a multiple of kXcds so the map is a bijection.
+__device__ __forceinline__ int xcd_block(int nblk_padded)
+{
+    const int b = blockIdx.x;
+    const int per = nblk_padded / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+// Per-ray constants of the two-level walk.  Distances t are measured in mm
+// from the point where the ray enters the grid.
+struct Ray {
+    float t_end;        // exit distance
+    float t0[3];        // first voxel-plane crossing per axis (inf if parallel)
+    float dt[3];        // distance between voxel-plane crossings
+    float inv_dt[3];    // 1 / dt (0 if parallel)
+    float tc0[3];       // first brick-plane crossing per axis (inf if parallel)
+    float dtc[3];       // distance between brick-plane crossings
+    int i0[3];          // entry voxel
+    int sgn[3];         // direction of travel per axis: +1, -1, or 0 if parallel
+};
+
+// FP64 set-up of the ray from the source to the centre of pixel (iv, iu):
+// entry and exit by the slab method, then everything re-based at the entry
+// point and rounded once to FP32.
+__device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double st, int iv, int iu, Ray &r)
+{
+    const double pu = ((double)iu - G.cu) * G.du + G.off_u;
+    const double pv = ((double)iv - G.cv) * G.dv + G.off_v;
+    const double s[3] = {G.sid * ct, G.sid * st, 0.0};
+    const double p[3] = {-G.back * ct - pu * st, -G.back * st + pu * ct, pv};
+    double d[3], inv[3];
+    double amin = 0.0, amax = 1.0;
+    bool inside = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        d[ax] = p[ax] - s[ax];
+        const double lo = G.lo[ax];
+        const double hi = G.lo[ax] + G.n[ax] * G.h[ax];
+        if (d[ax] == 0.0) {
+            inv[ax] = 0.0;
+            inside = inside && s[ax] >= lo && s[ax] < hi;
+        } else {
+            inv[ax] = 1.0 / d[ax];
+            const double a0 = (lo - s[ax]) * inv[ax];
+            const double a1 = (hi - s[ax]) * inv[ax];
+            amin = fmax(amin, fmin(a0, a1));
+            amax = fmin(amax, fmax(a0, a1));
+        }
+    }
+    if (!inside || !(amax > amin)) return false;
+    const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    r.t_end = (float)((amax - amin) * len);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double q = (s[ax] + amin * d[ax] - G.lo[ax]) * G.inv_h[ax];
+        // entering through a plane: the voxel beyond it in the direction of travel
+        int i = d[ax] < 0.0 ? (int)ceil(q) - 1 : (int)floor(q);
+        i = min(max(i, 0), G.n[ax] - 1);
+        r.i0[ax] = i;
+        if (d[ax] != 0.0) {
+            const int plane = d[ax] > 0.0 ? i + 1 : i;
+            const double ap = (G.lo[ax] + plane * G.h[ax] - s[ax]) * inv[ax];
+            const double step = G.h[ax] * len * fabs(inv[ax]);
+            r.t0[ax] = (float)fmax((ap - amin) * len, 0.0);
+            r.dt[ax] = (float)step;
+            r.inv_dt[ax] = (float)(1.0 / step);
+            const int b = i / kBrickEdge;
+            const int bplane = (d[ax] > 0.0 ? b + 1 : b) * kBrickEdge;
+            const double bp = (G.lo[ax] + bplane * G.h[ax] - s[ax]) * inv[ax];
+            r.tc0[ax] = (float)fmax((bp - amin) * len, 0.0);
+            r.dtc[ax] = (float)(step * kBrickEdge);
+            r.sgn[ax] = d[ax] > 0.0 ? 1 : -1;
+        } else {
+            r.t0[ax] = INFINITY;
+            r.dt[ax] = 0.0f;
+            r.inv_dt[ax] = 0.0f;
+            r.tc0[ax] = INFINITY;
+            r.dtc[ax] = 0.0f;
+            r.sgn[ax] = 0;
+        }
+    }
+    return true;
+}
+
+// Compensated add of x to material m (compare-select over the padded
+// material count, so the register arrays are never indexed dynamically).
+// Labels outside 0..MP-1 match nothing and add nothing.
+template <int MP>
+__device__ __forceinline__ void kahan_add(float (&L)[MP], float (&C)[MP], int m, float x)
+{
+    float l = 0.0f, c = 0.0f;
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        l = (k == m) ? L[k] : l;
+        c = (k == m) ? C[k] : c;
+    }
+    const float y = x - c;
+    const float t = l + y;
+    c = (t - l) - y;
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        L[k] = (k == m) ? t : L[k];
+        C[k] = (k == m) ? c : C[k];
+    }
+}
+
+// Number of crossings of one axis at or before distance T: the k with
+// t0 + (k-1) dt <= T < t0 + k dt, evaluated with the same rounded formula
+// the walk uses, so that a walk resumed at T stays consistent with one that
+// had stepped through every plane.
+__device__ __forceinline__ float crossings_before(float T, float t0, float dt, float inv_dt)
+{
+    if (!(T >= t0)) return 0.0f;
+    float k = floorf((T - t0) * inv_dt) + 1.0f;
+    if (k > 0.0f && fmaf(k - 1.0f, dt, t0) > T) k -= 1.0f;
+    if (fmaf(k, dt, t0) <= T) k += 1.0f;
+    return k;
+}
+
+// Two-level exact walk (Siddon's path lengths, found hierarchically).
+//
+// The grid is tiled into B x B x B bricks; bricks[] holds the label of a
+// brick whose voxels all share one label, or -1.  The coarse walk crosses
+// brick planes; a uniform brick contributes its whole segment to its label
+// in one step, and only inside mixed bricks does the fine walk cross the
+// individual voxel planes.  Crossing k + 1 of an axis lies at t0 + k dt (one
+// rounding from its exact value) for both levels; path length is charged to
+// a material only when the label changes, with compensated summation.
+template <int MP>
+__device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const TraceGeom &G,
+                                             const int8_t *__restrict__ labels_bm,
+                                             const int8_t *__restrict__ bricks, float (&L)[MP])
+{
+    float C[MP];
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        L[m] = 0.0f;
+        C[m] = 0.0f;
+    }
+    if (!hit) return;
+    const float t_end = r.t_end;
+    const int nbx = G.nb[0], nby = G.nb[1];
+    const int last_brick = G.nb[0] * G.nb[1] * G.nb[2] - 1;
+    const int lstride[3] = {1, kBrickEdge, kBrickEdge * kBrickEdge};
+    const int bstride[3] = {1, nbx, nbx * nby};
+
+    float kc[3] = {0.0f, 0.0f, 0.0f};
+    float tc[3] = {r.tc0[0], r.tc0[1], r.tc0[2]};
+    const int db[3] = {r.sgn[0] * bstride[0], r.sgn[1] * bstride[1], r.sgn[2] * bstride[2]};
+    const int dl[3] = {r.sgn[0] * lstride[0], r.sgn[1] * lstride[1], r.sgn[2] * lstride[2]};
+    int bc[3] = {r.i0[0] / kBrickEdge, r.i0[1] / kBrickEdge, r.i0[2] / kBrickEdge};
+    int blin = (bc[2] * nby + bc[1]) * nbx + bc[0];
+    int bl = bricks[blin];
+    int cur = -1;
+    float run = 0.0f;
+    float T_in = 0.0f;
+    int budget = G.nb[0] + G.nb[1] + G.nb[2] + 4;
+    bool active = true;
+    while (active) {
+        const float tco = fminf(tc[0], fminf(tc[1], tc[2]));
+        const bool last = !(tco < t_end) || --budget < 0;
+        const float T_out = last ? t_end : tco;
+        if (bl >= 0) {
+            if (bl != cur) {
+                kahan_add<MP>(L, C, cur, T_in - run);
+                cur = bl;
+                run = T_in;
+            }
+        } else {
+            // fine walk over [T_in, T_out) inside brick `blin`, whose 512
+            // labels are contiguous in the brick-major copy: resume the
+            // voxel counters at T_in, then step plane by plane
+            // The voxel is kept inside the brick: where rounding of the two
+            // levels disagrees about a plane at T_in, the brick decides.
+            float k[3], t[3];
+            int loc = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int b0 = bc[a] * kBrickEdge;
+                int ia = r.i0[a];
+                if (r.sgn[a]) {
+                    const float kk = crossings_before(T_in, r.t0[a], r.dt[a], r.inv_dt[a]);
+                    ia = min(max(r.i0[a] + r.sgn[a] * (int)kk, b0), b0 + kBrickEdge - 1);
+                }
+                k[a] = (float)(r.sgn[a] * (ia - r.i0[a]));
+                t[a] = r.sgn[a] ? fmaf(k[a], r.dt[a], r.t0[a]) : INFINITY;
+                loc += (ia - b0) * lstride[a];
+            }
+            const int8_t *brick = labels_bm + (int64_t)min(max(blin, 0), last_brick) * kBrickVox;
+            int lab = brick[loc];
+            // the walk runs one crossing ahead of the label comparison, so
+            // each label load has a step's worth of work to arrive
+            auto advance = [&](float &tn, int &labn) {
+                tn = fminf(t[0], fminf(t[1], t[2]));
+                const bool bx = (t[0] == tn);
+                const bool by = !bx && (t[1] == tn);
+                const bool bz = !bx && !by;
+                loc += (bx ? dl[0] : 0) + (by ? dl[1] : 0) + (bz ? dl[2] : 0);
+                k[0] += bx ? 1.0f : 0.0f;
+                k[1] += by ? 1.0f : 0.0f;
+                k[2] += bz ? 1.0f : 0.0f;
+                t[0] = r.sgn[0] ? fmaf(k[0], r.dt[0], r.t0[0]) : INFINITY;
+                t[1] = r.sgn[1] ? fmaf(k[1], r.dt[1], r.t0[1]) : INFINITY;
+                t[2] = r.sgn[2] ? fmaf(k[2], r.dt[2], r.t0[2]) : INFINITY;
+                labn = brick[min(max(loc, 0), kBrickVox - 1)];
+            };
+            float tn;
+            int labn;
+            advance(tn, labn);
+            if (lab != cur) {
+                kahan_add<MP>(L, C, cur, T_in - run);
+                cur = lab;
+                run = T_in;
+            }
+            for (int f = 0; f < 3 * kBrickEdge + 3; ++f) {
+                if (!(tn < T_out)) break;
+                float tn2;
+                int lab2;
+                advance(tn2, lab2);
+                if (labn != cur) {
+                    kahan_add<MP>(L, C, cur, tn - run);
+                    cur = labn;
+                    run = tn;
+                }
+                tn = tn2;
+                labn = lab2;
+            }
+        }
+        if (last) {
+            active = false;
+        } else {
+            const bool bx = (tc[0] == tco);
+            const bool by = !bx && (tc[1] == tco);
+            const bool bz = !bx && !by;
+            blin += (bx ? db[0] : 0) + (by ? db[1] : 0) + (bz ? db[2] : 0);
+            bc[0] += bx ? r.sgn[0] : 0;
+            bc[1] += by ? r.sgn[1] : 0;
+            bc[2] += bz ? r.sgn[2] : 0;
+            kc[0] += bx ? 1.0f : 0.0f;
+            kc[1] += by ? 1.0f : 0.0f;
+            kc[2] += bz ? 1.0f : 0.0f;
+            tc[0] = r.sgn[0] ? fmaf(kc[0], r.dtc[0], r.tc0[0]) : INFINITY;
+            tc[1] = r.sgn[1] ? fmaf(kc[1], r.dtc[1], r.tc0[1]) : INFINITY;
+            tc[2] = r.sgn[2] ? fmaf(kc[2], r.dtc[2], r.tc0[2]) : INFINITY;
+            T_in = tco;
+            bl = bricks[min(max(blin, 0), last_brick)];
+        }
+    }
+    kahan_add<MP>(L, C, cur, t_end - run);
+}
+
+// sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3)
+template <int MP>
+__device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTables &T, int e0, int e1)
+{
+    float acc = 0.0f;
+    for (int e = e0; e < e1; ++e) {
+        const float *mrow = T.muT + e * MP;
+        float P = 0.0f;
+#pragma unroll
+        for (int m = 0; m < MP; ++m) P = fmaf(mrow[m], L[m], P);
+        acc = fmaf(T.w[e], expf(-P), acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double angle_of(const TraceGeom &G, int a)
+{
+    return G.angles ? G.angles[a] : (2.0 * M_PI) * (double)a / (double)G.n_angles;
+}
+
+}  // namespace fcat

@@ -13,6 +13,8 @@ namespace fcat {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kBrickEdge = 8;      // edge of the cubic label bricks of the two-level walk
+constexpr int kBrickVox = kBrickEdge * kBrickEdge * kBrickEdge;
 
 // Ray geometry of one launch, everything a lane needs to build its ray in
 // FP64.  lo/h/n describe the voxel grid; cu/cv are the detector centre
@@ -25,11 +27,12 @@ struct TraceGeom {
     int n[3];
     int nu, nv, n_angles;
     const double *angles;          // device, or null for 2 pi a / A
-    // Brick map of the labels: B x B x B bricks, nb[] per axis, bricks[]
-    // ([nb2][nb1][nb0]) holds the common label of a uniform brick or -1.
-    int B;
+    // Brick map of the labels: kBrickEdge^3 bricks, nb[] per axis; bricks[]
+    // ([nb2][nb1][nb0]) holds the common label of a uniform brick or -1, and
+    // labels_bm[brick][z][y][x] is the brick-major copy of the labels.
     int nb[3];
     const int8_t *bricks;
+    const int8_t *labels_bm;
 };
 
 // Spectral tables prepared on the device (in the workspace) from mu, phi,
@@ -41,6 +44,20 @@ struct SpecTables {
     const float *Wsg;              // [G]      sum of w * s_bin over the group
     int E, M, G, mp;
     int gstart[FCAT_MAX_GROUPS + 1];
+};
+
+// Tables of the split-precision contraction.  The energy axis is cut into
+// tiles of 16 bins that never straddle two groups (each group is padded to a
+// multiple of 16 bins with zero weight); tiles gtile[g] .. gtile[g+1]-1
+// belong to group g.  afrag holds, per tile and 32-wide k block, the
+// matrix-core A operand (16 energies x 32 k, BF16) in lane order: lane l has
+// row l % 16 and k = 8 (l / 16) .. + 7.  k runs over [mu_hi | mu_lo | mu_hi]
+// (n_mat each, zero-padded).  wtile[t][row] is phi * eta of the tile's bins.
+struct SplitTables {
+    const uint4 *afrag;            // [T][nkb][64]  (8 BF16 per lane)
+    const float *wtile;            // [T][16]
+    int T, nkb;
+    int gtile[FCAT_MAX_GROUPS + 1];
 };
 
 // Launch helpers (fcat_kernels.hip).  All are stream-ordered and return the
@@ -56,21 +73,27 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
                                const float *flood, const float *scatter, int a0, int n_ang,
                                float *Y, float *out, hipStream_t stream);
 
+// Builds SplitTables::afrag and ::wtile from mu and the prepared w.
+hipError_t launch_prep_split(const float *mu, const SpecTables &t, const SplitTables &sp, uint4 *afrag,
+                             float *wtile, hipStream_t stream);
+
 // Same as launch_project_rows with the L . mu contraction on matrix cores
 // (BF16 hi/lo split, FP32 accumulate).
 hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, const SpecTables &t,
-                                     const float *flood, const float *scatter, int a0, int n_ang,
-                                     float *Y, float *out, hipStream_t stream);
+                                     const SplitTables &sp, const float *flood, const float *scatter, int a0,
+                                     int n_ang, float *Y, float *out, hipStream_t stream);
 
-// Brick map of B x B x B bricks (see TraceGeom::bricks).
-hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int B, int8_t *bricks,
+// Brick map and brick-major label copy (see TraceGeom::bricks).
+hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int8_t *bricks, int8_t *labels_bm,
                                hipStream_t stream);
 
 hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0,
                               int n_ang, float *L, hipStream_t stream);
 
 hipError_t launch_spectral(const float *L, int64_t n, const SpecTables &t, const float *i0,
-                           const float *S, bool split, float *Y, hipStream_t stream);
+                           const float *S, float *Y, hipStream_t stream);
+hipError_t launch_spectral_split(const float *L, int64_t n, const SpecTables &t, const SplitTables &sp,
+                                 const float *i0, const float *S, float *Y, hipStream_t stream);
 
 hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const float *kernels,
                       int k, float *out, hipStream_t stream);
