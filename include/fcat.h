@@ -127,7 +127,7 @@ typedef struct fcat_psf_t {
  * Learned replacement of the primary spectral sum (MLP with SiLU).
  * For a ray with path lengths L (n_in = n_mat values):
  *   x_m  = L_m * in_scale[m]
- *   z_g  = sum_m lin[g][m] L_m + MLP(x)_g
+ *   z_g  = sum_m lin[g][m] L_m + out_scale[g] MLP(x)_g
  *   Y_g  = I0 W_g exp(-z_g) + Ws_g S          with W_g = sum_{e in g} phi_e eta_e
  * MLP: h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), MLP(x) = W3 h2 + b3, with
  * weights rounded to BF16 and FP32 accumulation.  The exact spectral sum is
@@ -137,16 +137,29 @@ typedef struct fcat_psf_t {
  */
 #define FCAT_MLP_HIDDEN 64
 #define FCAT_MLP_CELLS 16
+#define FCAT_MLP_MAX_IO 16
+#define FCAT_MLP_MAX_BATCH 65536
 typedef struct fcat_surrogate_t {
-    int32_t n_in;             /* == n_mat, <= 16 */
-    int32_t n_out;            /* == n_groups, <= 16 */
-    const float *params;      /* DEVICE FP32: W1[64][n_in], b1[64], W2[64][64], b2[64],
-                                 W3[n_out][64], b3[n_out] */
+    int32_t n_in;             /* == n_mat, 1..16 */
+    int32_t n_out;            /* == n_groups, 1..16 */
+    const float *params;      /* DEVICE FP32 [fcat_mlp_param_count]: W1[64][n_in], b1[64],
+                                 W2[64][64], b2[64], W3[n_out][64], b3[n_out] */
     const float *in_scale;    /* DEVICE [n_in] */
-    const float *lin;         /* DEVICE [n_out][n_in] */
-    const uint8_t *cell_ok;   /* DEVICE [n_in * 16] */
-    float cell_lo, cell_hi;   /* log10(mm) range of the 16 length bins */
+    const float *out_scale;   /* DEVICE [n_out] */
+    const float *lin;         /* DEVICE [n_out][n_in] (fcat_mlp_linear_term) */
+    const uint8_t *cell_ok;   /* DEVICE [n_in * 16] (fcat_mlp_validate); needed by fcat_project only */
+    float cell_lo, cell_hi;   /* log10(mm) range of the 16 length bins, cell_lo < cell_hi */
+    int32_t *counts;          /* DEVICE [2] or NULL: fcat_project adds the number of rays the
+                                 network handled and the number that fell back to the exact sum */
 } fcat_surrogate_t;
+
+/* Training state of the surrogate (Adam, Kingma & Ba 2015). */
+typedef struct fcat_mlp_train_t {
+    float *params;            /* DEVICE FP32 [P], updated in place */
+    float *adam_m, *adam_v;   /* DEVICE FP32 [P], zero before the first step */
+    int32_t step;             /* Adam steps taken so far; each update increments it */
+    float lr, beta1, beta2, eps;
+} fcat_mlp_train_t;
 
 /* ---------------------------------------------------------------- status */
 
@@ -173,7 +186,8 @@ size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_
  * Full projector: out[a][v][u] (DEVICE float [n_angles][nv][nu]) for every
  * angle and pixel.  scatter NULL turns the scatter term off; psf NULL turns
  * the optical spread off (out = sum_g Y_g).  surrogate is required for
- * FCAT_MODE_SURROGATE and ignored otherwise.
+ * FCAT_MODE_SURROGATE and ignored otherwise; in that mode the path lengths
+ * of each angle chunk pass through the workspace.
  */
 fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
                          const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
@@ -222,6 +236,75 @@ fcat_status fcat_psf(const float *Y, int32_t n_ang, int32_t n_groups, int32_t nv
 fcat_status fcat_check_inputs(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
                               const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
                               const fcat_psf_t *psf, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* ------------------------------------------------------------ surrogate */
+/*
+ * The learned form of the primary spectral sum (see fcat_surrogate_t).  The
+ * paper trains no network; it names simulated data for machine learning as
+ * a use of the simulator (Sec. IV.B).  Training data are (L, Yprim) pairs of
+ * rays produced by fcat_pathlengths and fcat_spectral (no scatter, I0 = 1).
+ * Every product runs on the matrix cores with BF16 operands and FP32
+ * accumulation; the FP32 parameters are the master copy.
+ */
+
+/* Number of FP32 parameters of an n_in -> 64 -> 64 -> n_out network. */
+int32_t fcat_mlp_param_count(int32_t n_in, int32_t n_out);
+
+/* Workspace needed by the fcat_mlp_* calls for up to `batch` samples per step. */
+size_t fcat_mlp_workspace_bytes(const fcat_spectral_t *spectral, int64_t batch);
+
+/* lin[g][m] = sum_{e in g} phi_e eta_e mu[m][e] / sum_{e in g} phi_e eta_e (DEVICE [G][M]). */
+fcat_status fcat_mlp_linear_term(const fcat_spectral_t *spectral, float *lin, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/* Network prediction of Yprim[g][r] (DEVICE [G][n]) for L (DEVICE [n][n_in]), no fallback. */
+fcat_status fcat_mlp_forward(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral,
+                             const float *L, int64_t n, float *Yprim, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/*
+ * Gradient grad (DEVICE [P]) and value loss (DEVICE [1]) of the weighted
+ * mean squared error, over n <= FCAT_MLP_MAX_BATCH samples and the n_out
+ * groups, between out_scale[g] MLP(x)_g and the residual target
+ * r_g = -ln(Yprim_g / W_g) - sum_m lin[g][m] L_m, each term weighted by
+ * min(1, Yprim_g / (1e-6 sum_g Yprim_g))^2 (groups carrying a negligible
+ * share of the ray's signal count little, as in fcat_mlp_validate).
+ */
+fcat_status fcat_mlp_gradients(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral,
+                               const float *L, const float *Yprim, int64_t n, float *grad, float *loss,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * One Adam step of `train` on samples order[base .. base+count) (order:
+ * DEVICE int32 [..] indices into L [n][n_in] and Yprim [G][n]; NULL means
+ * base .. base+count).  count <= FCAT_MLP_MAX_BATCH.  loss (DEVICE [1] or
+ * NULL) receives the batch loss before the update.  surrogate supplies
+ * in_scale and lin; its params are ignored (train->params is used).
+ */
+fcat_status fcat_mlp_train_step(fcat_mlp_train_t *train, const fcat_surrogate_t *surrogate,
+                                const fcat_spectral_t *spectral, const float *L, const float *Yprim, int64_t n,
+                                const int32_t *order, int64_t base, int32_t count, float *loss,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* One epoch of fcat_mlp_train_step over order[0 .. n) in batches; batch_loss DEVICE [ceil(n/batch)] or NULL. */
+fcat_status fcat_mlp_train_epoch(fcat_mlp_train_t *train, const fcat_surrogate_t *surrogate,
+                                 const fcat_spectral_t *spectral, const float *L, const float *Yprim, int64_t n,
+                                 const int32_t *order, int32_t batch, float *batch_loss, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/*
+ * Held-out validation: for every ray inside the training range (x_m <= 1 and
+ * log10(sum L) in [cell_lo, cell_hi)), the largest over groups of
+ * |predicted - exact| / max(exact, 1e-6 sum_g exact) is taken into its cell
+ * (dominant material x 16 log-length bins).  cell_err (DEVICE float
+ * [n_in*16] or NULL) gets the maximum per cell (inf where no ray fell),
+ * cell_ok (DEVICE uint8 [n_in*16]) gets 1 where the cell holds at least
+ * min_count rays and its maximum is <= threshold.
+ */
+fcat_status fcat_mlp_validate(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral,
+                              const float *L, const float *Yprim, int64_t n, float threshold, int32_t min_count,
+                              float *cell_err, uint8_t *cell_ok, void *workspace, size_t workspace_bytes,
                               void *stream);
 
 /* ---------------------------------------------------------- kernel timing */

@@ -28,6 +28,8 @@ __all__ = [
     "fcat_version", "fcat_status_string", "fcat_last_error", "fcat_project_workspace_bytes",
     "fcat_project", "fcat_pathlengths_workspace_bytes", "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_psf",
     "fcat_check_inputs", "fcat_timing_enable", "fcat_timing_read", "STAGES", "lib_path", "load",
+    "Surrogate", "MlpTrain", "fcat_mlp_param_count", "fcat_mlp_workspace_bytes", "fcat_mlp_linear_term",
+    "fcat_mlp_forward", "fcat_mlp_gradients", "fcat_mlp_train_step", "fcat_mlp_train_epoch", "fcat_mlp_validate",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -76,8 +78,14 @@ class _CPsf(C.Structure):
 
 class _CSurrogate(C.Structure):
     _fields_ = [("n_in", C.c_int32), ("n_out", C.c_int32), ("params", C.c_void_p),
-                ("in_scale", C.c_void_p), ("lin", C.c_void_p), ("cell_ok", C.c_void_p),
-                ("cell_lo", C.c_float), ("cell_hi", C.c_float)]
+                ("in_scale", C.c_void_p), ("out_scale", C.c_void_p), ("lin", C.c_void_p), ("cell_ok", C.c_void_p),
+                ("cell_lo", C.c_float), ("cell_hi", C.c_float), ("counts", C.c_void_p)]
+
+
+class _CTrain(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("adam_m", C.c_void_p), ("adam_v", C.c_void_p),
+                ("step", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
 
 
 def lib_path() -> str:
@@ -120,6 +128,24 @@ def load() -> C.CDLL:
     L.fcat_psf.restype = st
     L.fcat_check_inputs.argtypes = [gp, pp, sp, scp, psp, vp, sz, vp]
     L.fcat_check_inputs.restype = st
+    sup2, trp = C.POINTER(_CSurrogate), C.POINTER(_CTrain)
+    i64 = C.c_int64
+    L.fcat_mlp_param_count.argtypes = [C.c_int32, C.c_int32]
+    L.fcat_mlp_param_count.restype = C.c_int32
+    L.fcat_mlp_workspace_bytes.argtypes = [sp, i64]
+    L.fcat_mlp_workspace_bytes.restype = sz
+    L.fcat_mlp_linear_term.argtypes = [sp, vp, vp, sz, vp]
+    L.fcat_mlp_linear_term.restype = st
+    L.fcat_mlp_forward.argtypes = [sup2, sp, vp, i64, vp, vp, sz, vp]
+    L.fcat_mlp_forward.restype = st
+    L.fcat_mlp_gradients.argtypes = [sup2, sp, vp, vp, i64, vp, vp, vp, sz, vp]
+    L.fcat_mlp_gradients.restype = st
+    L.fcat_mlp_train_step.argtypes = [trp, sup2, sp, vp, vp, i64, vp, i64, C.c_int32, vp, vp, sz, vp]
+    L.fcat_mlp_train_step.restype = st
+    L.fcat_mlp_train_epoch.argtypes = [trp, sup2, sp, vp, vp, i64, vp, C.c_int32, vp, vp, sz, vp]
+    L.fcat_mlp_train_epoch.restype = st
+    L.fcat_mlp_validate.argtypes = [sup2, sp, vp, vp, i64, C.c_float, C.c_int32, vp, vp, vp, sz, vp]
+    L.fcat_mlp_validate.restype = st
     L.fcat_timing_enable.argtypes = [C.c_int]
     L.fcat_timing_enable.restype = st
     L.fcat_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int]
@@ -230,6 +256,41 @@ class Psf:
 
     def c(self) -> _CPsf:
         return _CPsf(int(self.kernels.shape[-1]), _ptr(self.kernels))
+
+
+@dataclass
+class Surrogate:
+    """Learned replacement of the primary spectral sum (device tensors)."""
+    params: object                 # float32 [P]
+    in_scale: object               # float32 [n_in]
+    out_scale: object              # float32 [n_out]
+    lin: object                    # float32 [n_out][n_in]
+    cell_ok: object = None         # uint8 [n_in * 16]
+    cell_lo: float = 0.0
+    cell_hi: float = 1.0
+    counts: object = None          # int32 [2] or None
+
+    def c(self) -> _CSurrogate:
+        n_out, n_in = (int(x) for x in self.lin.shape)
+        return _CSurrogate(n_in, n_out, _ptr(self.params), _ptr(self.in_scale), _ptr(self.out_scale), _ptr(self.lin),
+                           _ptr(self.cell_ok), float(self.cell_lo), float(self.cell_hi), _ptr(self.counts))
+
+
+@dataclass
+class MlpTrain:
+    """Adam state of surrogate training (device tensors); step counts updates done."""
+    params: object
+    adam_m: object
+    adam_v: object
+    step: int = 0
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self) -> _CTrain:
+        return _CTrain(_ptr(self.params), _ptr(self.adam_m), _ptr(self.adam_v), int(self.step), float(self.lr),
+                       float(self.beta1), float(self.beta2), float(self.eps))
 
 
 @dataclass
@@ -402,3 +463,105 @@ def fcat_timing_read(reset: bool = True) -> dict:
     cnt = (C.c_int64 * n)()
     _check(load().fcat_timing_read(ms, cnt, n, 1 if reset else 0))
     return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+# ------------------------------------------------------------- surrogate
+
+def fcat_mlp_param_count(n_in: int, n_out: int) -> int:
+    return int(load().fcat_mlp_param_count(int(n_in), int(n_out)))
+
+
+def fcat_mlp_workspace_bytes(spectral: Spectral, batch: int) -> int:
+    cs, _keep = spectral.c()
+    return int(load().fcat_mlp_workspace_bytes(C.byref(cs), int(batch)))
+
+
+def _mlp_ws(spectral: Spectral, batch: int, device, workspace):
+    if workspace is not None:
+        return workspace
+    return _workspace(fcat_mlp_workspace_bytes(spectral, batch), device)
+
+
+def fcat_mlp_linear_term(spectral: Spectral, out=None, workspace=None, stream=None):
+    """lin[g][m] = sum_{e in g} w_e mu[m][e] / W_g."""
+    torch = _require_gpu()
+    M, _E = spectral.mu.shape
+    dev = spectral.mu.device
+    if out is None:
+        out = torch.empty((spectral.n_groups, M), dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = _workspace(fcat_spectral_workspace_bytes(spectral), dev)
+    cs, _keep = spectral.c()
+    _check(load().fcat_mlp_linear_term(C.byref(cs), _ptr(out), _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def fcat_mlp_forward(sur: Surrogate, spectral: Spectral, L, out=None, workspace=None, stream=None):
+    """Network prediction of Yprim[g][r] for L[r][m] (no fallback)."""
+    torch = _require_gpu()
+    n = int(L.shape[0])
+    if out is None:
+        out = torch.empty((spectral.n_groups, n), dtype=torch.float32, device=L.device)
+    ws = _mlp_ws(spectral, 1, L.device, workspace)
+    cs, _keep = spectral.c()
+    cu = sur.c()
+    _check(load().fcat_mlp_forward(C.byref(cu), C.byref(cs), _ptr(L), n, _ptr(out), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return out
+
+
+def fcat_mlp_gradients(sur: Surrogate, spectral: Spectral, L, Yprim, workspace=None, stream=None):
+    """(loss, grad) of the mean squared residual error over all samples."""
+    torch = _require_gpu()
+    n = int(L.shape[0])
+    grad = torch.empty_like(sur.params)
+    loss = torch.empty(1, dtype=torch.float32, device=L.device)
+    ws = _mlp_ws(spectral, n, L.device, workspace)
+    cs, _keep = spectral.c()
+    cu = sur.c()
+    _check(load().fcat_mlp_gradients(C.byref(cu), C.byref(cs), _ptr(L), _ptr(Yprim), n, _ptr(grad), _ptr(loss),
+                                     _ptr(ws), ws.numel(), _stream(stream)))
+    return loss, grad
+
+
+def fcat_mlp_train_step(train: MlpTrain, sur: Surrogate, spectral: Spectral, L, Yprim, order=None, base: int = 0,
+                        count: Optional[int] = None, loss=None, workspace=None, stream=None):
+    """One Adam step on samples order[base:base+count] (or base:base+count)."""
+    n = int(L.shape[0])
+    count = n - base if count is None else count
+    ws = _mlp_ws(spectral, count, L.device, workspace)
+    cs, _keep = spectral.c()
+    cu, ct = sur.c(), train.c()
+    _check(load().fcat_mlp_train_step(C.byref(ct), C.byref(cu), C.byref(cs), _ptr(L), _ptr(Yprim), n, _ptr(order),
+                                      int(base), int(count), _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)))
+    train.step = int(ct.step)
+
+
+def fcat_mlp_train_epoch(train: MlpTrain, sur: Surrogate, spectral: Spectral, L, Yprim, order, batch: int,
+                         batch_loss=None, workspace=None, stream=None):
+    """Minibatch Adam steps over order[0:n]."""
+    n = int(L.shape[0])
+    ws = _mlp_ws(spectral, batch, L.device, workspace)
+    cs, _keep = spectral.c()
+    cu, ct = sur.c(), train.c()
+    _check(load().fcat_mlp_train_epoch(C.byref(ct), C.byref(cu), C.byref(cs), _ptr(L), _ptr(Yprim), n, _ptr(order),
+                                       int(batch), _ptr(batch_loss), _ptr(ws), ws.numel(), _stream(stream)))
+    train.step = int(ct.step)
+
+
+def fcat_mlp_validate(sur: Surrogate, spectral: Spectral, L, Yprim, threshold: float = 1e-3, min_count: int = 8,
+                      workspace=None, stream=None):
+    """(cell_err, cell_ok) of the held-out set; also stores cell_ok in ``sur``."""
+    torch = _require_gpu()
+    n_out, n_in = (int(x) for x in sur.lin.shape)
+    dev = L.device
+    cell_err = torch.empty(n_in * 16, dtype=torch.float32, device=dev)
+    cell_ok = torch.empty(n_in * 16, dtype=torch.uint8, device=dev)
+    ws = _mlp_ws(spectral, 1, dev, workspace)
+    cs, _keep = spectral.c()
+    cu = sur.c()
+    _check(load().fcat_mlp_validate(C.byref(cu), C.byref(cs), _ptr(L), _ptr(Yprim), int(L.shape[0]),
+                                    float(threshold), int(min_count), _ptr(cell_err), _ptr(cell_ok), _ptr(ws),
+                                    ws.numel(), _stream(stream)))
+    sur.cell_ok = cell_ok
+    return cell_err, cell_ok

@@ -156,8 +156,9 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, afrag, wtile, bricks, Y, fixed;
-    size_t per_angle;  // bytes of group signal per angle (0 without psf)
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, frag, bricks, Y, Lbuf, fixed;
+    size_t per_angle;    // bytes of per-angle chunk buffers (group signals, path lengths)
+    size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
 };
 
 // Host part of the split-precision tables: group-aligned tiles of 16 bins.
@@ -174,7 +175,7 @@ void split_host(const SpecTables &t, SplitTables &sp)
 }
 
 Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size_t nbricks = 0,
-              const SplitTables *sp = nullptr)
+              const SplitTables *sp = nullptr, bool surrogate = false)
 {
     Layout L{};
     size_t o = 0;
@@ -192,15 +193,22 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (sp) o += align_up((size_t)sp->T * sp->nkb * kWave * 16);
     L.wtile = o;
     if (sp) o += align_up((size_t)sp->T * 16 * sizeof(float));
+    L.frag = o;
+    if (surrogate) o += align_up((size_t)kMlpFrags * kWave * 16);
     L.bricks = o;
     o += align_up(nbricks);
-    L.Y = o;
     L.fixed = o;
-    L.per_angle = (with_psf && g) ? align_up((size_t)t.G * g->nu * g->nv * sizeof(float)) : 0;
+    L.y_per_angle = (with_psf && g) ? align_up((size_t)t.G * g->nu * g->nv * sizeof(float)) : 0;
+    const size_t l_per_angle = (surrogate && g) ? align_up((size_t)t.M * g->nu * g->nv * sizeof(float)) : 0;
+    L.per_angle = L.y_per_angle + l_per_angle;
+    L.Y = o;       // chunk buffers follow the fixed part: Y [chunk][G][plane], then L [chunk * plane][M]
+    L.Lbuf = o;    // (offset of Lbuf depends on the chunk; see chunk_lbuf)
     return L;
 }
 
 constexpr size_t kDefaultChunkBytes = (size_t)1 << 30;
+
+size_t chunk_lbuf(const Layout &L, int chunk) { return L.Y + (size_t)chunk * L.y_per_angle; }
 
 int default_chunk(const Layout &L, int n_angles)
 {
@@ -303,6 +311,71 @@ fcat_status prep_split(const fcat_spectral_t *s, const SpecTables &t, SplitTable
     return FCAT_OK;
 }
 
+fcat_status check_surrogate(const fcat_surrogate_t *u, const SpecTables &t, bool need_cells)
+{
+    if (!u) return fail(FCAT_E_INVALID_ARG, "surrogate is NULL");
+    if (u->n_in != t.M || u->n_out != t.G)
+        return fail(FCAT_E_INVALID_ARG, "surrogate n_in/n_out must equal n_mat/n_groups");
+    if (u->n_in < 1 || u->n_in > FCAT_MLP_MAX_IO || u->n_out < 1 || u->n_out > FCAT_MLP_MAX_IO)
+        return fail(FCAT_E_INVALID_ARG, "surrogate n_in and n_out must be in 1..%d", FCAT_MLP_MAX_IO);
+    if (!u->params || !u->in_scale || !u->out_scale || !u->lin)
+        return fail(FCAT_E_INVALID_ARG, "surrogate params, in_scale, out_scale and lin must not be NULL");
+    if (need_cells) {
+        if (!u->cell_ok) return fail(FCAT_E_INVALID_ARG, "surrogate cell_ok is NULL");
+        if (!std::isfinite(u->cell_lo) || !std::isfinite(u->cell_hi) || !(u->cell_lo < u->cell_hi))
+            return fail(FCAT_E_INVALID_ARG, "surrogate cell range must be finite with cell_lo < cell_hi");
+    }
+    return FCAT_OK;
+}
+
+fcat_status prep_mlp(const fcat_surrogate_t *u, const float *params, const SpecTables &t, const Layout &L, void *ws,
+                     hipStream_t stream, MlpTables &mt)
+{
+    uint4 *frag = at<uint4>(ws, L.frag);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        e = launch_mlp_prep(params, t.M, t.G, frag, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "mlp_prep");
+    mt.frag = frag;
+    mt.params = params;
+    mt.in_scale = u->in_scale;
+    mt.out_scale = u->out_scale;
+    mt.lin = u->lin;
+    mt.cell_ok = u->cell_ok;
+    mt.cell_lo = u->cell_lo;
+    mt.cell_hi = u->cell_hi;
+    mt.n_in = t.M;
+    mt.n_out = t.G;
+    return FCAT_OK;
+}
+
+// Workspace of the fcat_mlp_* calls: spectral tables, fragments, per-wave
+// gradient partials and loss sums, and the validation cells.
+struct MlpLayout {
+    Layout base;
+    size_t partial, loss_partial, cells, total;
+    int nparts, P;
+};
+
+MlpLayout mlp_layout(const SpecTables &t, int64_t batch)
+{
+    MlpLayout m{};
+    m.base = layout(t, nullptr, false, 0, nullptr, true);
+    m.P = mlp_param_count(t.M, t.G);
+    m.nparts = (int)((std::max<int64_t>(batch, 1) + kWave - 1) / kWave);
+    size_t o = m.base.fixed;
+    m.partial = o;
+    o += align_up((size_t)m.nparts * m.P * sizeof(float));
+    m.loss_partial = o;
+    o += align_up((size_t)m.nparts * sizeof(float));
+    m.cells = o;
+    o += align_up((size_t)2 * FCAT_MLP_MAX_IO * FCAT_MLP_CELLS * sizeof(int));
+    m.total = o;
+    return m;
+}
+
 fcat_status check_pending()
 {
     hipError_t e = hipGetLastError();
@@ -346,7 +419,8 @@ size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_
         return 0;
     SplitTables sp{};
     split_host(t, sp);
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), mode == FCAT_MODE_SPLIT_BF16 ? &sp : nullptr);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), mode == FCAT_MODE_SPLIT_BF16 ? &sp : nullptr,
+                      mode == FCAT_MODE_SURROGATE);
     int chunk = angles_per_chunk > 0 ? angles_per_chunk : default_chunk(L, geometry->n_angles);
     if (chunk > geometry->n_angles) chunk = geometry->n_angles;
     return L.fixed + (size_t)chunk * L.per_angle;
@@ -357,7 +431,6 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
                          const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
                          float *out, void *workspace, size_t workspace_bytes, void *stream_)
 {
-    (void)surrogate;
     g_last_error.clear();
     SpecTables t{};
     fcat_status s;
@@ -368,11 +441,12 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     if (scatter && !scatter->maps) return fail(FCAT_E_INVALID_ARG, "scatter maps is NULL");
     if (mode != FCAT_MODE_PLAIN && mode != FCAT_MODE_SPLIT_BF16 && mode != FCAT_MODE_SURROGATE)
         return fail(FCAT_E_INVALID_ARG, "unknown mode %d", (int)mode);
-    if (mode == FCAT_MODE_SURROGATE) return fail(FCAT_E_UNSUPPORTED, "surrogate mode is not built yet");
     const bool split = mode == FCAT_MODE_SPLIT_BF16;
+    const bool sur = mode == FCAT_MODE_SURROGATE;
+    if (sur && (s = check_surrogate(surrogate, t, true))) return s;
     SplitTables sp{};
     split_host(t, sp);
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), split ? &sp : nullptr);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), split ? &sp : nullptr, sur);
     const size_t need = L.fixed + L.per_angle;  // at least one angle per chunk
     if ((s = check_workspace(workspace, workspace_bytes, need))) return s;
     if ((s = check_pending())) return s;
@@ -380,6 +454,8 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
 
     if ((s = prep_tables(spectral, scatter ? scatter->s_bin : nullptr, t, L, workspace, stream))) return s;
     if (split && (s = prep_split(spectral, t, sp, L, workspace, stream))) return s;
+    MlpTables mt{};
+    if (sur && (s = prep_mlp(surrogate, surrogate->params, t, L, workspace, stream, mt))) return s;
     TraceGeom G = make_geom(geometry, phantom);
     G.bricks = at<int8_t>(workspace, L.bricks);
     G.labels_bm = G.bricks + align_up(brick_count(phantom));
@@ -398,27 +474,51 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
         return split ? launch_project_rows_split(G, phantom->labels, t, sp, spectral->flood, S, a0, n, Yc, outc, stream)
                      : launch_project_rows(G, phantom->labels, t, spectral->flood, S, a0, n, Yc, outc, stream);
     };
-    if (!psf) {
+    if (L.per_angle == 0) {
         StageTimer tm(FCAT_STAGE_TRACE, stream);
         e = rows(0, A, nullptr, out);
         if (e != hipSuccess) return device_fail(e, "project_rows");
         return FCAT_OK;
     }
     const int chunk = (int)std::min<size_t>((size_t)A, (workspace_bytes - L.fixed) / L.per_angle);
-    float *Y = at<float>(workspace, L.Y);
+    float *Y = psf ? at<float>(workspace, L.Y) : nullptr;
+    float *Lbuf = sur ? at<float>(workspace, chunk_lbuf(L, chunk)) : nullptr;
     for (int a0 = 0; a0 < A; a0 += chunk) {
         const int n = std::min(chunk, A - a0);
-        {
+        if (sur) {
+            {
+                StageTimer tm(FCAT_STAGE_TRACE, stream);
+                e = launch_pathlengths(G, phantom->labels, t.M, a0, n, Lbuf, stream);
+            }
+            if (e != hipSuccess) return device_fail(e, "pathlengths");
+            SurrogateIO io{};
+            io.L = Lbuf;
+            io.n = (int64_t)n * plane;
+            io.plane = plane;
+            io.flood = spectral->flood;
+            io.scatter = S ? S + a0 * plane : nullptr;
+            io.Y = Y;
+            io.out = psf ? nullptr : out + a0 * plane;
+            io.counts = surrogate->counts;
+            io.force_mlp = 0;
+            {
+                StageTimer tm(FCAT_STAGE_MLP, stream);
+                e = launch_mlp_spectral(t, mt, io, stream);
+            }
+            if (e != hipSuccess) return device_fail(e, "mlp_spectral");
+        } else {
             StageTimer tm(FCAT_STAGE_TRACE, stream);
-            e = rows(a0, n, Y, nullptr);
+            e = rows(a0, n, Y, psf ? nullptr : out);
+            if (e != hipSuccess) return device_fail(e, "project_rows");
         }
-        if (e != hipSuccess) return device_fail(e, "project_rows");
-        {
-            StageTimer tm(FCAT_STAGE_PSF, stream);
-            e = launch_psf(Y, n, t.G, geometry->nv, geometry->nu, psf->kernels, psf->k, out + a0 * plane,
-                           stream);
+        if (psf) {
+            {
+                StageTimer tm(FCAT_STAGE_PSF, stream);
+                e = launch_psf(Y, n, t.G, geometry->nv, geometry->nu, psf->kernels, psf->k, out + a0 * plane,
+                               stream);
+            }
+            if (e != hipSuccess) return device_fail(e, "psf");
         }
-        if (e != hipSuccess) return device_fail(e, "psf");
     }
     return FCAT_OK;
 }
@@ -565,6 +665,220 @@ fcat_status fcat_check_inputs(const fcat_geometry_t *geometry, const fcat_phanto
     if (e != hipSuccess) return device_fail(e, "check readback");
     if (host[0]) return fail(FCAT_E_LABEL_RANGE, "a phantom label is outside 0..%d", t.M - 1);
     if (host[1]) return fail(FCAT_E_NONFINITE, "a float table holds NaN or Inf");
+    return FCAT_OK;
+}
+
+int32_t fcat_mlp_param_count(int32_t n_in, int32_t n_out)
+{
+    if (n_in < 1 || n_in > FCAT_MLP_MAX_IO || n_out < 1 || n_out > FCAT_MLP_MAX_IO) return 0;
+    return mlp_param_count(n_in, n_out);
+}
+
+size_t fcat_mlp_workspace_bytes(const fcat_spectral_t *spectral, int64_t batch)
+{
+    SpecTables t{};
+    if (check_spectral(spectral, false, t) || batch < 1 || batch > FCAT_MLP_MAX_BATCH) return 0;
+    return mlp_layout(t, batch).total;
+}
+
+fcat_status fcat_mlp_linear_term(const fcat_spectral_t *spectral, float *lin, void *workspace, size_t workspace_bytes,
+                                 void *stream_)
+{
+    g_last_error.clear();
+    SpecTables t{};
+    fcat_status s;
+    if ((s = check_spectral(spectral, true, t))) return s;
+    if (!lin) return fail(FCAT_E_INVALID_ARG, "lin is NULL");
+    Layout L = layout(t, nullptr, false);
+    if ((s = check_workspace(workspace, workspace_bytes, L.fixed))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((s = prep_tables(spectral, nullptr, t, L, workspace, stream))) return s;
+    hipError_t e = launch_mlp_linear(spectral->mu, t, lin, stream);
+    if (e != hipSuccess) return device_fail(e, "mlp_linear");
+    return FCAT_OK;
+}
+
+// Shared set-up of the fcat_mlp_* calls.
+static fcat_status mlp_begin(const fcat_surrogate_t *u, const fcat_spectral_t *spectral, const float *params,
+                             int64_t batch, void *workspace, size_t workspace_bytes, hipStream_t stream, SpecTables &t,
+                             MlpLayout &ml, MlpTables &mt)
+{
+    fcat_status s;
+    if ((s = check_spectral(spectral, true, t))) return s;
+    if ((s = check_surrogate(u, t, false))) return s;
+    if (!params) return fail(FCAT_E_INVALID_ARG, "params is NULL");
+    ml = mlp_layout(t, batch);
+    if ((s = check_workspace(workspace, workspace_bytes, ml.total))) return s;
+    if ((s = check_pending())) return s;
+    if ((s = prep_tables(spectral, nullptr, t, ml.base, workspace, stream))) return s;
+    return prep_mlp(u, params, t, ml.base, workspace, stream, mt);
+}
+
+fcat_status fcat_mlp_forward(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral, const float *L,
+                             int64_t n, float *Yprim, void *workspace, size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    if (n < 0) return fail(FCAT_E_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!L || !Yprim)) return fail(FCAT_E_INVALID_ARG, "L and Yprim must not be NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SpecTables t{};
+    MlpLayout ml{};
+    MlpTables mt{};
+    fcat_status s;
+    if ((s = mlp_begin(surrogate, spectral, surrogate ? surrogate->params : nullptr, 1, workspace, workspace_bytes,
+                       stream, t, ml, mt)))
+        return s;
+    if (n == 0) return FCAT_OK;
+    SurrogateIO io{};
+    io.L = L;
+    io.n = n;
+    io.plane = n;
+    io.Y = Yprim;
+    io.force_mlp = 1;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_MLP, stream);
+        e = launch_mlp_spectral(t, mt, io, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "mlp_forward");
+    return FCAT_OK;
+}
+
+fcat_status fcat_mlp_gradients(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral, const float *L,
+                               const float *Yprim, int64_t n, float *grad, float *loss, void *workspace,
+                               size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    if (n < 1 || n > FCAT_MLP_MAX_BATCH) return fail(FCAT_E_INVALID_ARG, "n must be in 1..%d", FCAT_MLP_MAX_BATCH);
+    if (!L || !Yprim || !grad) return fail(FCAT_E_INVALID_ARG, "L, Yprim and grad must not be NULL");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SpecTables t{};
+    MlpLayout ml{};
+    MlpTables mt{};
+    fcat_status s;
+    if ((s = mlp_begin(surrogate, spectral, surrogate ? surrogate->params : nullptr, n, workspace, workspace_bytes,
+                       stream, t, ml, mt)))
+        return s;
+    float *partial = at<float>(workspace, ml.partial);
+    float *lp = at<float>(workspace, ml.loss_partial);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_MLP, stream);
+        e = launch_mlp_grad(t, mt, L, Yprim, n, nullptr, 0, (int)n, partial, lp, stream);
+        if (e == hipSuccess)
+            e = launch_mlp_reduce_adam(partial, (int)((n + kWave - 1) / kWave), ml.P, grad, nullptr, nullptr, nullptr,
+                                       0, 0.f, 0.f, 0.f, 0.f, lp, 1.0f / ((float)n * (float)t.G), loss, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "mlp_gradients");
+    return FCAT_OK;
+}
+
+static fcat_status check_train(const fcat_mlp_train_t *tr)
+{
+    if (!tr) return fail(FCAT_E_INVALID_ARG, "train is NULL");
+    if (!tr->params || !tr->adam_m || !tr->adam_v)
+        return fail(FCAT_E_INVALID_ARG, "train params and Adam moments must not be NULL");
+    if (tr->step < 0) return fail(FCAT_E_INVALID_ARG, "train step must be >= 0");
+    if (!(tr->lr > 0.0f) || !(tr->beta1 >= 0.0f && tr->beta1 < 1.0f) || !(tr->beta2 >= 0.0f && tr->beta2 < 1.0f) ||
+        !(tr->eps >= 0.0f))
+        return fail(FCAT_E_INVALID_ARG, "Adam hyper-parameters out of range");
+    return FCAT_OK;
+}
+
+static hipError_t train_one(fcat_mlp_train_t *train, const SpecTables &t, MlpTables &mt, const MlpLayout &ml,
+                            void *workspace, const float *L, const float *Yprim, int64_t n, const int32_t *order,
+                            int64_t base, int count, float *loss, hipStream_t stream)
+{
+    float *partial = at<float>(workspace, ml.partial);
+    float *lp = at<float>(workspace, ml.loss_partial);
+    StageTimer tm(FCAT_STAGE_MLP, stream);
+    hipError_t e = launch_mlp_prep(train->params, t.M, t.G, const_cast<uint4 *>(mt.frag), stream);
+    if (e == hipSuccess) e = launch_mlp_grad(t, mt, L, Yprim, n, order, base, count, partial, lp, stream);
+    if (e == hipSuccess)
+        e = launch_mlp_reduce_adam(partial, (count + kWave - 1) / kWave, ml.P, nullptr, train->params, train->adam_m,
+                                   train->adam_v, train->step + 1, train->lr, train->beta1, train->beta2, train->eps,
+                                   lp, 1.0f / ((float)count * (float)t.G), loss, stream);
+    if (e == hipSuccess) train->step += 1;
+    return e;
+}
+
+fcat_status fcat_mlp_train_step(fcat_mlp_train_t *train, const fcat_surrogate_t *surrogate,
+                                const fcat_spectral_t *spectral, const float *L, const float *Yprim, int64_t n,
+                                const int32_t *order, int64_t base, int32_t count, float *loss, void *workspace,
+                                size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    fcat_status s;
+    if ((s = check_train(train))) return s;
+    if (count < 1 || count > FCAT_MLP_MAX_BATCH) return fail(FCAT_E_INVALID_ARG, "count must be in 1..%d", FCAT_MLP_MAX_BATCH);
+    if (!L || !Yprim || n < 1 || base < 0 || (!order && base + count > n))
+        return fail(FCAT_E_INVALID_ARG, "bad sample range");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SpecTables t{};
+    MlpLayout ml{};
+    MlpTables mt{};
+    if ((s = mlp_begin(surrogate, spectral, train->params, count, workspace, workspace_bytes, stream, t, ml, mt)))
+        return s;
+    hipError_t e = train_one(train, t, mt, ml, workspace, L, Yprim, n, order, base, count, loss, stream);
+    if (e != hipSuccess) return device_fail(e, "mlp_train_step");
+    return FCAT_OK;
+}
+
+fcat_status fcat_mlp_train_epoch(fcat_mlp_train_t *train, const fcat_surrogate_t *surrogate,
+                                 const fcat_spectral_t *spectral, const float *L, const float *Yprim, int64_t n,
+                                 const int32_t *order, int32_t batch, float *batch_loss, void *workspace,
+                                 size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    fcat_status s;
+    if ((s = check_train(train))) return s;
+    if (batch < 1 || batch > FCAT_MLP_MAX_BATCH) return fail(FCAT_E_INVALID_ARG, "batch must be in 1..%d", FCAT_MLP_MAX_BATCH);
+    if (!L || !Yprim || n < 1) return fail(FCAT_E_INVALID_ARG, "bad sample range");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SpecTables t{};
+    MlpLayout ml{};
+    MlpTables mt{};
+    if ((s = mlp_begin(surrogate, spectral, train->params, batch, workspace, workspace_bytes, stream, t, ml, mt)))
+        return s;
+    int64_t b = 0;
+    for (int64_t base = 0; base < n; base += batch, ++b) {
+        const int count = (int)std::min<int64_t>(batch, n - base);
+        hipError_t e = train_one(train, t, mt, ml, workspace, L, Yprim, n, order, base, count,
+                                 batch_loss ? batch_loss + b : nullptr, stream);
+        if (e != hipSuccess) return device_fail(e, "mlp_train_epoch");
+    }
+    return FCAT_OK;
+}
+
+fcat_status fcat_mlp_validate(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral, const float *L,
+                              const float *Yprim, int64_t n, float threshold, int32_t min_count, float *cell_err,
+                              uint8_t *cell_ok, void *workspace, size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    if (n < 1 || !L || !Yprim || !cell_ok) return fail(FCAT_E_INVALID_ARG, "L, Yprim, cell_ok and n >= 1 are needed");
+    if (!(threshold >= 0.0f) || min_count < 1) return fail(FCAT_E_INVALID_ARG, "threshold >= 0 and min_count >= 1");
+    if (!surrogate || !std::isfinite(surrogate->cell_lo) || !std::isfinite(surrogate->cell_hi) ||
+        !(surrogate->cell_lo < surrogate->cell_hi))
+        return fail(FCAT_E_INVALID_ARG, "surrogate cell range must be finite with cell_lo < cell_hi");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SpecTables t{};
+    MlpLayout ml{};
+    MlpTables mt{};
+    fcat_status s;
+    if ((s = mlp_begin(surrogate, spectral, surrogate->params, 1, workspace, workspace_bytes, stream, t, ml, mt)))
+        return s;
+    const int ncell = t.M * FCAT_MLP_CELLS;
+    unsigned *bits = at<unsigned>(workspace, ml.cells);
+    int *count = reinterpret_cast<int *>(bits + FCAT_MLP_MAX_IO * FCAT_MLP_CELLS);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_MLP, stream);
+        e = launch_zero_ints(reinterpret_cast<int *>(bits), 2 * FCAT_MLP_MAX_IO * FCAT_MLP_CELLS, stream);
+        if (e == hipSuccess) e = launch_mlp_validate(t, mt, L, Yprim, n, bits, count, stream);
+        if (e == hipSuccess) e = launch_mlp_cells(bits, count, ncell, threshold, min_count, cell_err, cell_ok, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "mlp_validate");
     return FCAT_OK;
 }
 

@@ -60,6 +60,48 @@ struct SplitTables {
     int gtile[FCAT_MAX_GROUPS + 1];
 };
 
+// Surrogate network tables (fcat_mlp.hip).  frag holds the BF16 B-operand
+// fragments of every weight view the forward and backward passes use.
+constexpr int kMlpFrags = 26;
+struct MlpTables {
+    const uint4 *frag;             // [kMlpFrags][64]
+    const float *params;           // FP32 master parameters (biases read from here)
+    const float *in_scale;         // [n_in]
+    const float *out_scale;        // [n_out]
+    const float *lin;              // [n_out][n_in]
+    const uint8_t *cell_ok;        // [n_in * FCAT_MLP_CELLS]
+    float cell_lo, cell_hi;
+    int n_in, n_out;
+};
+
+// Inputs and outputs of the surrogate spectral stage over n rays of L.
+// Ray r belongs to angle r / plane, pixel r % plane.
+struct SurrogateIO {
+    const float *L;                // [n][n_mat]
+    int64_t n, plane;
+    const float *flood;            // [plane] or null
+    const float *scatter;          // [n] or null
+    float *Y;                      // [n / plane][G][plane] or null
+    float *out;                    // [n] (sum over groups) or null
+    int *counts;                   // [2]: rays by the network, rays by the exact sum; or null
+    int force_mlp;                 // 1: no fallback (validation and training checks)
+};
+
+int mlp_param_count(int n_in, int n_out);
+hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag, hipStream_t stream);
+hipError_t launch_mlp_linear(const float *mu, const SpecTables &t, float *lin, hipStream_t stream);
+hipError_t launch_mlp_spectral(const SpecTables &t, const MlpTables &m, const SurrogateIO &io, hipStream_t stream);
+hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n_all,
+                           const int32_t *order, int64_t base, int count, float *partial, float *loss_partial,
+                           hipStream_t stream);
+hipError_t launch_mlp_reduce_adam(const float *partial, int nparts, int P, float *grad, float *params, float *m,
+                                  float *v, int step, float lr, float beta1, float beta2, float eps,
+                                  const float *loss_partial, float loss_scale, float *loss_out, hipStream_t stream);
+hipError_t launch_mlp_validate(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n,
+                               unsigned *err_bits, int *count, hipStream_t stream);
+hipError_t launch_mlp_cells(const unsigned *err_bits, const int *count, int ncell, float threshold, int min_count,
+                            float *cell_err, uint8_t *cell_ok, hipStream_t stream);
+
 // Launch helpers (fcat_kernels.hip).  All are stream-ordered and return the
 // hipError_t of the launch.
 hipError_t launch_prep_tables(const float *mu, const float *phi, const float *eta,

@@ -23,17 +23,6 @@
 namespace fcat {
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint32_t bf16_rne(float x)
-{
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
-__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
-
 template <int NKB>
 constexpr int split_row_stride() { return NKB * 32 + 8; }   // BF16 units; +16 bytes spreads the banks
 

@@ -1,0 +1,152 @@
+"""Training and set-up of the learned surrogate (host orchestration).
+
+Every computation runs in libfcat.so: path lengths of the training rays
+(``fcat_pathlengths``), their exact primary group signals (``fcat_spectral``),
+the linear term (``fcat_mlp_linear_term``), forward/backward/Adam
+(``fcat_mlp_train_epoch``) and the held-out validation that decides where
+the network may replace the exact sum (``fcat_mlp_validate``).  This module
+only draws the seeded samples and initial weights (inputs to those kernels),
+slices tensors and loops over epochs.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import (MlpTrain, Problem, Surrogate, fcat_mlp_linear_term, fcat_mlp_param_count, fcat_mlp_train_epoch,
+               fcat_mlp_validate, fcat_pathlengths, fcat_spectral)
+
+HIDDEN = 64
+
+
+def init_params(n_in: int, n_out: int, seed: int) -> np.ndarray:
+    """Seeded initial weights: uniform(+-sqrt(6 / (fan_in + fan_out))), zero biases, small last layer."""
+    rng = np.random.default_rng(seed)
+
+    def glorot(fan_out, fan_in, gain=1.0):
+        lim = gain * math.sqrt(6.0 / (fan_in + fan_out))
+        return rng.uniform(-lim, lim, size=(fan_out, fan_in))
+    parts = [glorot(HIDDEN, n_in), np.zeros(HIDDEN), glorot(HIDDEN, HIDDEN), np.zeros(HIDDEN),
+             glorot(n_out, HIDDEN, 0.1), np.zeros(n_out)]
+    p = np.concatenate([a.ravel() for a in parts]).astype(np.float32)
+    assert p.size == fcat_mlp_param_count(n_in, n_out)
+    return p
+
+
+def sample_rays(pb: Problem, n_mat: int, n_samples: int, angles, seed: int, chunk: int = 4):
+    """Path lengths L[n][n_mat] (device) of n_samples rays drawn without replacement
+    from the rays of the given angles that cross the phantom."""
+    import torch
+    rng = np.random.default_rng(seed)
+    angles = np.asarray(angles, dtype=np.int64)
+    picked = []
+    per_angle = pb.geometry.nu * pb.geometry.nv
+    # draw the share of each angle chunk in proportion to its hit count
+    chunks = [angles[i:i + chunk] for i in range(0, len(angles), chunk)]
+    want = [n_samples * len(c) // len(angles) for c in chunks]
+    want[-1] += n_samples - sum(want)
+    for c, k in zip(chunks, want):
+        rows = []
+        for a in c:
+            La = fcat_pathlengths(pb, n_mat, int(a), int(a) + 1).reshape(per_angle, n_mat)
+            rows.append(La.cpu().numpy())
+        La = np.concatenate(rows)
+        hit = np.nonzero(La.sum(1) > 0)[0]
+        sel = rng.choice(hit, size=min(k, hit.size), replace=False)
+        picked.append(La[np.sort(sel)])
+    L = np.concatenate(picked)
+    L = L[rng.permutation(L.shape[0])]
+    return torch.as_tensor(L, device=pb.phantom.labels.device)
+
+
+def residual_scale(sp, L, Y, lin) -> np.ndarray:
+    """Per-group output scale: the loss-weighted RMS of the training residuals
+    r_g = -ln(Y_g / W_g) - sum_m lin[g][m] L_m (set-up statistics of the data)."""
+    phi = sp.phi.cpu().numpy().astype(np.float64)
+    eta = sp.eta.cpu().numpy().astype(np.float64)
+    G = int(sp.n_groups)
+    E = phi.size
+    gob = np.asarray(sp.group_of_bin) if sp.group_of_bin is not None else np.arange(E) * G // E
+    W = np.array([(phi * eta)[gob == g].sum() for g in range(G)])
+    Y = np.asarray(Y, np.float64)
+    r = -np.log(np.maximum(Y.T, 1e-300) / W[None, :]) - np.asarray(L, np.float64) @ np.asarray(lin, np.float64).T
+    om = np.minimum(1.0, Y.T / (1e-6 * Y.sum(0)[:, None])) ** 2
+    s = np.sqrt((om * r * r).sum(0) / np.maximum(om.sum(0), 1e-30))
+    return np.maximum(s, 1e-3).astype(np.float32)
+
+
+@dataclass
+class TrainReport:
+    n_train: int
+    n_holdout: int
+    epochs: int
+    batch: int
+    seconds: float
+    epoch_loss: list = field(default_factory=list)
+    cell_err: Optional[np.ndarray] = None
+    cell_ok: Optional[np.ndarray] = None
+    holdout_in_ok_cells: float = 0.0
+
+
+def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.1, epochs: int = 40,
+                    batch: int = 4096, lr: float = 2e-3, lr_final: float = 2e-5, threshold: float = 1e-3,
+                    min_count: int = 16, angles=None, seed: int = 47365, verbose: bool = False):
+    """Train the surrogate on rays of ``pb`` and validate it; returns (Surrogate, TrainReport)."""
+    import torch
+    sp = pb.spectral
+    M, _E = (int(x) for x in sp.mu.shape)
+    G = int(sp.n_groups)
+    dev = pb.phantom.labels.device
+    A = pb.geometry.n_angles
+    if angles is None:
+        angles = np.arange(0, A, max(1, A // 36))
+    L = sample_rays(pb, M, n_samples, angles, seed)
+    Y = fcat_spectral(L, sp)                                   # exact primary group signals
+    n = int(L.shape[0])
+    n_hold = int(round(n * holdout))
+    n_train = n - n_hold
+    Lt, Lh = L[:n_train].contiguous(), L[n_train:].contiguous()
+    Yt, Yh = Y[:, :n_train].contiguous(), Y[:, n_train:].contiguous()
+
+    Ltr = Lt.cpu().numpy()
+    lmax = np.maximum(Ltr.max(0), 1e-6)
+    tot = Ltr.sum(1)
+    cell_lo = float(np.floor(np.log10(tot.min()) * 100) / 100)
+    cell_hi = float(np.ceil(np.log10(tot.max()) * 100) / 100 + 0.01)
+    lin = fcat_mlp_linear_term(sp)
+    out_scale = residual_scale(sp, Ltr, Yt.cpu().numpy(), lin.cpu().numpy())
+    params = torch.as_tensor(init_params(M, G, seed), device=dev)
+    sur = Surrogate(params=params, in_scale=torch.as_tensor((1.0 / lmax).astype(np.float32), device=dev),
+                    out_scale=torch.as_tensor(out_scale, device=dev), lin=lin, cell_ok=None, cell_lo=cell_lo,
+                    cell_hi=cell_hi)
+    train = MlpTrain(params=params, adam_m=torch.zeros_like(params), adam_v=torch.zeros_like(params), lr=lr)
+    nb = (n_train + batch - 1) // batch
+    batch_loss = torch.empty(nb, dtype=torch.float32, device=dev)
+    report = TrainReport(n_train, n_hold, epochs, batch, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        train.lr = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * ep / max(epochs - 1, 1)))
+        g = torch.Generator().manual_seed(seed * 1000 + ep)
+        order = torch.randperm(n_train, generator=g).to(torch.int32).to(dev)
+        fcat_mlp_train_epoch(train, sur, sp, Lt, Yt, order, batch, batch_loss=batch_loss)
+        report.epoch_loss.append(float(batch_loss.mean().item()))
+        if verbose:
+            print(f"epoch {ep}: lr {train.lr:.2e} loss {report.epoch_loss[-1]:.3e}", flush=True)
+    torch.cuda.synchronize()
+    report.seconds = time.perf_counter() - t0
+    cell_err, cell_ok = fcat_mlp_validate(sur, sp, Lh, Yh, threshold=threshold, min_count=min_count)
+    report.cell_err = cell_err.cpu().numpy()
+    report.cell_ok = cell_ok.cpu().numpy()
+    # share of held-out rays that fall in validated cells
+    Lhn = Lh.cpu().numpy()
+    toth = Lhn.sum(1)
+    b = np.floor(16 * (np.log10(toth) - cell_lo) / (cell_hi - cell_lo))
+    inside = (b >= 0) & (b < 16) & np.all(Lhn * (1.0 / lmax) <= 1.0, axis=1)
+    cell = np.argmax(Lhn, axis=1) * 16 + np.clip(b, 0, 15).astype(np.int64)
+    report.holdout_in_ok_cells = float(np.mean(inside & (report.cell_ok[cell] == 1)))
+    return sur, report

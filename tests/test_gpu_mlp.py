@@ -1,0 +1,131 @@
+"""GPU checks of the learned surrogate: kernels against the FP64 network oracle.
+
+Gradients of the training kernels are compared with the oracle that rounds
+to BF16 at the same points (2e-2 relative per parameter block) and with the
+plain FP64 oracle (1e-1); forward predictions and one Adam update likewise.
+A small training run must cut the loss, and the projector in surrogate mode
+(network where validated, exact sum elsewhere) must stay within 1e-3 of the
+exact FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import rel_err
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
+
+
+def _setup(fc, torch, n=1000, seed=0, scale=1.0):
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(3)
+    s = cfg.spectral
+    rng = np.random.default_rng(seed)
+    M, G = s.n_mat, s.n_groups
+    L = np.zeros((n, M), np.float32)
+    for i in range(n):                               # a few materials per ray, realistic lengths
+        k = rng.integers(1, 5)
+        L[i, rng.choice(M, size=k, replace=False)] = rng.uniform(0.5, 60.0, size=k)
+    Y = oracle.spectral(L, s.mu, s.phi, s.eta, s.group_of_bin, G).astype(np.float32)
+    sp = fc.Spectral(_t(torch, s.mu), _t(torch, s.phi), _t(torch, s.eta), G, s.group_of_bin)
+    lin = fc.fcat_mlp_linear_term(sp)
+    in_scale = (1.0 / L.max(0)).astype(np.float32)
+    out_scale = rng.uniform(0.2, 2.0, size=G).astype(np.float32)
+    p = sg.init_params(M, G, seed) * scale
+    p[-G:] = rng.normal(0, 0.05, size=G)
+    sur = fc.Surrogate(params=_t(torch, p), in_scale=_t(torch, in_scale), out_scale=_t(torch, out_scale), lin=lin,
+                       cell_lo=0.0, cell_hi=2.5)
+    return cfg, s, L, Y, sp, sur, p, in_scale, out_scale
+
+
+def _blocks(v, n_in, n_out):
+    return dict(zip(["W1", "b1", "W2", "b2", "W3", "b3"], [np.ravel(a) for a in omlp.unpack(v, n_in, n_out)]))
+
+
+def test_linear_term(fc):
+    import torch
+    cfg, s, L, Y, sp, sur, p, _, _ = _setup(fc, torch, n=64)
+    ref = omlp.linear_term(s.mu, s.phi, s.eta, s.group_of_bin, s.n_groups)
+    assert rel_err(sur.lin.cpu().numpy(), ref).max() <= 1e-6
+
+
+@pytest.mark.parametrize("n", [64, 1000])
+def test_gradients_match_oracle(fc, n):
+    import torch
+    cfg, s, L, Y, sp, sur, p, in_scale, osc = _setup(fc, torch, n=n, seed=n, scale=2.0)
+    M, G = s.n_mat, s.n_groups
+    loss, grad = fc.fcat_mlp_gradients(sur, sp, _t(torch, L), _t(torch, Y))
+    grad = grad.cpu().numpy().astype(np.float64)
+    W = omlp.group_weights(s.phi, s.eta, s.group_of_bin, G)
+    lin = omlp.linear_term(s.mu, s.phi, s.eta, s.group_of_bin, G)
+    T = omlp.residual_targets(L, Y, W, lin)
+    X = L.astype(np.float64) * in_scale
+    wts = omlp.loss_weights(Y)
+    l16, g16 = omlp.gradients(p, X, T, M, G, bf16=True, out_scale=osc, weights=wts)
+    l64, g64 = omlp.gradients(p, X, T, M, G, out_scale=osc, weights=wts)
+    assert abs(loss.item() - l16) <= 2e-3 * l16
+    gb, b16, b64 = _blocks(grad, M, G), _blocks(g16, M, G), _blocks(g64, M, G)
+    for k in gb:
+        e16 = np.linalg.norm(gb[k] - b16[k]) / np.linalg.norm(b16[k])
+        e64 = np.linalg.norm(gb[k] - b64[k]) / np.linalg.norm(b64[k])
+        print(f"n={n} {k}: vs bf16 oracle {e16:.2e}, vs fp64 oracle {e64:.2e}")
+        assert e16 <= 2e-2 and e64 <= 1e-1
+
+
+def test_forward_matches_oracle(fc):
+    import torch
+    cfg, s, L, Y, sp, sur, p, in_scale, osc = _setup(fc, torch, n=777, seed=3, scale=2.0)
+    G = s.n_groups
+    pred = fc.fcat_mlp_forward(sur, sp, _t(torch, L)).cpu().numpy()
+    W = omlp.group_weights(s.phi, s.eta, s.group_of_bin, G)
+    lin = omlp.linear_term(s.mu, s.phi, s.eta, s.group_of_bin, G)
+    ref = omlp.predict_yprim(p, L, in_scale, lin, W, G, bf16=True, out_scale=osc)
+    dz = np.abs(np.log(pred / ref))
+    print(f"forward: max |dz| vs bf16 oracle {dz.max():.2e}")
+    assert dz.max() <= 5e-3
+
+
+def test_adam_step_matches_oracle(fc):
+    import torch
+    cfg, s, L, Y, sp, sur, p, in_scale, osc = _setup(fc, torch, n=300, seed=5, scale=2.0)
+    loss, grad = fc.fcat_mlp_gradients(sur, sp, _t(torch, L), _t(torch, Y))
+    g = grad.cpu().numpy().astype(np.float64)
+    params = sur.params.clone()
+    tr = fc.MlpTrain(params=params, adam_m=torch.zeros_like(params), adam_v=torch.zeros_like(params), lr=1e-3)
+    fc.fcat_mlp_train_step(tr, sur, sp, _t(torch, L), _t(torch, Y))
+    assert tr.step == 1
+    want, m, v = omlp.adam(p.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    np.testing.assert_allclose(params.cpu().numpy(), want, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(tr.adam_m.cpu().numpy(), m, rtol=1e-5, atol=1e-12)
+
+
+def test_training_and_surrogate_projector(fc):
+    """Train on head-phantom rays (reduced size), validate, then project with the
+    network where validated and the exact sum elsewhere."""
+    import torch
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(5)
+    pb = fc.upload(cfg)
+    sur, rep = sg.build_surrogate(pb, n_samples=1_000_000, epochs=30, batch=4096, angles=np.arange(0, 720, 40),
+                                  seed=11)
+    print(f"training: {rep.n_train} samples, {rep.epochs} epochs, {rep.seconds:.2f} s; loss "
+          f"{rep.epoch_loss[0]:.3e} -> {rep.epoch_loss[-1]:.3e}; ok cells {int(rep.cell_ok.sum())}; "
+          f"held-out rays in ok cells {rep.holdout_in_ok_cells:.3f}")
+    print("cell max errors:", np.array2string(rep.cell_err.reshape(-1, 16), precision=1, max_line_width=200))
+    assert rep.epoch_loss[-1] < 0.2 * rep.epoch_loss[0]
+    sur.counts = torch.zeros(2, dtype=torch.int32, device="cuda")
+    out = fc.fcat_project(pb, mode="surrogate", surrogate=sur)
+    sample = [17, 500]
+    o = out[sample].cpu().numpy()
+    counts = sur.counts.cpu().numpy()
+    del out, pb
+    torch.cuda.empty_cache()
+    err = rel_err(o, oracle.project(cfg, sample))
+    print(f"surrogate projector: max rel err {err.max():.2e}; rays by network {counts[0]}, by exact sum {counts[1]}")
+    assert err.max() <= 1e-3

@@ -1,0 +1,125 @@
+"""Pins of the surrogate-network oracle.
+
+Gradients are pinned by central finite differences of the FP64 loss; the
+forward pass by a network whose output has a closed form; SiLU by its
+textbook values; Adam's first step by its closed form (|step| = lr per
+coordinate, up to eps); the linear term and residual targets by the
+single-bin (monoenergetic) group, where the residual is exactly zero, and by
+the first-order expansion for small path lengths.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _rand_params(rng, n_in, n_out, scale=0.3):
+    return rng.normal(0, scale, size=mlp.n_params(n_in, n_out))
+
+
+def test_silu_values():
+    z = np.array([0.0, 1.0, -1.0, 30.0, -30.0])
+    np.testing.assert_allclose(mlp.silu(z), [0.0, 1 / (1 + math.exp(-1)), -1 / (1 + math.e), 30.0, 0.0],
+                               atol=1e-10)
+    # derivative by central differences
+    zz = np.linspace(-6, 6, 101)
+    h = 1e-6
+    np.testing.assert_allclose(mlp.dsilu(zz), (mlp.silu(zz + h) - mlp.silu(zz - h)) / (2 * h), atol=1e-8)
+
+
+def test_forward_closed_form():
+    n_in, n_out = 10, 8
+    W1, b1 = np.zeros((64, n_in)), np.full(64, 0.5)
+    W2, b2 = np.zeros((64, 64)), np.full(64, -0.25)
+    W3 = np.arange(n_out * 64, dtype=float).reshape(n_out, 64) * 1e-3
+    b3 = np.linspace(-1, 1, n_out)
+    p = mlp.pack(W1, b1, W2, b2, W3, b3)
+    X = np.random.default_rng(0).uniform(0, 1, size=(5, n_in))
+    out, _ = mlp.forward(p, X, n_in, n_out)
+    want = W3.sum(1) * mlp.silu(-0.25) + b3
+    np.testing.assert_allclose(out, np.broadcast_to(want, (5, n_out)), rtol=1e-14)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradients_match_finite_differences(weighted):
+    rng = np.random.default_rng(1)
+    n_in, n_out, n = 10, 8, 17
+    p = _rand_params(rng, n_in, n_out)
+    X = rng.uniform(0, 1, size=(n, n_in))
+    T = rng.normal(0, 0.2, size=(n, n_out))
+    kw = {}
+    if weighted:
+        kw = dict(out_scale=rng.uniform(0.1, 3.0, size=n_out), weights=rng.uniform(0, 1, size=(n, n_out)))
+    _, g = mlp.gradients(p, X, T, n_in, n_out, **kw)
+    idx = rng.choice(p.size, size=60, replace=False)
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (mlp.loss(pp, X, T, n_in, n_out, **kw) - mlp.loss(pm, X, T, n_in, n_out, **kw)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+
+
+def test_loss_weights():
+    Y = np.array([[1.0, 1e-3], [1e-9, 2e-10], [0.5, 0.0]])      # [G][n]
+    w = mlp.loss_weights(Y)
+    tot = Y.sum(0)
+    assert w.shape == (2, 3)                                   # [n][G]
+    np.testing.assert_allclose(w[0], [1.0, min(1, 1e-9 / (1e-6 * tot[0])) ** 2, 1.0])
+    np.testing.assert_allclose(w[1], [1.0, min(1, 2e-10 / (1e-6 * tot[1])) ** 2, 0.0])
+
+
+def test_bf16_emulation_is_close_to_fp64():
+    rng = np.random.default_rng(2)
+    n_in, n_out = 10, 8
+    p = _rand_params(rng, n_in, n_out)
+    X = rng.uniform(0, 1, size=(64, n_in))
+    o64, _ = mlp.forward(p, X, n_in, n_out)
+    o16, _ = mlp.forward(p, X, n_in, n_out, bf16=True)
+    assert 0 < np.abs(o16 - o64).max() <= 0.05 * np.abs(o64).max()
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=20)
+    g = rng.normal(size=20)
+    lr = 1e-3
+    p1, m, v = mlp.adam(p, g, np.zeros(20), np.zeros(20), 1, lr, eps=0.0)
+    np.testing.assert_allclose(p1 - p, -lr * np.sign(g), rtol=1e-12)
+    # a quadratic bowl is descended
+    q = np.array([3.0])
+    m = v = np.zeros(1)
+    for t in range(1, 2001):
+        q, m, v = mlp.adam(q, q, m, v, t, 0.05)
+    assert abs(q[0]) < 0.05
+
+
+def test_linear_term_and_residuals():
+    rng = np.random.default_rng(4)
+    M, E = 4, 6
+    mu = rng.uniform(0.01, 0.1, size=(M, E))
+    phi, eta = rng.uniform(0.1, 1, size=E), rng.uniform(0.2, 1, size=E)
+    grp = np.array([0, 1, 1, 2, 2, 2])                  # group 0 is a single bin
+    lin = mlp.linear_term(mu, phi, eta, grp, 3)
+    np.testing.assert_allclose(lin[0], mu[:, 0], rtol=1e-15)
+    L = rng.uniform(0, 30, size=(50, M))
+    w = phi * eta
+    Yp = np.stack([(w[grp == g][None, :] * np.exp(-L @ mu[:, grp == g])).sum(1) for g in range(3)])
+    W = mlp.group_weights(phi, eta, grp, 3)
+    r = mlp.residual_targets(L, Yp, W, lin)
+    np.testing.assert_allclose(r[:, 0], 0.0, atol=1e-12)   # one bin: no beam hardening
+    assert np.all(r[:, 1:] <= 1e-12)                        # Jensen: the residual is never positive
+    # small path lengths: the residual is second order in L
+    r_small = mlp.residual_targets(L * 1e-3, np.stack([(w[grp == g][None, :] * np.exp(-(L * 1e-3) @ mu[:, grp == g])).sum(1)
+                                                       for g in range(3)]), W, lin)
+    assert np.abs(r_small).max() <= 1e-5 * np.abs(r).max() + 1e-15
+
+
+def test_cell_index():
+    L = np.array([[1.0, 5.0, 0.0], [10.0, 0.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 1e5]])
+    c = mlp.cell_index(L, 0.0, 2.0)
+    # sum 6 -> log10 0.778 -> bin 6, dominant 1; sum 10 -> bin 8, dominant 0; miss; out of range
+    np.testing.assert_array_equal(c, [1 * 16 + 6, 0 * 16 + 8, -1, -1])
