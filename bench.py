@@ -6,14 +6,18 @@ A step is one fcat_project call over the whole contrast-phantom workload:
 maps and 8 energy-group 15x15 optical spread kernels.  Inputs are seeded
 synthetic stand-ins, resident in HBM before timing starts.
 
-Prints one JSON line: rays x energy-bins per second, the roofline of the
-dominant kernel (timed live with HIP events on the library's stream), HBM
-GB/s of the compulsory traffic, and the FP64 oracle timed on the host on a
-bounded sample of the same workload.
+Prints one JSON line: rays x energy-bins per second of the plain FP32 form,
+the roofline of the dominant kernel (timed live with HIP events on the
+library's stream), the two other forms of the projector (BF16 hi/lo split on
+the same workload; the learned surrogate on the head workload, trained here
+by the library's own kernels) with their error against the plain form, and
+the FP64 oracle timed on the host on a bounded sample of the workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,8 +26,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+# MI355X: 256 compute units x 4 SIMDs x 16 lanes at 2.4 GHz.
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9          # 3.93e13 vector lane-operations per second
+PEAK_FP32_VECTOR_TFLOPS = 157.3               # published FP32 vector peak (packed FMA)
+PEAK_BF16_MFMA_TFLOPS = 2500.0                # published dense BF16 matrix peak
 PEAK_HBM_GBPS = 8000.0
+
+# Algorithmic work per unit (vector lane-operations).
+OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk
+EXP_SLOTS = 4                 # a transcendental issues at quarter rate
 
 
 def parse():
@@ -31,12 +42,181 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="plain", choices=["plain", "split_bf16", "surrogate"])
-    ap.add_argument("--cpu-angles", type=int, default=24,
+    ap.add_argument("--cpu-angles", type=int, default=360,
                     help="angles of the workload the FP64 oracle is timed on (0: skip)")
     ap.add_argument("--variant", default="", help="'z' for the 1.5625 mm slab variant")
+    ap.add_argument("--forms", default="split_bf16,surrogate",
+                    help="comma list of extra forms to measure beside the plain one ('' for none)")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
+    ap.add_argument("--surrogate-samples", type=int, default=4_000_000)
+    ap.add_argument("--surrogate-epochs", type=int, default=60)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (scale reference for HBM counters)")
     return ap.parse_args()
 
+
+# ----------------------------------------------------------------- counts
+
+def workload_counts(cfg, angles=None) -> dict:
+    """Rays, rays that cross the phantom and voxel segments of the exact walk
+    (per-axis voxel-plane crossings inside the box, plus one), for the given
+    angles; FP64 slab method in the conventions of the library."""
+    g, p = cfg.geometry, cfg.phantom
+    n = np.array([p.nx, p.ny, p.nz], np.float64)
+    h = np.array([p.dx, p.dy, p.dz], np.float64)
+    lo = np.array([p.cx, p.cy, p.cz], np.float64) - n * h / 2
+    hi = lo + n * h
+    th = g.angle_values()
+    if angles is None:
+        angles = np.arange(g.n_angles)
+    pu = ((np.arange(g.nu) - (g.nu - 1) / 2) * g.du + g.off_u)[None, :]
+    pv = ((np.arange(g.nv) - (g.nv - 1) / 2) * g.dv + g.off_v)[:, None]
+    segs = hits = 0
+    for a in angles:
+        c, s = np.cos(th[a]), np.sin(th[a])
+        src = np.array([g.sid * c, g.sid * s, 0.0])
+        cen = -(g.sdd - g.sid) * np.array([c, s, 0.0])
+        dst = np.stack(np.broadcast_arrays(cen[0] - pu * s, cen[1] + pu * c, pv + 0 * pu), -1)
+        d = dst - src
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a0, a1 = (lo - src) / d, (hi - src) / d
+            amin = np.maximum(0.0, np.nanmax(np.minimum(a0, a1), -1))
+            amax = np.minimum(1.0, np.nanmin(np.maximum(a0, a1), -1))
+        hit = amax > amin
+        i0 = np.clip(np.floor((src + amin[..., None] * d - lo) / h), 0, n - 1)
+        i1 = np.clip(np.floor((src + amax[..., None] * d - lo) / h), 0, n - 1)
+        segs += int((1 + np.abs(i1 - i0).sum(-1))[hit].sum())
+        hits += int(hit.sum())
+    return {"rays": len(angles) * g.nu * g.nv, "hit_rays": hits, "segments": segs}
+
+
+# -------------------------------------------------------------- traffic
+
+def source_digest(files) -> str:
+    hsh = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2011_04736_amd", "csrc", f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+TRACE_SOURCES = ["fcat_kernels.hip", "fcat_device.h", "fcat_internal.h"]
+
+
+def profiled_traffic(kernel: str, digest: str):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary,
+    or None when the summary is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_contrast.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"^sources:\s*(\S+)", text, re.M)
+    t = re.search(r"^traffic_bytes_per_launch:\s*(\S+)", text, re.M)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return float(t.group(1))
+
+
+# ----------------------------------------------------------------- forms
+
+def timed_steps(fn, warmup, steps, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    import paper_2011_04736_amd as fc
+    fc.fcat_timing_enable(True)
+    fc.fcat_timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = fc.fcat_timing_read(reset=True)
+    fc.fcat_timing_enable(False)
+    return elapsed, stages
+
+
+def rel_errors(x, ref, torch):
+    """Max and RMS of |x - ref| / max(|ref|, 1e-12 max|ref| of the angle), over all pixels."""
+    mx, ss, n = 0.0, 0.0, 0
+    for a0 in range(0, ref.shape[0], 64):
+        r = ref[a0:a0 + 64]
+        floor = 1e-12 * r.abs().amax(dim=(1, 2), keepdim=True)
+        e = (x[a0:a0 + 64] - r).abs() / torch.maximum(r.abs(), floor)
+        mx = max(mx, float(e.max()))
+        ss += float(e.double().pow(2).sum())
+        n += e.numel()
+    return mx, (ss / n) ** 0.5
+
+
+def form_split(pb, cfg, plain_out, args, torch, fc):
+    g, s = cfg.geometry, cfg.spectral
+    out = torch.empty_like(plain_out)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "split_bf16"), dtype=torch.uint8, device=out.device)
+    elapsed, stages = timed_steps(lambda: fc.fcat_project(pb, mode="split_bf16", out=out, workspace=ws),
+                                  1, args.steps, torch)
+    mx, rms = rel_errors(out, plain_out, torch)
+    ray_e = g.n_angles * g.nu * g.nv * s.n_energy
+    return {"workload": "contrast phantom (as the plain form)", "value": ray_e * args.steps / elapsed,
+            "unit": "ray*E/s", "ms_per_step": 1e3 * elapsed / args.steps,
+            "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
+            "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
+            "note": "the plain form is within 1e-5 of the FP64 oracle (parity tests)"}
+
+
+def form_surrogate(args, torch, fc):
+    import synth
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(5)
+    g, s = cfg.geometry, cfg.spectral
+    pb = fc.upload(cfg)
+    dev = pb.phantom.labels.device
+    ray_e = g.n_angles * g.nu * g.nv * s.n_energy
+    K = args.form_steps
+    plain = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "plain"), dtype=torch.uint8, device=dev)
+    t_plain, st_plain = timed_steps(lambda: fc.fcat_project(pb, mode="plain", out=plain, workspace=ws), 1, K, torch)
+    del ws
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    sur, rep = sg.build_surrogate(pb, n_samples=args.surrogate_samples, epochs=args.surrogate_epochs)
+    t_build = time.perf_counter() - t0
+    out = torch.empty_like(plain)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "surrogate"), dtype=torch.uint8, device=dev)
+    sur.counts = torch.zeros(2, dtype=torch.int32, device=dev)
+    fc.fcat_project(pb, mode="surrogate", surrogate=sur, out=out, workspace=ws)
+    counts = sur.counts.cpu().numpy().astype(np.int64)
+    sur.counts = None
+    t_sur, st_sur = timed_steps(lambda: fc.fcat_project(pb, mode="surrogate", surrogate=sur, out=out, workspace=ws),
+                                0, K, torch)
+    mx, rms = rel_errors(out, plain, torch)
+    mlp_ms = st_sur["mlp"][0] / K
+    # network MACs: n_in*64 + 64*64 + 64*n_out per ray that takes the network
+    macs = 64 * s.n_mat + 64 * 64 + 64 * s.n_groups
+    result = {
+        "workload": "head phantom 512x512x256 @0.5 mm, 10 materials, 120 bins 1-120 keV, 1024x768 detector "
+                    "@0.4 mm, 720 angles, scatter + 8 groups 15x15 PSF",
+        "plain": {"value": ray_e * K / t_plain, "unit": "ray*E/s", "ms_per_step": 1e3 * t_plain / K,
+                  "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st_plain.items() if v[1]}},
+        "surrogate": {"value": ray_e * K / t_sur, "unit": "ray*E/s", "ms_per_step": 1e3 * t_sur / K,
+                      "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st_sur.items() if v[1]},
+                      "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
+                      "rays_by_network": int(counts[0]), "rays_by_exact_sum": int(counts[1]),
+                      "mlp_stage_mfma_tflops": 2.0 * macs * counts[0] / (mlp_ms * 1e-3) / 1e12,
+                      "mlp_stage_mfma_frac": 2.0 * macs * counts[0] / (mlp_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS},
+        "gain_vs_plain": t_plain / t_sur,
+        "training": {"samples": rep.n_train, "holdout": rep.n_holdout, "epochs": rep.epochs,
+                     "train_seconds": round(rep.seconds, 2), "setup_seconds": round(t_build, 2),
+                     "final_loss": rep.epoch_loss[-1], "validated_cells": int(rep.cell_ok.sum()),
+                     "holdout_share_in_validated_cells": rep.holdout_in_ok_cells},
+    }
+    del pb, out, plain, ws
+    torch.cuda.empty_cache()
+    return result
+
+
+# ------------------------------------------------------------------ main
 
 def main():
     args = parse()
@@ -57,54 +237,57 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.copy_probe_mib > 0:
+        nel = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     cfg = synth.make_config(2, variant=args.variant)
     g, s = cfg.geometry, cfg.spectral
     pb = fc.upload(cfg, device=dev)
     out = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
-    ws_bytes = fc.fcat_project_workspace_bytes(pb, args.mode)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "plain"), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        fc.fcat_project(pb, mode=args.mode, out=out, workspace=ws, stream=stream)
-    torch.cuda.synchronize()
-
-    fc.fcat_timing_enable(True)
-    fc.fcat_timing_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fc.fcat_project(pb, mode=args.mode, out=out, workspace=ws, stream=stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = fc.fcat_timing_read(reset=True)
-    fc.fcat_timing_enable(False)
+    elapsed, stages = timed_steps(lambda: fc.fcat_project(pb, mode="plain", out=out, workspace=ws, stream=stream),
+                                  args.warmup, args.steps, torch)
 
     rays = g.n_angles * g.nu * g.nv
     ray_e = rays * s.n_energy
     ms_per_step = 1e3 * elapsed / args.steps
     value = ray_e * args.steps / elapsed
 
-    # dominant kernel and its roofline
-    G, K = s.n_groups, cfg.psf.k
-    dominant = max(("trace", "psf"), key=lambda k: stages[k][0])
-    psf_ms, psf_n = stages["psf"]
+    # rooflines of the two kernels of the step; the dominant one is reported
+    cnt = workload_counts(cfg)
+    G, K, M, E = s.n_groups, cfg.psf.k, s.n_mat, s.n_energy
     trace_ms, trace_n = stages["trace"]
-    psf_flops_total = 2.0 * G * K * K * rays * args.steps
-    roof = {
-        "kernel": "k_psf (optical spread + group sum)" if dominant == "psf" else "k_project_rows (traversal + spectral)",
-        "bound": "alu",
-        "unit": "TFLOP/s",
-        "peak": PEAK_FP32_VECTOR_TFLOPS,
-        "traffic": None,
+    psf_ms, psf_n = stages["psf"]
+    trace_ops = (OPS_PER_SEGMENT * cnt["segments"] + cnt["hit_rays"] * E * (M + 2 + EXP_SLOTS)) / max(trace_n
+                                                                                                    / args.steps, 1)
+    trace_avg = trace_ms / max(trace_n, 1)
+    trace_ach = trace_ops / (trace_avg * 1e-3) / 1e12
+    psf_flops = 2.0 * G * K * K * rays / max(psf_n / args.steps, 1)
+    psf_avg = psf_ms / max(psf_n, 1)
+    psf_ach = psf_flops / (psf_avg * 1e-3) / 1e12
+    kernels = {
+        "k_project_rows": {"bound": "alu", "achieved": round(trace_ach, 3), "peak": round(VALU_LANE_OPS / 1e12, 2),
+                           "unit": "Top/s", "frac": round(trace_ach * 1e12 / VALU_LANE_OPS, 4),
+                           "avg_launch_ms": round(trace_avg, 4), "launches_per_step": trace_n / args.steps,
+                           "algorithmic_ops_per_launch": trace_ops,
+                           "traffic": profiled_traffic("k_project_rows", source_digest(TRACE_SOURCES))},
+        "k_psf": {"bound": "alu", "achieved": round(psf_ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                  "unit": "TFLOP/s", "frac": round(psf_ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                  "avg_launch_ms": round(psf_avg, 4), "launches_per_step": psf_n / args.steps,
+                  "algorithmic_flops_per_launch": psf_flops,
+                  "traffic": profiled_traffic("k_psf", source_digest(TRACE_SOURCES))},
     }
-    if dominant == "psf":
-        ach = psf_flops_total / (psf_ms * 1e-3) / 1e12
-        roof.update(achieved=round(ach, 3), frac=round(ach / PEAK_FP32_VECTOR_TFLOPS, 4),
-                    avg_launch_ms=round(psf_ms / max(psf_n, 1), 4), launches=psf_n)
-    else:
-        roof.update(achieved=None, frac=None, avg_launch_ms=round(trace_ms / max(trace_n, 1), 4),
-                    launches=trace_n)
+    dominant = "k_project_rows" if trace_ms >= psf_ms else "k_psf"
+    roof = {k: kernels[dominant][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+    roof["kernel"] = dominant
 
     # compulsory HBM traffic per step: labels + scatter maps in, projections out
     comp_bytes = cfg.phantom.labels.size + 2 * rays * 4
@@ -127,14 +310,26 @@ def main():
             "workload": "contrast phantom 1024x1024x10 @0.15625 mm, 8 materials, 200 bins 0.01-6 MeV, "
                         "1024x64 detector @0.392 mm, 360 angles, scatter + 8 groups 15x15 PSF"
                         + (" (dz=1.5625 variant)" if args.variant == "z" else ""),
-            "mode": args.mode,
+            "mode": "plain",
             "rays": rays,
-            "energy_bins": s.n_energy,
+            "energy_bins": E,
+            "hit_rays": cnt["hit_rays"],
+            "voxel_segments": cnt["segments"],
         },
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
         "hbm_compulsory_GBps": round(hbm, 2),
         "roofline": roof,
+        "kernels": kernels,
     }
+
+    forms = [f for f in args.forms.split(",") if f]
+    result["forms"] = {}
+    if "split_bf16" in forms:
+        result["forms"]["split_bf16"] = form_split(pb, cfg, out, args, torch, fc)
+    del ws, out, pb
+    torch.cuda.empty_cache()
+    if "surrogate" in forms:
+        result["forms"]["surrogate"] = form_surrogate(args, torch, fc)
 
     if args.cpu_angles > 0:
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_angles, ray_e / g.n_angles)
@@ -153,7 +348,8 @@ def cpu_baseline(cfg, n_angles: int, ray_e_per_angle: float) -> dict:
     dt = time.perf_counter() - t0
     return {"value": len(angles) * ray_e_per_angle / dt, "unit": "ray*E/s", "cores": oracle.max_threads(),
             "kind": "oracle", "seconds": round(dt, 2),
-            "sample": f"{len(angles)} of {A} angles (evenly spaced), full detector, all bins, scatter and PSF"}
+            "sample": (f"{len(angles)} of {A} angles (evenly spaced), " if len(angles) < A else "all angles, ")
+                      + "full detector, all bins, scatter and PSF"}
 
 
 if __name__ == "__main__":
