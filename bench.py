@@ -49,7 +49,7 @@ def parse():
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
     ap.add_argument("--surrogate-samples", type=int, default=4_000_000)
-    ap.add_argument("--surrogate-epochs", type=int, default=60)
+    ap.add_argument("--surrogate-epochs", type=int, default=120)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale reference for HBM counters)")
     return ap.parse_args()

@@ -129,11 +129,16 @@ typedef struct fcat_psf_t {
  *   x_m  = L_m * in_scale[m]
  *   z_g  = sum_m lin[g][m] L_m + out_scale[g] MLP(x)_g
  *   Y_g  = I0 W_g exp(-z_g) + Ws_g S          with W_g = sum_{e in g} phi_e eta_e
- * MLP: h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), MLP(x) = W3 h2 + b3, with
- * weights rounded to BF16 and FP32 accumulation.  The exact spectral sum is
- * used instead wherever the ray falls outside the validated domain: the ray
- * misses, some x_m > 1, log10(sum_m L_m) is outside [cell_lo, cell_hi), or
- * cell_ok[dominant material * 16 + log-length bin] is 0.
+ * MLP: h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), MLP(x) = W3 h2 + b3.
+ * Every product a.b runs on the matrix cores as a_hi.b_hi + a_lo.b_hi +
+ * a_hi.b_lo with a_hi = bf16(a), a_lo = bf16(a - a_hi), FP32 accumulation.
+ *
+ * Validated domain.  With mbar_m = sum_e phi_e eta_e mu[m][e] / sum_e phi_e eta_e
+ * (the spectrum-weighted mean attenuation), the cell of a hit ray is
+ * (argmax_m mbar_m L_m) * 16 + floor(16 (tau - cell_lo) / (cell_hi - cell_lo)),
+ * tau = sum_m mbar_m L_m its mean optical depth.  The exact spectral sum is
+ * used wherever the ray misses, some x_m > 1, tau is outside
+ * [cell_lo, cell_hi), or cell_ok[cell] is 0.
  */
 #define FCAT_MLP_HIDDEN 64
 #define FCAT_MLP_CELLS 16
@@ -148,7 +153,7 @@ typedef struct fcat_surrogate_t {
     const float *out_scale;   /* DEVICE [n_out] */
     const float *lin;         /* DEVICE [n_out][n_in] (fcat_mlp_linear_term) */
     const uint8_t *cell_ok;   /* DEVICE [n_in * 16] (fcat_mlp_validate); needed by fcat_project only */
-    float cell_lo, cell_hi;   /* log10(mm) range of the 16 length bins, cell_lo < cell_hi */
+    float cell_lo, cell_hi;   /* optical-depth range of the 16 bins, cell_lo < cell_hi */
     int32_t *counts;          /* DEVICE [2] or NULL: fcat_project adds the number of rays the
                                  network handled and the number that fell back to the exact sum */
 } fcat_surrogate_t;
@@ -245,7 +250,8 @@ fcat_status fcat_check_inputs(const fcat_geometry_t *geometry, const fcat_phanto
  * a use of the simulator (Sec. IV.B).  Training data are (L, Yprim) pairs of
  * rays produced by fcat_pathlengths and fcat_spectral (no scatter, I0 = 1).
  * Every product runs on the matrix cores with BF16 operands and FP32
- * accumulation; the FP32 parameters are the master copy.
+ * accumulation (three-term hi/lo split in the forward pass, hi parts in the
+ * backward pass); the FP32 parameters are the master copy.
  */
 
 /* Number of FP32 parameters of an n_in -> 64 -> 64 -> n_out network. */
@@ -268,8 +274,8 @@ fcat_status fcat_mlp_forward(const fcat_surrogate_t *surrogate, const fcat_spect
  * mean squared error, over n <= FCAT_MLP_MAX_BATCH samples and the n_out
  * groups, between out_scale[g] MLP(x)_g and the residual target
  * r_g = -ln(Yprim_g / W_g) - sum_m lin[g][m] L_m, each term weighted by
- * min(1, Yprim_g / (1e-6 sum_g Yprim_g))^2 (groups carrying a negligible
- * share of the ray's signal count little, as in fcat_mlp_validate).
+ * min(1, Yprim_g / (1e-3 sum_g Yprim_g))^2 (groups carrying less than 0.1%
+ * of the ray's signal count less, as in fcat_mlp_validate).
  */
 fcat_status fcat_mlp_gradients(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral,
                                const float *L, const float *Yprim, int64_t n, float *grad, float *loss,
@@ -294,18 +300,33 @@ fcat_status fcat_mlp_train_epoch(fcat_mlp_train_t *train, const fcat_surrogate_t
                                  size_t workspace_bytes, void *stream);
 
 /*
- * Held-out validation: for every ray inside the training range (x_m <= 1 and
- * log10(sum L) in [cell_lo, cell_hi)), the largest over groups of
- * |predicted - exact| / max(exact, 1e-6 sum_g exact) is taken into its cell
- * (dominant material x 16 log-length bins).  cell_err (DEVICE float
- * [n_in*16] or NULL) gets the maximum per cell (inf where no ray fell),
- * cell_ok (DEVICE uint8 [n_in*16]) gets 1 where the cell holds at least
- * min_count rays and its maximum is <= threshold.
+ * Held-out validation: for every hit ray inside the training range (see
+ * fcat_surrogate_t), the largest over groups of
+ * |predicted - exact| / max(exact, 1e-3 sum_g exact) is taken into its cell.
+ * A group below 0.1% of the ray's signal is thus held to 1e-6 of that signal,
+ * so the bound carries over to the projection sum_g K_g (*) Y_g.  cell_err
+ * (DEVICE float [n_in*16] or NULL) gets the maximum per cell (inf where no
+ * ray fell), cell_ok (DEVICE uint8 [n_in*16]) gets 1 where the cell holds at
+ * least min_count rays and its maximum is <= threshold, cell_count (DEVICE
+ * int32 [n_in*16] or NULL) the number of rays per cell.
  */
 fcat_status fcat_mlp_validate(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral,
                               const float *L, const float *Yprim, int64_t n, float threshold, int32_t min_count,
-                              float *cell_err, uint8_t *cell_ok, void *workspace, size_t workspace_bytes,
-                              void *stream);
+                              float *cell_err, uint8_t *cell_ok, int32_t *cell_count, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+/*
+ * Set-up statistics of a training set L (DEVICE [n][n_mat]), Yprim (DEVICE
+ * [G][n]) with lin from fcat_mlp_linear_term, all written to DEVICE float:
+ * in_scale[m] = 1 / max(max_s L[s][m], 1e-6); out_scale[g] =
+ * max(1e-3, sqrt(sum_s w r^2 / sum_s w)) with the residual target r and
+ * weight w of fcat_mlp_gradients; tau_max[0] = max_s sum_m mbar_m L[s][m]
+ * (mbar as in fcat_surrogate_t), the top of the cells' optical-depth range.
+ * Deterministic (fixed reduction order).  Workspace: fcat_mlp_workspace_bytes.
+ */
+fcat_status fcat_mlp_setup(const fcat_spectral_t *spectral, const float *lin, const float *L, const float *Yprim,
+                           int64_t n, float *in_scale, float *out_scale, float *tau_max, void *workspace,
+                           size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------- kernel timing */
 

@@ -15,15 +15,19 @@ n_in -> 64 -> 64 -> n_out with SiLU activations (silu(z) = z / (1 + e^-z)),
 parameters packed as W1[64][n_in], b1[64], W2[64][64], b2[64], W3[n_out][64],
 b3[n_out].  s f learns the residual r_g = z_g - sum_m lin[g][m] L_m (the
 beam-hardening part of the attenuation) under a weighted squared error whose
-weight min(1, Yprim_g / (1e-6 sum_g Yprim_g))^2 discounts groups that carry a
-negligible share of the ray's signal.
+weight min(1, Yprim_g / (1e-3 sum_g Yprim_g))^2 discounts groups that carry
+less than 0.1% of the ray's signal.  The validated domain groups rays into
+cells by their dominant material and mean optical depth (``cell_index``).
 
-Everything here is plain NumPy in FP64.  ``bf16=True`` rounds the weights,
-inputs, hidden activations and back-propagated signals to BF16 at exactly
-the points where the GPU kernels feed them to the matrix cores, so the GPU
-can be compared with an identical computation; the FP64 gradients are
-pinned by central finite differences.  Adam follows Kingma & Ba (2015,
-Algorithm 1).
+Everything here is plain NumPy in FP64.  ``bf16=True`` reproduces the
+roundings of the GPU kernels at exactly the points where they feed the
+matrix cores, so the GPU can be compared with an identical computation:
+in the forward pass every product a.b of a weight and an input or hidden
+activation is formed from BF16 parts, a_hi.b_hi + a_lo.b_hi + a_hi.b_lo with
+v_hi = bf16(v) and v_lo = bf16(v - v_hi) (the lo.lo term is dropped); the
+backward pass rounds the back-propagated signals to BF16 and uses the hi
+parts of weights and activations.  The FP64 gradients are pinned by central
+finite differences.  Adam follows Kingma & Ba (2015, Algorithm 1).
 """
 from __future__ import annotations
 
@@ -76,16 +80,31 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
+def _hi_lo(a):
+    hi = _b(a, True)
+    return hi, _b(np.asarray(a, np.float64) - hi, True)
+
+
+def _layer(A, W, b, bf16: bool):
+    """A W^T + b; with bf16 the three-term BF16 split of every product."""
+    if not bf16:
+        return np.asarray(A, np.float64) @ np.asarray(W, np.float64).T + b
+    Ah, Al = _hi_lo(A)
+    Wh, Wl = _hi_lo(W)
+    return Ah @ Wh.T + Al @ Wh.T + Ah @ Wl.T + b
+
+
 def forward(p, X, n_in: int, n_out: int, bf16: bool = False):
-    """Network output f(X) [n][n_out] and the cached intermediates."""
+    """Network output f(X) [n][n_out] and the cached intermediates (inputs
+    and activations as the backward pass uses them: BF16 hi parts when bf16)."""
     W1, b1, W2, b2, W3, b3 = unpack(p, n_in, n_out)
-    Xb = _b(X, bf16)
-    Z1 = Xb @ _b(W1, bf16).T + b1
-    H1 = _b(silu(Z1), bf16)
-    Z2 = H1 @ _b(W2, bf16).T + b2
-    H2 = _b(silu(Z2), bf16)
-    out = H2 @ _b(W3, bf16).T + b3
-    return out, (Xb, Z1, H1, Z2, H2)
+    X = np.asarray(X, np.float64)
+    Z1 = _layer(X, W1, b1, bf16)
+    H1 = silu(Z1)
+    Z2 = _layer(H1, W2, b2, bf16)
+    H2 = silu(Z2)
+    out = _layer(H2, W3, b3, bf16)
+    return out, (_b(X, bf16), Z1, _b(H1, bf16), Z2, _b(H2, bf16))
 
 
 def _scales(out_scale, weights, shape):
@@ -161,10 +180,13 @@ def residual_targets(L, Yprim, W, lin) -> np.ndarray:
     return z - L @ np.asarray(lin, np.float64).T
 
 
+SHARE_FLOOR = 1e-3
+
+
 def loss_weights(Yprim) -> np.ndarray:
-    """w[n][G] = min(1, Yprim_g / (1e-6 sum_g Yprim_g))^2 for Yprim [G][n]."""
+    """w[n][G] = min(1, Yprim_g / (1e-3 sum_g Yprim_g))^2 for Yprim [G][n]."""
     Y = np.asarray(Yprim, np.float64).T
-    return np.minimum(1.0, Y / (1e-6 * Y.sum(1, keepdims=True))) ** 2
+    return np.minimum(1.0, Y / (SHARE_FLOOR * Y.sum(1, keepdims=True))) ** 2
 
 
 def predict_yprim(p, L, in_scale, lin, W, n_out: int, bf16: bool = False, out_scale=None) -> np.ndarray:
@@ -178,13 +200,53 @@ def predict_yprim(p, L, in_scale, lin, W, n_out: int, bf16: bool = False, out_sc
     return (np.asarray(W, np.float64)[None, :] * np.exp(-z)).T
 
 
-def cell_index(L, cell_lo: float, cell_hi: float) -> np.ndarray:
-    """Validation cell of each ray: dominant material * 16 + log10(sum L) bin; -1 outside."""
-    L = np.asarray(L, np.float64)
-    tot = L.sum(1)
-    dom = np.argmax(L, axis=1)
-    with np.errstate(divide="ignore"):
-        lt = np.log10(tot)
-    b = np.floor(CELLS * (lt - cell_lo) / (cell_hi - cell_lo))
-    ok = (tot > 0) & (b >= 0) & (b < CELLS)
+def mean_attenuation(W, lin) -> np.ndarray:
+    """mbar[m] = sum_g W_g lin[g][m] / sum_g W_g = sum_e w_e mu[m][e] / sum_e w_e."""
+    W = np.asarray(W, np.float64)
+    return W @ np.asarray(lin, np.float64) / W.sum()
+
+
+def cell_index(L, mbar, cell_lo: float, cell_hi: float, in_scale=None) -> np.ndarray:
+    """Validation cell of each ray: argmax_m mbar_m L_m * 16 + bin of the mean
+    optical depth tau = sum_m mbar_m L_m over [cell_lo, cell_hi); -1 for a miss,
+    a depth outside the bins, or (with in_scale) some L_m in_scale_m > 1.
+
+    The cell is an integer decision taken from floating point, so it is taken
+    here in the kernels' precision: FP32 products and sums in material order,
+    FP32 bin arithmetic.
+    """
+    f = np.float32
+    L = np.asarray(L, f)
+    t = L * np.asarray(mbar, f)[None, :]
+    tau = np.zeros(L.shape[0], f)
+    for m in range(L.shape[1]):
+        tau = tau + t[:, m]
+    dom = np.argmax(t, axis=1)
+    b = np.floor((f(CELLS) * (tau - f(cell_lo))) / (f(cell_hi) - f(cell_lo)))
+    ok = (L.sum(1, dtype=np.float64) > 0) & (b >= 0) & (b < CELLS)
+    if in_scale is not None:
+        ok &= np.all(L * np.asarray(in_scale, f)[None, :] <= f(1.0), axis=1)
     return np.where(ok, dom * CELLS + np.clip(b, 0, CELLS - 1).astype(np.int64), -1)
+
+
+def validation_errors(pred, Yprim) -> np.ndarray:
+    """Per ray max_g |pred_g - Y_g| / max(Y_g, 1e-3 sum_g Y_g), for [G][n] arrays."""
+    P = np.asarray(pred, np.float64)
+    Y = np.asarray(Yprim, np.float64)
+    floor = SHARE_FLOOR * Y.sum(0, keepdims=True)
+    return (np.abs(P - Y) / np.maximum(Y, floor)).max(0)
+
+
+def setup_stats(L, Yprim, W, lin):
+    """(in_scale, out_scale, tau_max) of a training set: 1 / max L_m (floor
+    1e-6 mm), the weighted RMS of the residual targets (floor 1e-3) and the
+    largest mean optical depth."""
+    L = np.asarray(L, np.float64)
+    in_scale = 1.0 / np.maximum(L.max(0), 1e-6)
+    w = loss_weights(Yprim)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = residual_targets(L, Yprim, W, lin)
+    r = np.where(w > 0, r, 0.0)
+    out_scale = np.maximum(1e-3, np.sqrt((w * r * r).sum(0) / np.maximum(w.sum(0), 1e-30)))
+    tau_max = float((L @ mean_attenuation(W, lin)).max())
+    return in_scale, out_scale, tau_max

@@ -144,8 +144,10 @@ def load() -> C.CDLL:
     L.fcat_mlp_train_step.restype = st
     L.fcat_mlp_train_epoch.argtypes = [trp, sup2, sp, vp, vp, i64, vp, C.c_int32, vp, vp, sz, vp]
     L.fcat_mlp_train_epoch.restype = st
-    L.fcat_mlp_validate.argtypes = [sup2, sp, vp, vp, i64, C.c_float, C.c_int32, vp, vp, vp, sz, vp]
+    L.fcat_mlp_validate.argtypes = [sup2, sp, vp, vp, i64, C.c_float, C.c_int32, vp, vp, vp, vp, sz, vp]
     L.fcat_mlp_validate.restype = st
+    L.fcat_mlp_setup.argtypes = [sp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+    L.fcat_mlp_setup.restype = st
     L.fcat_timing_enable.argtypes = [C.c_int]
     L.fcat_timing_enable.restype = st
     L.fcat_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int]
@@ -551,17 +553,33 @@ def fcat_mlp_train_epoch(train: MlpTrain, sur: Surrogate, spectral: Spectral, L,
 
 def fcat_mlp_validate(sur: Surrogate, spectral: Spectral, L, Yprim, threshold: float = 1e-3, min_count: int = 8,
                       workspace=None, stream=None):
-    """(cell_err, cell_ok) of the held-out set; also stores cell_ok in ``sur``."""
+    """(cell_err, cell_ok, cell_count) of the held-out set; also stores cell_ok in ``sur``."""
     torch = _require_gpu()
     n_out, n_in = (int(x) for x in sur.lin.shape)
     dev = L.device
     cell_err = torch.empty(n_in * 16, dtype=torch.float32, device=dev)
     cell_ok = torch.empty(n_in * 16, dtype=torch.uint8, device=dev)
+    cell_count = torch.empty(n_in * 16, dtype=torch.int32, device=dev)
     ws = _mlp_ws(spectral, 1, dev, workspace)
     cs, _keep = spectral.c()
     cu = sur.c()
     _check(load().fcat_mlp_validate(C.byref(cu), C.byref(cs), _ptr(L), _ptr(Yprim), int(L.shape[0]),
-                                    float(threshold), int(min_count), _ptr(cell_err), _ptr(cell_ok), _ptr(ws),
-                                    ws.numel(), _stream(stream)))
+                                    float(threshold), int(min_count), _ptr(cell_err), _ptr(cell_ok),
+                                    _ptr(cell_count), _ptr(ws), ws.numel(), _stream(stream)))
     sur.cell_ok = cell_ok
-    return cell_err, cell_ok
+    return cell_err, cell_ok, cell_count
+
+
+def fcat_mlp_setup(spectral: Spectral, lin, L, Yprim, workspace=None, stream=None):
+    """(in_scale, out_scale, tau_max) of a training set (device tensors)."""
+    torch = _require_gpu()
+    M = int(spectral.mu.shape[0])
+    dev = L.device
+    in_scale = torch.empty(M, dtype=torch.float32, device=dev)
+    out_scale = torch.empty(spectral.n_groups, dtype=torch.float32, device=dev)
+    tau_max = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = _mlp_ws(spectral, 1, dev, workspace)
+    cs, _keep = spectral.c()
+    _check(load().fcat_mlp_setup(C.byref(cs), _ptr(lin), _ptr(L), _ptr(Yprim), int(L.shape[0]), _ptr(in_scale),
+                                 _ptr(out_scale), _ptr(tau_max), _ptr(ws), ws.numel(), _stream(stream)))
+    return in_scale, out_scale, tau_max

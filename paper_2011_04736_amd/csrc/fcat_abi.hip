@@ -156,7 +156,7 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, afrag, wtile, frag, bricks, Y, Lbuf, fixed;
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, frag, mbar, bricks, Y, Lbuf, fixed;
     size_t per_angle;    // bytes of per-angle chunk buffers (group signals, path lengths)
     size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
 };
@@ -195,6 +195,8 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (sp) o += align_up((size_t)sp->T * 16 * sizeof(float));
     L.frag = o;
     if (surrogate) o += align_up((size_t)kMlpFrags * kWave * 16);
+    L.mbar = o;
+    if (surrogate) o += align_up((size_t)FCAT_MLP_MAX_IO * sizeof(float));
     L.bricks = o;
     o += align_up(nbricks);
     L.fixed = o;
@@ -337,8 +339,11 @@ fcat_status prep_mlp(const fcat_surrogate_t *u, const float *params, const SpecT
         StageTimer tm(FCAT_STAGE_PREP, stream);
         e = launch_mlp_prep(params, t.M, t.G, frag, stream);
     }
+    float *mbar = at<float>(ws, L.mbar);
+    if (e == hipSuccess) e = launch_mlp_mbar(t, u->lin, mbar, stream);
     if (e != hipSuccess) return device_fail(e, "mlp_prep");
     mt.frag = frag;
+    mt.mbar = mbar;
     mt.params = params;
     mt.in_scale = u->in_scale;
     mt.out_scale = u->out_scale;
@@ -355,7 +360,7 @@ fcat_status prep_mlp(const fcat_surrogate_t *u, const float *params, const SpecT
 // gradient partials and loss sums, and the validation cells.
 struct MlpLayout {
     Layout base;
-    size_t partial, loss_partial, cells, total;
+    size_t partial, loss_partial, cells, stats, total;
     int nparts, P;
 };
 
@@ -372,6 +377,8 @@ MlpLayout mlp_layout(const SpecTables &t, int64_t batch)
     o += align_up((size_t)m.nparts * sizeof(float));
     m.cells = o;
     o += align_up((size_t)2 * FCAT_MLP_MAX_IO * FCAT_MLP_CELLS * sizeof(int));
+    m.stats = o;
+    o += align_up((size_t)kStatBlocks * kStatStride * sizeof(float));
     m.total = o;
     return m;
 }
@@ -853,7 +860,8 @@ fcat_status fcat_mlp_train_epoch(fcat_mlp_train_t *train, const fcat_surrogate_t
 
 fcat_status fcat_mlp_validate(const fcat_surrogate_t *surrogate, const fcat_spectral_t *spectral, const float *L,
                               const float *Yprim, int64_t n, float threshold, int32_t min_count, float *cell_err,
-                              uint8_t *cell_ok, void *workspace, size_t workspace_bytes, void *stream_)
+                              uint8_t *cell_ok, int32_t *cell_count, void *workspace, size_t workspace_bytes,
+                              void *stream_)
 {
     g_last_error.clear();
     if (n < 1 || !L || !Yprim || !cell_ok) return fail(FCAT_E_INVALID_ARG, "L, Yprim, cell_ok and n >= 1 are needed");
@@ -877,8 +885,40 @@ fcat_status fcat_mlp_validate(const fcat_surrogate_t *surrogate, const fcat_spec
         e = launch_zero_ints(reinterpret_cast<int *>(bits), 2 * FCAT_MLP_MAX_IO * FCAT_MLP_CELLS, stream);
         if (e == hipSuccess) e = launch_mlp_validate(t, mt, L, Yprim, n, bits, count, stream);
         if (e == hipSuccess) e = launch_mlp_cells(bits, count, ncell, threshold, min_count, cell_err, cell_ok, stream);
+        if (e == hipSuccess && cell_count)
+            e = hipMemcpyAsync(cell_count, count, (size_t)ncell * sizeof(int), hipMemcpyDeviceToDevice, stream);
     }
     if (e != hipSuccess) return device_fail(e, "mlp_validate");
+    return FCAT_OK;
+}
+
+fcat_status fcat_mlp_setup(const fcat_spectral_t *spectral, const float *lin, const float *L, const float *Yprim,
+                           int64_t n, float *in_scale, float *out_scale, float *tau_max, void *workspace,
+                           size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    if (n < 1 || !lin || !L || !Yprim || !in_scale || !out_scale || !tau_max)
+        return fail(FCAT_E_INVALID_ARG, "lin, L, Yprim, in_scale, out_scale, tau_max and n >= 1 are needed");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    SpecTables t{};
+    fcat_status s;
+    if ((s = check_spectral(spectral, true, t))) return s;
+    if (t.M > FCAT_MLP_MAX_IO || t.G > FCAT_MLP_MAX_IO)
+        return fail(FCAT_E_INVALID_ARG, "n_mat and n_groups must be <= %d", FCAT_MLP_MAX_IO);
+    const MlpLayout ml = mlp_layout(t, 1);
+    if ((s = check_workspace(workspace, workspace_bytes, ml.total))) return s;
+    if ((s = check_pending())) return s;
+    if ((s = prep_tables(spectral, nullptr, t, ml.base, workspace, stream))) return s;
+    float *mbar = at<float>(workspace, ml.base.mbar);
+    float *partial = at<float>(workspace, ml.stats);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_MLP, stream);
+        e = launch_mlp_mbar(t, lin, mbar, stream);
+        if (e == hipSuccess)
+            e = launch_mlp_stats(t, lin, mbar, L, Yprim, n, partial, in_scale, out_scale, tau_max, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "mlp_setup");
     return FCAT_OK;
 }
 

@@ -38,6 +38,23 @@ __device__ __forceinline__ uint32_t bf16_rne(float x)
 
 __device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to packed BF16 (a in the low half), round to nearest, ties to
+// even: one v_cvt_pk_bf16_f32 on gfx950.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b)
+{
+    const bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// hi = bf16(v), lo = bf16(v - hi) for a pair of floats (v - hi is exact in FP32).
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t &hi, uint32_t &lo)
+{
+    hi = pack_bf16x2(a, b);
+    lo = pack_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
+
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Hardware hands consecutive workgroups to the 8 XCDs in turn.  Remap so that

@@ -62,7 +62,7 @@ struct SplitTables {
 
 // Surrogate network tables (fcat_mlp.hip).  frag holds the BF16 B-operand
 // fragments of every weight view the forward and backward passes use.
-constexpr int kMlpFrags = 26;
+constexpr int kMlpFrags = 52;
 struct MlpTables {
     const uint4 *frag;             // [kMlpFrags][64]
     const float *params;           // FP32 master parameters (biases read from here)
@@ -70,9 +70,17 @@ struct MlpTables {
     const float *out_scale;        // [n_out]
     const float *lin;              // [n_out][n_in]
     const uint8_t *cell_ok;        // [n_in * FCAT_MLP_CELLS]
-    float cell_lo, cell_hi;
+    const float *mbar;             // [n_in] spectrum-weighted mean attenuation per material
+    float cell_lo, cell_hi;        // optical-depth range of the cells
     int n_in, n_out;
 };
+
+// Relative floor of the surrogate's error and loss weight: a group counts
+// fully once it carries this share of the ray's primary signal.
+constexpr float kMlpShareFloor = 1e-3f;
+// Set-up statistics: fixed grid and per-block record of k_mlp_stats.
+constexpr int kStatBlocks = 1024;
+constexpr int kStatStride = 64;    // max L [16], max tau [1], sum w r^2 [16], sum w [16]
 
 // Inputs and outputs of the surrogate spectral stage over n rays of L.
 // Ray r belongs to angle r / plane, pixel r % plane.
@@ -90,6 +98,10 @@ struct SurrogateIO {
 int mlp_param_count(int n_in, int n_out);
 hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag, hipStream_t stream);
 hipError_t launch_mlp_linear(const float *mu, const SpecTables &t, float *lin, hipStream_t stream);
+hipError_t launch_mlp_mbar(const SpecTables &t, const float *lin, float *mbar, hipStream_t stream);
+hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *mbar, const float *L, const float *Y,
+                            int64_t n, float *partial, float *in_scale, float *out_scale, float *tau_max,
+                            hipStream_t stream);
 hipError_t launch_mlp_spectral(const SpecTables &t, const MlpTables &m, const SurrogateIO &io, hipStream_t stream);
 hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n_all,
                            const int32_t *order, int64_t base, int count, float *partial, float *loss_partial,

@@ -9,14 +9,18 @@
 // perceptron of x_m = L_m in_scale_m, that learns the beam-hardening
 // residual.
 //
-// Every product runs on v_mfma_f32_16x16x32_bf16: weights, inputs and hidden
-// activations are rounded to BF16 (nearest even), accumulation is FP32.  One
-// wavefront handles 64 rays or samples; the activations pass between layers
-// through LDS (the matrix-core output layout is the transpose of the input
-// layout the next layer needs).  Training runs forward and backward on the
-// same 64-sample tiles and writes one gradient partial per wavefront; the
-// Adam kernel sums the partials in a fixed order, so training is
-// deterministic.
+// Every product runs on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// The forward pass (training and inference) splits each weight, input and
+// hidden activation v into v_hi = bf16(v) and v_lo = bf16(v - v_hi) and forms
+// a.b as a_hi.b_hi + a_lo.b_hi + a_hi.b_lo (the same three-term split as the
+// L . mu contraction of the split-precision projector), so the network is
+// evaluated to about FP32 accuracy rather than to BF16's 2^-9: the learned
+// residual is of order one, and BF16 rounding alone would leave errors of
+// order 1e-3 in the attenuation.  The backward pass uses the hi parts only
+// (gradient directions need no more).  One wavefront handles 64 rays or
+// samples; activations pass between layers through LDS.  Training writes one
+// gradient partial per wavefront and the Adam kernel sums the partials in a
+// fixed order, so training is deterministic.
 #include "fcat_device.h"
 
 namespace fcat {
@@ -27,12 +31,26 @@ constexpr int SX = 40;                 // row stride (BF16) of 32-wide K buffers
 constexpr int SH = 72;                 // row stride (BF16) of 64-wide K buffers
 constexpr int SO = 17;                 // row stride (FP32) of the 16-wide output buffer
 
-// B-operand fragment index (in units of 64 lanes) of each weight view.
-constexpr int kFragW1 = 0;    // [ct 0..3][kb 0]      W1[n][k], k < n_in
-constexpr int kFragW2 = 4;    // [ct 0..3][kb 0..1]   W2[n][k]
-constexpr int kFragW3 = 12;   // [ct 0][kb 0..1]      W3[n][k], n < n_out
-constexpr int kFragW3b = 14;  // [ct 0..3][kb 0]      B[o][h2] = W3[o][h2]   (dH2 = dZ3 W3)
-constexpr int kFragW2b = 18;  // [ct 0..3][kb 0..1]   B[h2][h1] = W2[h2][h1] (dH1 = dZ2 W2)
+// Fragment index (in units of 64 lanes) of each weight view.  Lane
+// (q = l/16, r = l%16) of tile t holds W[16 t + r][8 q + j], j < 8: the
+// layout of the B operand of v_mfma_f32_16x16x32_bf16 for W[n][k] and,
+// identically, of its A operand for W[m][k].
+constexpr int kFragW1 = 0;     // [ht 0..3]          k < 16: W1_hi[n][k]; 16 <= k < 32: W1_hi[n][k - 16]
+constexpr int kFragW1lo = 4;   // [ht 0..3]          k < 16: W1_lo[n][k]; else 0
+constexpr int kFragW2 = 8;     // [ht 0..3][kb 0..1] W2_hi[n][32 kb + k]
+constexpr int kFragW2lo = 16;  // [ht 0..3][kb 0..1] W2_lo
+constexpr int kFragW3 = 24;    // [kb 0..1]          W3_hi[n][32 kb + k], n < n_out
+constexpr int kFragW3lo = 26;  // [kb 0..1]          W3_lo
+constexpr int kFragW3b = 28;   // [ht 0..3]          B[o][h2] = W3_hi[o][h2]   (dH2 = dZ3 W3)
+constexpr int kFragW2b = 32;   // [ht 0..3][kb 0..1] B[h2][h1] = W2_hi[h2][h1] (dH1 = dZ2 W2)
+// Inference views with log2(e) folded in (see mlp_infer_wave): W1 scaled by
+// log2(e) and W3 by 1/log2(e) before the hi/lo split.
+constexpr int kFragW1i = 40;   // as kFragW1
+constexpr int kFragW1iLo = 44; // as kFragW1lo
+constexpr int kFragW3i = 48;   // as kFragW3
+constexpr int kFragW3iLo = 50; // as kFragW3lo
+static_assert(kFragW3iLo + 2 == kMlpFrags, "fragment table size");
+constexpr float kLog2e = 1.4426950408889634f;
 
 struct Offsets {
     int W1, b1, W2, b2, W3, b3, P;
@@ -61,11 +79,15 @@ __device__ __forceinline__ bf16x8 lds_frag(const uint16_t *base, int stride, int
     return *reinterpret_cast<const bf16x8 *>(base + row * stride + k);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// silu(z) = z sigmoid(z); sigmoid through v_exp_f32 and v_rcp_f32 (about
+// 1 ulp each).  exp(-z) overflows to +inf for z < -88, and rcp(inf) = 0.
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 
 __device__ __forceinline__ float dsilu(float z)
 {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -76,128 +98,188 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Forward pass of the 64 rays of the wavefront.  x (n_in values per lane)
-// goes in; the n_out outputs of the ray of lane l come back in O[l][0..n_out).
-__device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTables &M, uint16_t *X,
-                                               uint16_t *Hb, float *O)
+// Per-wavefront LDS of the forward pass.  X holds the inputs of the 64 rays,
+// row r = [x_hi (16) | x_lo (16)]; the outputs of ray r later reuse row r
+// (only that ray's tile has read it by then).  Hh/Hl hold the hi/lo parts of
+// one 16-ray tile's hidden activations, [ray][unit].
+constexpr int SOI = SX / 2;            // row stride (FP32) of the outputs in X
+struct InferLds {
+    uint16_t X[kWave * SX];
+    uint16_t Hh[16 * SH];
+    uint16_t Hl[16 * SH];
+};
+
+// With z' = log2(e) z, log2(e) silu(z) = z' / (1 + 2^-z'): one v_exp_f32,
+// one add, one v_rcp_f32 and one multiply.
+__device__ __forceinline__ float silu2(float zs)
+{
+    return zs * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-zs));
+}
+
+// SiLU of the 4 units of an output fragment (bias already in the
+// accumulator), split and stored as one 8-byte hi and one 8-byte lo write
+// at Hs[ray][unit0 .. unit0 + 3].
+__device__ __forceinline__ void silu_store4(const floatx4 &acc, uint16_t *Hh, uint16_t *Hl, int at)
+{
+    const float h0 = silu2(acc[0]), h1 = silu2(acc[1]);
+    const float h2 = silu2(acc[2]), h3 = silu2(acc[3]);
+    uint32_t hi01, lo01, hi23, lo23;
+    split_bf16x2(h0, h1, hi01, lo01);
+    split_bf16x2(h2, h3, hi23, lo23);
+    *reinterpret_cast<uint2 *>(Hh + at) = make_uint2(hi01, hi23);
+    *reinterpret_cast<uint2 *>(Hl + at) = make_uint2(lo01, lo23);
+}
+
+// Forward pass of the 64 rays of the wavefront, one 16-ray tile at a time.
+// The weights are the A operand (rows = units), the activations the B
+// operand (columns = rays), so each lane ends up with 4 consecutive units of
+// one ray and stores them with one write; the accumulators start at the
+// biases.  The pass runs on z' = log2(e) z: W1 and b1, b2 carry the factor
+// (W2 needs none, since the hidden values are log2(e) silu), and W3 its
+// inverse, which yields the same network output as the unscaled form.
+// x (n_in values per lane, zero beyond) goes in; the n_out outputs of lane
+// l's ray come back in out[].
+__device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTables &M, InferLds &S,
+                                               float (&out)[16])
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int q = lane >> 4, r16 = lane & 15;
     const Offsets off = param_offsets(M.n_in, M.n_out);
     const float *P = M.params;
+    {
+        uint32_t hi[8], lo[8];
 #pragma unroll
-    for (int k = 0; k < 32; k += 2) {
-        const uint32_t lo = k < 16 ? bf16_rne(x[k]) : 0u;
-        const uint32_t hi = k + 1 < 16 ? bf16_rne(x[k + 1]) : 0u;
-        *reinterpret_cast<uint32_t *>(X + lane * SX + k) = lo | (hi << 16);
+        for (int k = 0; k < 8; ++k) split_bf16x2(x[2 * k], x[2 * k + 1], hi[k], lo[k]);
+        uint4 *row = reinterpret_cast<uint4 *>(S.X + lane * SX);
+        row[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        row[1] = make_uint4(hi[4], hi[5], hi[6], hi[7]);
+        row[2] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        row[3] = make_uint4(lo[4], lo[5], lo[6], lo[7]);
     }
+    floatx4 b1[4], b2[4], b3;
+#pragma unroll
+    for (int ht = 0; ht < 4; ++ht)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            b1[ht][i] = kLog2e * P[off.b1 + 16 * ht + 4 * q + i];
+            b2[ht][i] = kLog2e * P[off.b2 + 16 * ht + 4 * q + i];
+        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b3[i] = 4 * q + i < M.n_out ? P[off.b3 + 4 * q + i] : 0.0f;
     wave_sync_lds();
-    // layer 1: [64 x 32] x [32 x 64]
-    floatx4 acc[4][4];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        const bf16x8 a = lds_frag(X, SX, 16 * rt + r16, 8 * q);
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1 + ct, lane),
-                                                                  floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    }
-#pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
-        const float b = P[off.b1 + 16 * ct + r16];
+        // layer 1: Z1 = W1_hi (x_hi + x_lo) + W1_lo x_hi + b1
+        const bf16x8 bx = lds_frag(S.X, SX, 16 * ct + r16, 8 * q);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                Hb[(16 * rt + 4 * q + i) * SH + 16 * ct + r16] = (uint16_t)bf16_rne(silu(acc[rt][ct][i] + b));
-    }
-    wave_sync_lds();
-    // layer 2: [64 x 64] x [64 x 64]
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+        for (int ht = 0; ht < 4; ++ht) {
+            floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW1i + ht, lane), bx, b1[ht],
+                                                                  0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW1iLo + ht, lane), bx, acc, 0, 0, 0);
+            silu_store4(acc, S.Hh, S.Hl, r16 * SH + 16 * ht + 4 * q);
+        }
+        wave_sync_lds();
+        // layer 2 (in place): Z2 = W2_hi (H1_hi + H1_lo) + W2_lo H1_hi
+        bf16x8 hh[2], hl[2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 a = lds_frag(Hb, SH, 16 * rt + r16, 32 * kb + 8 * q);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, frag_of(M.frag, kFragW2 + ct * 2 + kb, lane), acc[rt][ct], 0, 0, 0);
+            hh[kb] = lds_frag(S.Hh, SH, r16, 32 * kb + 8 * q);
+            hl[kb] = lds_frag(S.Hl, SH, r16, 32 * kb + 8 * q);
         }
-    wave_sync_lds();
+        wave_sync_lds();
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const float b = P[off.b2 + 16 * ct + r16];
+        for (int ht = 0; ht < 4; ++ht) {
+            floatx4 acc = b2[ht];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
+            for (int kb = 0; kb < 2; ++kb) {
+                const bf16x8 wh = frag_of(M.frag, kFragW2 + ht * 2 + kb, lane);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hh[kb], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hl[kb], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW2lo + ht * 2 + kb, lane),
+                                                              hh[kb], acc, 0, 0, 0);
+            }
+            silu_store4(acc, S.Hh, S.Hl, r16 * SH + 16 * ht + 4 * q);
+        }
+        wave_sync_lds();
+        // layer 3: outputs 4q .. 4q+3 of ray 16 ct + r16
+        floatx4 acc = b3;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                Hb[(16 * rt + 4 * q + i) * SH + 16 * ct + r16] = (uint16_t)bf16_rne(silu(acc[rt][ct][i] + b));
+        for (int kb = 0; kb < 2; ++kb) {
+            const bf16x8 h = lds_frag(S.Hh, SH, r16, 32 * kb + 8 * q);
+            const bf16x8 l = lds_frag(S.Hl, SH, r16, 32 * kb + 8 * q);
+            const bf16x8 wh = frag_of(M.frag, kFragW3i + kb, lane);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, h, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, l, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW3iLo + kb, lane), h, acc, 0, 0, 0);
+        }
+        if (4 * q < M.n_out) {
+            float *o = reinterpret_cast<float *>(S.X) + (16 * ct + r16) * SOI + 4 * q;
+            *reinterpret_cast<float4 *>(o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        }
+        wave_sync_lds();
     }
-    wave_sync_lds();
-    // layer 3: [64 x 64] x [64 x 16]
-    floatx4 o3[4];
+    const float *o = reinterpret_cast<const float *>(S.X) + lane * SOI;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        o3[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_frag(Hb, SH, 16 * rt + r16, 32 * kb + 8 * q),
-                                                             frag_of(M.frag, kFragW3 + kb, lane), o3[rt], 0, 0, 0);
-    }
-    const float b3 = r16 < M.n_out ? P[off.b3 + r16] : 0.0f;
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) O[(16 * rt + 4 * q + i) * SO + r16] = o3[rt][i] + b3;
+    for (int g = 0; g < 16; ++g) out[g] = g < M.n_out ? o[g] : 0.0f;
     wave_sync_lds();
 }
 
-// Per-wavefront LDS of the forward pass; the output buffer reuses the input
-// buffer, which is dead after the first layer.
-struct InferLds {
-    union {
-        uint16_t X[kWave * SX];
-        float O[kWave * SO];
-    };
-    uint16_t Hb[kWave * SH];
-};
-
 // ------------------------------------------------------------ kernels
 
-// B-operand fragments of every weight view (FP32 master -> BF16).
+// Fragments of every weight view (FP32 master -> BF16 hi or lo part).
+__device__ __forceinline__ float hi_part(float v) { return bf16_value(bf16_rne(v)); }
+
 __global__ __launch_bounds__(kBlock) void k_mlp_prep(const float *__restrict__ params, int n_in, int n_out,
                                                      uint4 *__restrict__ frag)
 {
     const int idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= kMlpFrags * kWave) return;
-    const int f = idx / kWave, lane = idx % kWave;
+    const int fi = idx / kWave, lane = idx % kWave;
     const int q = lane >> 4, r16 = lane & 15;
     const Offsets off = param_offsets(n_in, n_out);
+    // the inference views are the W1 / W3 views of scaled weights
+    int f = fi;
+    float scale = 1.0f;
+    if (fi >= kFragW1i && fi < kFragW3i) {
+        f = kFragW1 + (fi - kFragW1i);
+        scale = kLog2e;
+    } else if (fi >= kFragW3i) {
+        f = kFragW3 + (fi - kFragW3i);
+        scale = 1.0f / kLog2e;
+    }
     uint32_t h[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
+        const int kk = 8 * q + j;
         float v = 0.0f;
-        if (f < kFragW2) {                       // W1[n][k]
-            const int n = 16 * (f - kFragW1) + r16, k = 8 * q + j;
-            if (k < n_in) v = params[off.W1 + n * n_in + k];
-        } else if (f < kFragW3) {                // W2[n][k]
-            const int ct = (f - kFragW2) / 2, kb = (f - kFragW2) % 2;
-            const int n = 16 * ct + r16, k = 32 * kb + 8 * q + j;
-            v = params[off.W2 + n * H + k];
-        } else if (f < kFragW3b) {               // W3[n][k]
-            const int kb = f - kFragW3;
-            const int n = r16, k = 32 * kb + 8 * q + j;
-            if (n < n_out) v = params[off.W3 + n * H + k];
+        if (f < kFragW1lo) {                     // [W1_hi | W1_hi]
+            const int n = 16 * (f - kFragW1) + r16, k = kk & 15;
+            if (k < n_in) v = hi_part(scale * params[off.W1 + n * n_in + k]);
+        } else if (f < kFragW2) {                // [W1_lo | 0]
+            const int n = 16 * (f - kFragW1lo) + r16;
+            if (kk < n_in) {
+                const float w = scale * params[off.W1 + n * n_in + kk];
+                v = w - hi_part(w);
+            }
+        } else if (f < kFragW3) {                // W2_hi, W2_lo
+            const bool lo = f >= kFragW2lo;
+            const int t = f - (lo ? kFragW2lo : kFragW2);
+            const int n = 16 * (t / 2) + r16, k = 32 * (t % 2) + kk;
+            const float w = params[off.W2 + n * H + k];
+            v = lo ? w - hi_part(w) : w;
+        } else if (f < kFragW3b) {               // W3_hi, W3_lo
+            const bool lo = f >= kFragW3lo;
+            const int kb = f - (lo ? kFragW3lo : kFragW3);
+            const int n = r16, k = 32 * kb + kk;
+            if (n < n_out) {
+                const float w = scale * params[off.W3 + n * H + k];
+                v = lo ? w - hi_part(w) : w;
+            }
         } else if (f < kFragW2b) {               // B[k = o][n = h2] = W3[o][h2]
-            const int n = 16 * (f - kFragW3b) + r16, k = 8 * q + j;
-            if (k < n_out) v = params[off.W3 + k * H + n];
+            const int n = 16 * (f - kFragW3b) + r16;
+            if (kk < n_out) v = params[off.W3 + kk * H + n];
         } else {                                 // B[k = h2][n = h1] = W2[h2][h1]
             const int ct = (f - kFragW2b) / 2, kb = (f - kFragW2b) % 2;
-            const int n = 16 * ct + r16, k = 32 * kb + 8 * q + j;
+            const int n = 16 * ct + r16, k = 32 * kb + kk;
             v = params[off.W2 + k * H + n];
         }
         h[j] = bf16_rne(v);
@@ -220,26 +302,37 @@ __global__ __launch_bounds__(kBlock) void k_mlp_linear(const float *__restrict__
     lin[idx] = (float)(a / b);
 }
 
-// Validated-domain test of one ray (see fcat_surrogate_t).
-__device__ __forceinline__ bool in_domain(const float (&L)[16], const float (&x)[16], float tot, const MlpTables &M)
+// Validation cell of a hit ray: the dominant material by optical depth
+// mbar_m L_m, times 16 bins of the total optical depth over
+// [cell_lo, cell_hi); -1 outside the training range (some x_m > 1 or the
+// depth outside the bins).
+__device__ __forceinline__ int cell_of(const float (&L)[16], const float (&x)[16], const MlpTables &M)
 {
-    bool ok = tot > 0.0f;
+    bool inside = true;
     int dom = 0;
-    float best = -1.0f;
+    float best = -1.0f, tau = 0.0f;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         if (m < M.n_in) {
-            ok = ok && x[m] <= 1.0f;
-            if (L[m] > best) {
-                best = L[m];
+            inside = inside && x[m] <= 1.0f;
+            const float t = __fmul_rn(M.mbar[m], L[m]);    // no contraction: the cell is an integer decision
+            tau = __fadd_rn(tau, t);
+            if (t > best) {
+                best = t;
                 dom = m;
             }
         }
     }
-    const float b = floorf((float)FCAT_MLP_CELLS * (log10f(tot) - M.cell_lo) / (M.cell_hi - M.cell_lo));
-    ok = ok && b >= 0.0f && b < (float)FCAT_MLP_CELLS;
-    if (!ok) return false;
-    return M.cell_ok[dom * FCAT_MLP_CELLS + (int)b] != 0;
+    const float b = floorf(__fdiv_rn(__fmul_rn((float)FCAT_MLP_CELLS, __fsub_rn(tau, M.cell_lo)),
+                                     __fsub_rn(M.cell_hi, M.cell_lo)));
+    if (!inside || !(b >= 0.0f && b < (float)FCAT_MLP_CELLS)) return -1;
+    return dom * FCAT_MLP_CELLS + (int)b;
+}
+
+__device__ __forceinline__ bool in_domain(const float (&L)[16], const float (&x)[16], const MlpTables &M)
+{
+    const int c = cell_of(L, x, M);
+    return c >= 0 && M.cell_ok[c] != 0;
 }
 
 // Spectral stage with the surrogate: L [n][M] in, group signals out.
@@ -255,12 +348,15 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         L[m] = (valid && m < T.M) ? io.L[r * T.M + m] : 0.0f;
-        x[m] = m < M.n_in ? L[m] * M.in_scale[m] : 0.0f;
+        x[m] = m < M.n_in ? __fmul_rn(L[m], M.in_scale[m]) : 0.0f;
         tot += L[m];
     }
     const bool hit = valid && tot > 0.0f;
-    const bool use = hit && (io.force_mlp || in_domain(L, x, tot, M));
-    if (__ballot(use) != 0) mlp_infer_wave(x, M, lds[wave].X, lds[wave].Hb, lds[wave].O);
+    const bool use = hit && (io.force_mlp || in_domain(L, x, M));
+    float o[16];
+#pragma unroll
+    for (int g = 0; g < 16; ++g) o[g] = 0.0f;
+    if (__ballot(use) != 0) mlp_infer_wave(x, M, lds[wave], o);
     if (io.counts && valid) {
         const uint64_t bu = __ballot(use), bh = __ballot(hit);
         if (lane == 0) {
@@ -279,7 +375,11 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
     for (int g = 0; g < T.G; ++g) {
         float prim;
         if (use) {
-            float z = M.out_scale[g] * lds[wave].O[lane * SO + g];
+            float og = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k == g) og = o[k];
+            float z = M.out_scale[g] * og;
 #pragma unroll
             for (int m = 0; m < 16; ++m)
                 if (m < T.M) z = fmaf(M.lin[g * T.M + m], L[m], z);
@@ -314,7 +414,7 @@ struct TrainLds {
 // Forward + backward of one 64-sample tile per workgroup (one wavefront).
 // Samples order[base + i], i < count; the loss is the mean over `count`
 // samples and n_out outputs of omega (s f - r)^2, with r the residual
-// target, s = out_scale and omega = min(1, Y_g / (1e-6 sum_g Y_g))^2.  Writes
+// target, s = out_scale and omega = min(1, Y_g / (1e-3 sum_g Y_g))^2.  Writes
 // the gradient partial of the tile to partial[blockIdx.x][P] and its loss
 // sum to loss_partial[blockIdx.x].
 __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, const float *__restrict__ Lin,
@@ -346,25 +446,35 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
         float t = 0.0f, om = 0.0f;
         if (valid && g < n_out) {
             const float y = Yin[(int64_t)g * n_all + s];
-            t = -logf(y / T.Wg[g]);
+            const float f = fminf(1.0f, y / (kMlpShareFloor * ysum));
+            if (f > 0.0f) {                    // y > 0: the target is finite
+                t = -logf(y / T.Wg[g]);
 #pragma unroll
-            for (int m = 0; m < 16; ++m)
-                if (m < n_in) t -= M.lin[g * n_in + m] * L[m];
-            const float f = fminf(1.0f, y / (1e-6f * ysum));
-            om = f * f;
+                for (int m = 0; m < 16; ++m)
+                    if (m < n_in) t -= M.lin[g * n_in + m] * L[m];
+                om = f * f;
+            }
         }
         S.Tg[lane * SO + g] = t;
         S.Wt[lane * SO + g] = om;
     }
+    {   // row = [x_hi (16) | x_lo (16)]; the transpose keeps x_hi for dW1
+        uint32_t hi[8], lo[8];
 #pragma unroll
-    for (int k = 0; k < 32; k += 2) {
-        const uint32_t lo = k < 16 ? bf16_rne(x[k]) : 0u;
-        const uint32_t hi = k + 1 < 16 ? bf16_rne(x[k + 1]) : 0u;
-        *reinterpret_cast<uint32_t *>(S.X + lane * SX + k) = lo | (hi << 16);
+        for (int k = 0; k < 8; ++k) split_bf16x2(x[2 * k], x[2 * k + 1], hi[k], lo[k]);
+        uint4 *row = reinterpret_cast<uint4 *>(S.X + lane * SX);
+        row[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        row[1] = make_uint4(hi[4], hi[5], hi[6], hi[7]);
+        row[2] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        row[3] = make_uint4(lo[4], lo[5], lo[6], lo[7]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            S.XT[(2 * k) * SH + lane] = (uint16_t)(hi[k] & 0xffffu);
+            S.XT[(2 * k + 1) * SH + lane] = (uint16_t)(hi[k] >> 16);
+        }
     }
-#pragma unroll
-    for (int m = 0; m < 16; ++m) S.XT[m * SH + lane] = (uint16_t)bf16_rne(x[m]);
     wave_sync_lds();
+    uint16_t *const Hlo = S.D1T;     // lo parts of H1, then of H2 (D1T is free until the backward pass)
 
     // ---- forward
     floatx4 Z1[4][4], Z2[4][4], acc[4][4];
@@ -372,9 +482,12 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
     for (int rt = 0; rt < 4; ++rt) {
         const bf16x8 a = lds_frag(S.X, SX, 16 * rt + r16, 8 * q);
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
+        for (int ct = 0; ct < 4; ++ct) {
             Z1[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1 + ct, lane),
                                                                  floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            Z1[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1lo + ct, lane),
+                                                                 Z1[rt][ct], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
@@ -384,10 +497,13 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 Z1[rt][ct][i] += b;
-                const uint16_t h = (uint16_t)bf16_rne(silu(Z1[rt][ct][i]));
+                const float hv = silu(Z1[rt][ct][i]);
+                const uint32_t hb = bf16_rne(hv);
+                const uint16_t h = (uint16_t)hb;
                 const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
                 S.H1[row * SH + col] = h;
                 S.H1T[col * SH + row] = h;
+                Hlo[row * SH + col] = (uint16_t)bf16_rne(hv - bf16_value(hb));
             }
     }
     wave_sync_lds();
@@ -400,11 +516,17 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
             const bf16x8 a = lds_frag(S.H1, SH, 16 * rt + r16, 32 * kb + 8 * q);
+            const bf16x8 al = lds_frag(Hlo, SH, 16 * rt + r16, 32 * kb + 8 * q);
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
+            for (int ct = 0; ct < 4; ++ct) {
+                const bf16x8 wh = frag_of(M.frag, kFragW2 + ct * 2 + kb, lane);
+                Z2[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wh, Z2[rt][ct], 0, 0, 0);
+                Z2[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, Z2[rt][ct], 0, 0, 0);
                 Z2[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, frag_of(M.frag, kFragW2 + ct * 2 + kb, lane), Z2[rt][ct], 0, 0, 0);
+                    a, frag_of(M.frag, kFragW2lo + ct * 2 + kb, lane), Z2[rt][ct], 0, 0, 0);
+            }
         }
+    wave_sync_lds();
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const float b = P[off.b2 + 16 * ct + r16];
@@ -413,10 +535,13 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 Z2[rt][ct][i] += b;
-                const uint16_t h = (uint16_t)bf16_rne(silu(Z2[rt][ct][i]));
+                const float hv = silu(Z2[rt][ct][i]);
+                const uint32_t hb = bf16_rne(hv);
+                const uint16_t h = (uint16_t)hb;
                 const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
                 S.H2[row * SH + col] = h;
                 S.H2T[col * SH + row] = h;
+                Hlo[row * SH + col] = (uint16_t)bf16_rne(hv - bf16_value(hb));
             }
     }
     wave_sync_lds();
@@ -425,10 +550,17 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
     for (int rt = 0; rt < 4; ++rt) {
         o3[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_frag(S.H2, SH, 16 * rt + r16, 32 * kb + 8 * q),
-                                                             frag_of(M.frag, kFragW3 + kb, lane), o3[rt], 0, 0, 0);
+        for (int kb = 0; kb < 2; ++kb) {
+            const bf16x8 a = lds_frag(S.H2, SH, 16 * rt + r16, 32 * kb + 8 * q);
+            const bf16x8 al = lds_frag(Hlo, SH, 16 * rt + r16, 32 * kb + 8 * q);
+            const bf16x8 wh = frag_of(M.frag, kFragW3 + kb, lane);
+            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wh, o3[rt], 0, 0, 0);
+            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, o3[rt], 0, 0, 0);
+            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW3lo + kb, lane), o3[rt], 0, 0,
+                                                             0);
+        }
     }
+    wave_sync_lds();
 
     // ---- output error dZ3 = 2 omega (s f - r) s / (count n_out)
     const float b3 = r16 < n_out ? P[off.b3 + r16] : 0.0f;
@@ -625,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float *__restr
 }
 
 // Held-out validation: per ray, the largest relative error over groups of
-// the predicted primary signal, with a floor of 1e-6 of the ray's total
+// the predicted primary signal, with a floor of 1e-3 of the ray's total
 // signal; its maximum and the sample count per cell.
 __global__ __launch_bounds__(kBlock) void k_mlp_validate(SpecTables T, MlpTables M, const float *__restrict__ Lin,
                                                          const float *__restrict__ Yin, int64_t n,
@@ -633,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(SpecTables T, MlpTables
                                                          int *__restrict__ cell_count)
 {
     __shared__ __align__(16) InferLds lds[kBlock / kWave];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = r < n;
     float L[16], x[16];
@@ -641,40 +773,148 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(SpecTables T, MlpTables
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         L[m] = (valid && m < T.M) ? Lin[r * T.M + m] : 0.0f;
-        x[m] = m < M.n_in ? L[m] * M.in_scale[m] : 0.0f;
+        x[m] = m < M.n_in ? __fmul_rn(L[m], M.in_scale[m]) : 0.0f;
         tot += L[m];
     }
-    mlp_infer_wave(x, M, lds[wave].X, lds[wave].Hb, lds[wave].O);
+    float o[16];
+    mlp_infer_wave(x, M, lds[wave], o);
     if (!(valid && tot > 0.0f)) return;
-    bool inside = true;
-    int dom = 0;
-    float best = -1.0f;
-#pragma unroll
-    for (int m = 0; m < 16; ++m)
-        if (m < M.n_in) {
-            inside = inside && x[m] <= 1.0f;
-            if (L[m] > best) {
-                best = L[m];
-                dom = m;
-            }
-        }
-    const float b = floorf((float)FCAT_MLP_CELLS * (log10f(tot) - M.cell_lo) / (M.cell_hi - M.cell_lo));
-    if (!inside || !(b >= 0.0f && b < (float)FCAT_MLP_CELLS)) return;
+    const int cell = cell_of(L, x, M);
+    if (cell < 0) return;
     float ysum = 0.0f;
     for (int g = 0; g < T.G; ++g) ysum += Yin[(int64_t)g * n + r];
     float err = 0.0f;
     for (int g = 0; g < T.G; ++g) {
-        float z = M.out_scale[g] * lds[wave].O[lane * SO + g];
+        float og = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (k == g) og = o[k];
+        float z = M.out_scale[g] * og;
 #pragma unroll
         for (int m = 0; m < 16; ++m)
             if (m < T.M) z = fmaf(M.lin[g * T.M + m], L[m], z);
         const float pred = T.Wg[g] * expf(-z);
         const float ref = Yin[(int64_t)g * n + r];
-        err = fmaxf(err, fabsf(pred - ref) / fmaxf(ref, 1e-6f * ysum));
+        err = fmaxf(err, fabsf(pred - ref) / fmaxf(ref, kMlpShareFloor * ysum));
     }
-    const int cell = dom * FCAT_MLP_CELLS + (int)b;
     atomicMax(cell_err_bits + cell, __float_as_uint(err));   // non-negative floats order as their bits
     atomicAdd(cell_count + cell, 1);
+}
+
+// mbar[m] = sum_g W_g lin[g][m] / sum_g W_g, the spectrum-weighted mean
+// attenuation of material m (zero beyond n_mat).
+__global__ void k_mlp_mbar(SpecTables T, const float *__restrict__ lin, float *__restrict__ mbar)
+{
+    const int m = threadIdx.x;
+    if (m >= FCAT_MLP_MAX_IO) return;
+    double a = 0.0, b = 0.0;
+    if (m < T.M)
+        for (int g = 0; g < T.G; ++g) {
+            a += (double)T.Wg[g] * (double)lin[g * T.M + m];
+            b += (double)T.Wg[g];
+        }
+    mbar[m] = m < T.M ? (float)(a / b) : 0.0f;
+}
+
+// Set-up statistics of a training set, pass 1: a fixed grid of kStatBlocks
+// blocks strides over the samples; block b writes partial[b][kStatStride]:
+// max_s L[s][m], max_s sum_m mbar_m L[s][m], and per group the sums of
+// omega r^2 and omega (target and weight as in k_mlp_grad).
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) v = fmaxf(v, __shfl_xor(v, sh));
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_stats(SpecTables T, const float *__restrict__ lin,
+                                                      const float *__restrict__ mbar, const float *__restrict__ Lin,
+                                                      const float *__restrict__ Yin, int64_t n,
+                                                      float *__restrict__ partial)
+{
+    __shared__ float red[kBlock / kWave][kStatStride];
+    float mx[16], a[16], b[16], tmax = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) mx[k] = a[k] = b[k] = 0.0f;
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n; s += (int64_t)kStatBlocks * kBlock) {
+        float L[16], tau = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            L[m] = m < T.M ? Lin[s * T.M + m] : 0.0f;
+            mx[m] = fmaxf(mx[m], L[m]);
+            if (m < T.M) tau = fmaf(mbar[m], L[m], tau);
+        }
+        tmax = fmaxf(tmax, tau);
+        float ysum = 0.0f;
+        for (int g = 0; g < T.G; ++g) ysum += Yin[(int64_t)g * n + s];
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+            if (g < T.G) {
+                const float y = Yin[(int64_t)g * n + s];
+                const float f = fminf(1.0f, y / (kMlpShareFloor * ysum));
+                if (f > 0.0f) {
+                    float r = -logf(y / T.Wg[g]);
+#pragma unroll
+                    for (int m = 0; m < 16; ++m)
+                        if (m < T.M) r -= lin[g * T.M + m] * L[m];
+                    a[g] = fmaf(f * f, r * r, a[g]);
+                    b[g] += f * f;
+                }
+            }
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const float vm = wave_max(mx[k]), va = wave_sum(a[k]), vb = wave_sum(b[k]);
+        if (lane == 0) {
+            red[wave][k] = vm;
+            red[wave][17 + k] = va;
+            red[wave][33 + k] = vb;
+        }
+    }
+    const float vt = wave_max(tmax);
+    if (lane == 0) red[wave][16] = vt;
+    __syncthreads();
+    if (threadIdx.x < 49) {
+        const int k = threadIdx.x;
+        float v = red[0][k];
+        for (int w = 1; w < kBlock / kWave; ++w) v = (k <= 16) ? fmaxf(v, red[w][k]) : v + red[w][k];
+        partial[(int64_t)blockIdx.x * kStatStride + k] = v;
+    }
+}
+
+// Pass 2: reduce the block records in a fixed order (deterministic).
+__global__ void k_mlp_stats_final(const float *__restrict__ partial, int M, int G, float *__restrict__ in_scale,
+                                  float *__restrict__ out_scale, float *__restrict__ tau_max)
+{
+    const int k = threadIdx.x;
+    if (k < M) {
+        float v = 0.0f;
+        for (int b = 0; b < kStatBlocks; ++b) v = fmaxf(v, partial[(int64_t)b * kStatStride + k]);
+        in_scale[k] = 1.0f / fmaxf(v, 1e-6f);
+    }
+    if (k == 16) {
+        float v = 0.0f;
+        for (int b = 0; b < kStatBlocks; ++b) v = fmaxf(v, partial[(int64_t)b * kStatStride + 16]);
+        tau_max[0] = v;
+    }
+    if (k >= 32 && k - 32 < G) {
+        const int g = k - 32;
+        double sa = 0.0, sb = 0.0;
+        for (int b = 0; b < kStatBlocks; ++b) {
+            sa += partial[(int64_t)b * kStatStride + 17 + g];
+            sb += partial[(int64_t)b * kStatStride + 33 + g];
+        }
+        out_scale[g] = fmaxf(1e-3f, (float)sqrt(sa / fmax(sb, 1e-30)));
+    }
 }
 
 __global__ void k_mlp_cells(const unsigned *__restrict__ err_bits, const int *__restrict__ count, int ncell,
@@ -701,6 +941,24 @@ hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag
 hipError_t launch_mlp_linear(const float *mu, const SpecTables &t, float *lin, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_mlp_linear, dim3((t.G * t.M + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, mu, t, lin);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_mbar(const SpecTables &t, const float *lin, float *mbar, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_mlp_mbar, dim3(1), dim3(64), 0, stream, t, lin, mbar);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *mbar, const float *L, const float *Y,
+                            int64_t n, float *partial, float *in_scale, float *out_scale, float *tau_max,
+                            hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_mlp_stats, dim3(kStatBlocks), dim3(kBlock), 0, stream, t, lin, mbar, L, Y, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_stats_final, dim3(1), dim3(64), 0, stream, partial, t.M, t.G, in_scale, out_scale,
+                       tau_max);
     return hipGetLastError();
 }
 

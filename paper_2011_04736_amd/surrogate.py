@@ -2,11 +2,12 @@
 
 Every computation runs in libfcat.so: path lengths of the training rays
 (``fcat_pathlengths``), their exact primary group signals (``fcat_spectral``),
-the linear term (``fcat_mlp_linear_term``), forward/backward/Adam
+the linear term (``fcat_mlp_linear_term``), the input/output scales and the
+optical-depth range of the cells (``fcat_mlp_setup``), forward/backward/Adam
 (``fcat_mlp_train_epoch``) and the held-out validation that decides where
 the network may replace the exact sum (``fcat_mlp_validate``).  This module
 only draws the seeded samples and initial weights (inputs to those kernels),
-slices tensors and loops over epochs.
+slices tensors, loops over epochs and sets the learning-rate schedule.
 """
 from __future__ import annotations
 
@@ -17,8 +18,8 @@ from typing import Optional
 
 import numpy as np
 
-from . import (MlpTrain, Problem, Surrogate, fcat_mlp_linear_term, fcat_mlp_param_count, fcat_mlp_train_epoch,
-               fcat_mlp_validate, fcat_pathlengths, fcat_spectral)
+from . import (MlpTrain, Problem, Surrogate, fcat_mlp_linear_term, fcat_mlp_param_count, fcat_mlp_setup,
+               fcat_mlp_train_epoch, fcat_mlp_validate, fcat_pathlengths, fcat_spectral)
 
 HIDDEN = 64
 
@@ -63,22 +64,6 @@ def sample_rays(pb: Problem, n_mat: int, n_samples: int, angles, seed: int, chun
     return torch.as_tensor(L, device=pb.phantom.labels.device)
 
 
-def residual_scale(sp, L, Y, lin) -> np.ndarray:
-    """Per-group output scale: the loss-weighted RMS of the training residuals
-    r_g = -ln(Y_g / W_g) - sum_m lin[g][m] L_m (set-up statistics of the data)."""
-    phi = sp.phi.cpu().numpy().astype(np.float64)
-    eta = sp.eta.cpu().numpy().astype(np.float64)
-    G = int(sp.n_groups)
-    E = phi.size
-    gob = np.asarray(sp.group_of_bin) if sp.group_of_bin is not None else np.arange(E) * G // E
-    W = np.array([(phi * eta)[gob == g].sum() for g in range(G)])
-    Y = np.asarray(Y, np.float64)
-    r = -np.log(np.maximum(Y.T, 1e-300) / W[None, :]) - np.asarray(L, np.float64) @ np.asarray(lin, np.float64).T
-    om = np.minimum(1.0, Y.T / (1e-6 * Y.sum(0)[:, None])) ** 2
-    s = np.sqrt((om * r * r).sum(0) / np.maximum(om.sum(0), 1e-30))
-    return np.maximum(s, 1e-3).astype(np.float32)
-
-
 @dataclass
 class TrainReport:
     n_train: int
@@ -89,10 +74,11 @@ class TrainReport:
     epoch_loss: list = field(default_factory=list)
     cell_err: Optional[np.ndarray] = None
     cell_ok: Optional[np.ndarray] = None
+    cell_count: Optional[np.ndarray] = None
     holdout_in_ok_cells: float = 0.0
 
 
-def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.1, epochs: int = 40,
+def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.1, epochs: int = 120,
                     batch: int = 4096, lr: float = 2e-3, lr_final: float = 2e-5, threshold: float = 1e-3,
                     min_count: int = 16, angles=None, seed: int = 47365, verbose: bool = False):
     """Train the surrogate on rays of ``pb`` and validate it; returns (Surrogate, TrainReport)."""
@@ -112,17 +98,11 @@ def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.
     Lt, Lh = L[:n_train].contiguous(), L[n_train:].contiguous()
     Yt, Yh = Y[:, :n_train].contiguous(), Y[:, n_train:].contiguous()
 
-    Ltr = Lt.cpu().numpy()
-    lmax = np.maximum(Ltr.max(0), 1e-6)
-    tot = Ltr.sum(1)
-    cell_lo = float(np.floor(np.log10(tot.min()) * 100) / 100)
-    cell_hi = float(np.ceil(np.log10(tot.max()) * 100) / 100 + 0.01)
     lin = fcat_mlp_linear_term(sp)
-    out_scale = residual_scale(sp, Ltr, Yt.cpu().numpy(), lin.cpu().numpy())
+    in_scale, out_scale, tau_max = fcat_mlp_setup(sp, lin, Lt, Yt)
     params = torch.as_tensor(init_params(M, G, seed), device=dev)
-    sur = Surrogate(params=params, in_scale=torch.as_tensor((1.0 / lmax).astype(np.float32), device=dev),
-                    out_scale=torch.as_tensor(out_scale, device=dev), lin=lin, cell_ok=None, cell_lo=cell_lo,
-                    cell_hi=cell_hi)
+    sur = Surrogate(params=params, in_scale=in_scale, out_scale=out_scale, lin=lin, cell_ok=None,
+                    cell_lo=0.0, cell_hi=float(tau_max.item()) * (1.0 + 1e-6))
     train = MlpTrain(params=params, adam_m=torch.zeros_like(params), adam_v=torch.zeros_like(params), lr=lr)
     nb = (n_train + batch - 1) // batch
     batch_loss = torch.empty(nb, dtype=torch.float32, device=dev)
@@ -139,14 +119,10 @@ def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.
             print(f"epoch {ep}: lr {train.lr:.2e} loss {report.epoch_loss[-1]:.3e}", flush=True)
     torch.cuda.synchronize()
     report.seconds = time.perf_counter() - t0
-    cell_err, cell_ok = fcat_mlp_validate(sur, sp, Lh, Yh, threshold=threshold, min_count=min_count)
+    cell_err, cell_ok, cell_count = fcat_mlp_validate(sur, sp, Lh, Yh, threshold=threshold, min_count=min_count)
     report.cell_err = cell_err.cpu().numpy()
     report.cell_ok = cell_ok.cpu().numpy()
+    report.cell_count = cell_count.cpu().numpy()
     # share of held-out rays that fall in validated cells
-    Lhn = Lh.cpu().numpy()
-    toth = Lhn.sum(1)
-    b = np.floor(16 * (np.log10(toth) - cell_lo) / (cell_hi - cell_lo))
-    inside = (b >= 0) & (b < 16) & np.all(Lhn * (1.0 / lmax) <= 1.0, axis=1)
-    cell = np.argmax(Lhn, axis=1) * 16 + np.clip(b, 0, 15).astype(np.int64)
-    report.holdout_in_ok_cells = float(np.mean(inside & (report.cell_ok[cell] == 1)))
+    report.holdout_in_ok_cells = float(report.cell_count[report.cell_ok == 1].sum()) / max(n_hold, 1)
     return sur, report

@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "Geometry", "Phantom", "Spectral", "Scatter", "Psf", "Config",
     "make_config", "config_seed", "random_phantom", "material_tables",
-    "kramers_spectrum", "detector_response", "gaussian_psfs",
+    "kramers_spectrum", "detector_response", "gaussian_psfs", "refine_spectral",
 ]
 
 SEED_BASE = 4736 * 10
@@ -248,6 +248,26 @@ def detector_response(rng: np.random.Generator, energies: np.ndarray, e_ref: flo
 def contiguous_groups(n_energy: int, n_groups: int) -> np.ndarray:
     """group_of_bin[e] = floor(e*G/E)."""
     return (np.arange(n_energy, dtype=np.int64) * n_groups // n_energy).astype(np.int32)
+
+
+def refine_spectral(spec: "Spectral", factor: int) -> "Spectral":
+    """The same source, attenuation and response on ``factor`` times finer bins.
+
+    Each (uniform) bin is cut into ``factor`` equal sub-bins; mu and eta are
+    interpolated linearly at the sub-bin centres (held constant beyond the
+    end centres), phi likewise and renormalised to sum 1, and the groups
+    stay contiguous over the new bins (so each group keeps its energy range).
+    """
+    e = np.asarray(spec.energies, np.float64)
+    step = (e[-1] - e[0]) / (e.size - 1)
+    sub = (np.arange(factor) + 0.5) / factor - 0.5
+    ef = (e[:, None] + sub[None, :] * step).ravel()
+    mu = np.stack([np.interp(ef, e, np.asarray(row, np.float64)) for row in spec.mu]).astype(np.float32)
+    phi = np.interp(ef, e, np.asarray(spec.phi, np.float64))
+    eta = np.interp(ef, e, np.asarray(spec.eta, np.float64)).astype(np.float32)
+    return Spectral(energies=ef, mu=mu, phi=(phi / phi.sum()).astype(np.float32), eta=eta,
+                    n_groups=spec.n_groups, group_of_bin=contiguous_groups(ef.size, spec.n_groups),
+                    flood=spec.flood, energy_unit=spec.energy_unit, material_names=spec.material_names)
 
 
 def gaussian_psfs(rng: np.random.Generator, n_groups: int, k: int,

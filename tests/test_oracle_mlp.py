@@ -68,8 +68,11 @@ def test_loss_weights():
     w = mlp.loss_weights(Y)
     tot = Y.sum(0)
     assert w.shape == (2, 3)                                   # [n][G]
-    np.testing.assert_allclose(w[0], [1.0, min(1, 1e-9 / (1e-6 * tot[0])) ** 2, 1.0])
-    np.testing.assert_allclose(w[1], [1.0, min(1, 2e-10 / (1e-6 * tot[1])) ** 2, 0.0])
+    np.testing.assert_allclose(w[0], [1.0, min(1, 1e-9 / (1e-3 * tot[0])) ** 2, 1.0])
+    np.testing.assert_allclose(w[1], [1.0, min(1, 2e-10 / (1e-3 * tot[1])) ** 2, 0.0])
+    # a group at exactly the floor share weighs 1, at a tenth of it 1/100
+    Y2 = np.array([[1.0, 1.0], [1e-3 / (1 - 1e-3), 1e-4 / (1 - 1e-4)]])
+    np.testing.assert_allclose(mlp.loss_weights(Y2)[:, 1], [1.0, 0.01], rtol=1e-9)
 
 
 def test_bf16_emulation_is_close_to_fp64():
@@ -79,7 +82,15 @@ def test_bf16_emulation_is_close_to_fp64():
     X = rng.uniform(0, 1, size=(64, n_in))
     o64, _ = mlp.forward(p, X, n_in, n_out)
     o16, _ = mlp.forward(p, X, n_in, n_out, bf16=True)
-    assert 0 < np.abs(o16 - o64).max() <= 0.05 * np.abs(o64).max()
+    # three-term split: each product is off by at most ~3 * 2^-18 of |a b|
+    assert 0 < np.abs(o16 - o64).max() <= 1e-4 * np.abs(o64).max()
+    # while BF16 operands alone (no lo terms) are off by ~2^-9
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(p, n_in, n_out)
+    r = lambda a: mlp._b(a, True)
+    h1 = mlp.silu(r(X) @ r(W1).T + b1)
+    h2 = mlp.silu(r(h1) @ r(W2).T + b2)
+    o_plain = r(h2) @ r(W3).T + b3
+    assert np.abs(o_plain - o64).max() > 10 * np.abs(o16 - o64).max()
 
 
 def test_adam_first_step_closed_form():
@@ -119,7 +130,42 @@ def test_linear_term_and_residuals():
 
 
 def test_cell_index():
-    L = np.array([[1.0, 5.0, 0.0], [10.0, 0.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 1e5]])
-    c = mlp.cell_index(L, 0.0, 2.0)
-    # sum 6 -> log10 0.778 -> bin 6, dominant 1; sum 10 -> bin 8, dominant 0; miss; out of range
-    np.testing.assert_array_equal(c, [1 * 16 + 6, 0 * 16 + 8, -1, -1])
+    mbar = np.array([0.001, 0.02, 0.05])
+    L = np.array([[100.0, 6.0, 0.0], [10.0, 0.0, 8.0], [0.0, 0.0, 0.0], [0.0, 0.0, 100.0], [50.0, 10.0, 1.0]])
+    c = mlp.cell_index(L, mbar, 0.0, 2.0)
+    # tau 0.22 (longest in air, but water-dominant by depth) -> bin 1; tau 0.41 -> bin 3, dominant 2; miss; tau 5 out of range;
+    # tau 0.05 + 0.2 + 0.05 = 0.3 -> bin 2, dominant 1
+    np.testing.assert_array_equal(c, [1 * 16 + 1, 2 * 16 + 3, -1, -1, 1 * 16 + 2])
+    # the input-range test sends rays beyond the training maxima to the exact sum
+    c2 = mlp.cell_index(L, mbar, 0.0, 2.0, in_scale=np.array([1 / 60.0, 1 / 20.0, 1 / 20.0]))
+    np.testing.assert_array_equal(c2, [-1, 2 * 16 + 3, -1, -1, 1 * 16 + 2])
+
+
+def test_mean_attenuation_and_setup_stats():
+    rng = np.random.default_rng(5)
+    M, E, G = 3, 12, 3
+    mu = rng.uniform(0.01, 0.5, size=(M, E))
+    phi, eta = rng.uniform(0.1, 1.0, E), rng.uniform(0.5, 1.0, E)
+    grp = np.arange(E) * G // E
+    W = mlp.group_weights(phi, eta, grp, G)
+    lin = mlp.linear_term(mu, phi, eta, grp, G)
+    w = phi * eta
+    np.testing.assert_allclose(mlp.mean_attenuation(W, lin), (mu * w).sum(1) / w.sum(), rtol=1e-12)
+    L = rng.uniform(0, 20, size=(500, M))
+    L[:, 2] *= 0.5
+    Y = np.stack([(w[grp == g][None, :] * np.exp(-L @ mu[:, grp == g])).sum(1) for g in range(G)])
+    i_s, o_s, tmax = mlp.setup_stats(L, Y, W, lin)
+    np.testing.assert_allclose(i_s, 1.0 / L.max(0), rtol=1e-12)
+    assert tmax == pytest.approx((L @ ((mu * w).sum(1) / w.sum())).max(), rel=1e-12)
+    r = mlp.residual_targets(L, Y, W, lin)
+    wt = mlp.loss_weights(Y)
+    np.testing.assert_allclose(o_s, np.sqrt((wt * r * r).sum(0) / wt.sum(0)), rtol=1e-12)
+
+
+def test_validation_errors():
+    Y = np.array([[1.0, 2.0], [1e-6, 1.0]])          # [G][n]
+    P = Y.copy()
+    P[1, 0] *= 2.0                                     # +100% on a group below the floor share
+    P[0, 1] *= 1.0 + 1e-4
+    e = mlp.validation_errors(P, Y)
+    np.testing.assert_allclose(e, [1e-6 / (1e-3 * (1.0 + 1e-6)), 1e-4], rtol=1e-9)
