@@ -57,6 +57,16 @@ __device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t &hi, uin
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Orders the LDS accesses of one wavefront around this point (a compiler and
+// memory fence at wavefront scope): needed where a wavefront reuses its own
+// LDS block under another type or layout.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Hardware hands consecutive workgroups to the 8 XCDs in turn.  Remap so that
 // each XCD (and its L2) works through one contiguous range of rays.  The
 // grid is padded to a multiple of kXcds so the map is a bijection.
@@ -143,27 +153,45 @@ __device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double 
     return true;
 }
 
-// Compensated add of x to material m (compare-select over the padded
-// material count, so the register arrays are never indexed dynamically).
-// Labels outside 0..MP-1 match nothing and add nothing.
+// Per-lane material accumulators in LDS.  A run of path length is charged
+// to its material only when the label changes, but the lanes of a wavefront
+// change label at different steps, so a register file indexed by
+// compare-select (two selects per material and value) would cost the whole
+// wavefront tens of instructions on almost every step.  LDS takes the
+// material as an index instead.  Layout per wavefront: [2][MP][64] floats
+// (sum, then Kahan compensation), lane-contiguous, so accesses are free of
+// bank conflicts.
 template <int MP>
-__device__ __forceinline__ void kahan_add(float (&L)[MP], float (&C)[MP], int m, float x)
-{
-    float l = 0.0f, c = 0.0f;
+struct MatAcc {
+    float *base;    // this lane's slot: wave block + lane
+
+    __device__ __forceinline__ void clear()
+    {
 #pragma unroll
-    for (int k = 0; k < MP; ++k) {
-        l = (k == m) ? L[k] : l;
-        c = (k == m) ? C[k] : c;
+        for (int m = 0; m < 2 * MP; ++m) base[m * kWave] = 0.0f;
     }
-    const float y = x - c;
-    const float t = l + y;
-    c = (t - l) - y;
+    // Compensated add of x to material m; labels outside 0..MP-1 add nothing.
+    __device__ __forceinline__ void add(int m, float x)
+    {
+        if (static_cast<unsigned>(m) >= static_cast<unsigned>(MP)) return;
+        float *ps = base + m * kWave;
+        float *pc = base + (MP + m) * kWave;
+        const float l = *ps, c = *pc;
+        const float y = x - c;
+        const float t = l + y;
+        *pc = (t - l) - y;
+        *ps = t;
+    }
+    __device__ __forceinline__ void read(float (&L)[MP]) const
+    {
 #pragma unroll
-    for (int k = 0; k < MP; ++k) {
-        L[k] = (k == m) ? t : L[k];
-        C[k] = (k == m) ? c : C[k];
+        for (int m = 0; m < MP; ++m) L[m] = base[m * kWave];
     }
-}
+};
+
+// LDS floats per wavefront of MatAcc<MP>.
+template <int MP>
+constexpr int mat_acc_floats() { return 2 * MP * kWave; }
 
 // Number of crossings of one axis at or before distance T: the k with
 // t0 + (k-1) dt <= T < t0 + k dt, evaluated with the same rounded formula
@@ -187,18 +215,20 @@ __device__ __forceinline__ float crossings_before(float T, float t0, float dt, f
 // individual voxel planes.  Crossing k + 1 of an axis lies at t0 + k dt (one
 // rounding from its exact value) for both levels; path length is charged to
 // a material only when the label changes, with compensated summation.
+//
+// acc_wave is this wavefront's MatAcc block in LDS; L receives the sums.
 template <int MP>
 __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const TraceGeom &G,
                                              const int8_t *__restrict__ labels_bm,
-                                             const int8_t *__restrict__ bricks, float (&L)[MP])
+                                             const int8_t *__restrict__ bricks, float *acc_wave, float (&L)[MP])
 {
-    float C[MP];
+    MatAcc<MP> acc{acc_wave + (threadIdx.x & (kWave - 1))};
+    acc.clear();
+    if (!hit) {
 #pragma unroll
-    for (int m = 0; m < MP; ++m) {
-        L[m] = 0.0f;
-        C[m] = 0.0f;
+        for (int m = 0; m < MP; ++m) L[m] = 0.0f;
+        return;
     }
-    if (!hit) return;
     const float t_end = r.t_end;
     const int nbx = G.nb[0], nby = G.nb[1];
     const int last_brick = G.nb[0] * G.nb[1] * G.nb[2] - 1;
@@ -223,7 +253,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
         const float T_out = last ? t_end : tco;
         if (bl >= 0) {
             if (bl != cur) {
-                kahan_add<MP>(L, C, cur, T_in - run);
+                acc.add(cur, T_in - run);
                 cur = bl;
                 run = T_in;
             }
@@ -269,7 +299,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             int labn;
             advance(tn, labn);
             if (lab != cur) {
-                kahan_add<MP>(L, C, cur, T_in - run);
+                acc.add(cur, T_in - run);
                 cur = lab;
                 run = T_in;
             }
@@ -279,7 +309,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                 int lab2;
                 advance(tn2, lab2);
                 if (labn != cur) {
-                    kahan_add<MP>(L, C, cur, tn - run);
+                    acc.add(cur, tn - run);
                     cur = labn;
                     run = tn;
                 }
@@ -307,7 +337,8 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             bl = bricks[min(max(blin, 0), last_brick)];
         }
     }
-    kahan_add<MP>(L, C, cur, t_end - run);
+    acc.add(cur, t_end - run);
+    acc.read(L);
 }
 
 // sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3)

@@ -16,6 +16,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
                                                          int n_ang, int waves_per_row, int nblk_pad,
                                                          float *__restrict__ Y, float *__restrict__ out)
 {
+    __shared__ float acc_all[(kBlock / kWave) * mat_acc_floats<MP>()];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
     float L[MP];
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
-    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, L);
+    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, acc_all + wave * mat_acc_floats<MP>(), L);
     const bool any_hit = __ballot(hit) != 0;
     if (!valid) return;
 
@@ -58,6 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_pathlengths(TraceGeom G, const int8_
                                                         int n_mat, int a0, int n_ang, int waves_per_row,
                                                         int nblk_pad, float *__restrict__ Lout)
 {
+    __shared__ float acc_all[(kBlock / kWave) * mat_acc_floats<MP>()];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
@@ -67,13 +69,14 @@ __global__ __launch_bounds__(kBlock) void k_pathlengths(TraceGeom G, const int8_
     const int iu = (gw - row * waves_per_row) * kWave + lane;
     const int al = row / G.nv;
     const int iv = row - al * G.nv;
-    if (iu >= G.nu) return;
+    const bool valid = iu < G.nu;
     double st, ct;
     sincos(angle_of(G, a0 + al), &st, &ct);
     float L[MP];
     Ray r{};
-    const bool hit = setup_ray(G, ct, st, iv, iu, r);
-    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, L);
+    const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
+    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, acc_all + wave * mat_acc_floats<MP>(), L);
+    if (!valid) return;
     float *dst = Lout + (((int64_t)al * G.nv + iv) * G.nu + iu) * n_mat;
 #pragma unroll
     for (int m = 0; m < MP; ++m)

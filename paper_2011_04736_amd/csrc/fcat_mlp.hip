@@ -91,13 +91,6 @@ __device__ __forceinline__ float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Per-wavefront LDS of the forward pass.  X holds the inputs of the 64 rays,
 // row r = [x_hi (16) | x_lo (16)]; the outputs of ray r later reuse row r
 // (only that ray's tile has read it by then).  Hh/Hl hold the hi/lo parts of

@@ -99,7 +99,12 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
                                                                int n_ang, int waves_per_row, int nblk_pad,
                                                                float *__restrict__ Y, float *__restrict__ out)
 {
-    __shared__ __align__(16) uint16_t lds_all[(kBlock / kWave) * kWave * split_row_stride<NKB>()];
+    // per wavefront: the traversal's material accumulators, then (after the
+    // walk, same wavefront only) the rows of the split contraction
+    constexpr int kRowBytes = kWave * split_row_stride<NKB>() * 2;
+    constexpr int kAccBytes = mat_acc_floats<MP>() * 4;
+    constexpr int kWaveBytes = kRowBytes > kAccBytes ? kRowBytes : kAccBytes;
+    __shared__ __align__(16) uint8_t lds_raw[(kBlock / kWave) * kWaveBytes];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
@@ -117,8 +122,10 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
     float L[MP];
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
-    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, L);
+    uint8_t *lds_wave = lds_raw + wave * kWaveBytes;
+    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, reinterpret_cast<float *>(lds_wave), L);
     const bool any_hit = __ballot(hit) != 0;
+    wave_sync_lds();
 
     const int64_t plane = (int64_t)G.nu * G.nv;
     const int64_t pix = (int64_t)iv * G.nu + min(iu, G.nu - 1);
@@ -134,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
         }
     };
     if (any_hit) {
-        split_group_sums<MP, NKB>(L, T.M, T.G, S, lds_all + wave * kWave * split_row_stride<NKB>(), emit);
+        split_group_sums<MP, NKB>(L, T.M, T.G, S, reinterpret_cast<uint16_t *>(lds_wave), emit);
     } else {
         for (int g = 0; g < T.G; ++g) emit(g, T.Wg[g]);
     }
