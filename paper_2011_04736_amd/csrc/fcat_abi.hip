@@ -156,7 +156,7 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, afrag, wtile, frag, mbar, bricks, Y, Lbuf, fixed;
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, Y, Lbuf, fixed;
     size_t per_angle;    // bytes of per-angle chunk buffers (group signals, path lengths)
     size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
 };
@@ -175,7 +175,7 @@ void split_host(const SpecTables &t, SplitTables &sp)
 }
 
 Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size_t nbricks = 0,
-              const SplitTables *sp = nullptr, bool surrogate = false)
+              const SplitTables *sp = nullptr, bool surrogate = false, int psf_split_k = 0)
 {
     Layout L{};
     size_t o = 0;
@@ -193,6 +193,8 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (sp) o += align_up((size_t)sp->T * sp->nkb * kWave * 16);
     L.wtile = o;
     if (sp) o += align_up((size_t)sp->T * 16 * sizeof(float));
+    L.pfrag = o;
+    if (psf_split_k > 0) o += align_up(psf_split_frag_count(t.G, psf_split_k) * 16);
     L.frag = o;
     if (surrogate) o += align_up((size_t)kMlpFrags * kWave * 16);
     L.mbar = o;
@@ -415,6 +417,12 @@ const char *fcat_last_error(void) { return g_last_error.c_str(); }
 
 int fcat_version(void) { return FCAT_VERSION; }
 
+// k of the matrix-core optical spread in the split form, or 0 where the FP32 one runs.
+static int psf_split_k(const fcat_psf_t *psf, fcat_mode mode)
+{
+    return (psf && mode == FCAT_MODE_SPLIT_BF16 && psf->k <= kPsfSplitMaxK) ? psf->k : 0;
+}
+
 size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
                                     const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
                                     const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk)
@@ -427,7 +435,7 @@ size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_
     SplitTables sp{};
     split_host(t, sp);
     Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), mode == FCAT_MODE_SPLIT_BF16 ? &sp : nullptr,
-                      mode == FCAT_MODE_SURROGATE);
+                      mode == FCAT_MODE_SURROGATE, psf_split_k(psf, mode));
     int chunk = angles_per_chunk > 0 ? angles_per_chunk : default_chunk(L, geometry->n_angles);
     if (chunk > geometry->n_angles) chunk = geometry->n_angles;
     return L.fixed + (size_t)chunk * L.per_angle;
@@ -453,7 +461,8 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     if (sur && (s = check_surrogate(surrogate, t, true))) return s;
     SplitTables sp{};
     split_host(t, sp);
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), split ? &sp : nullptr, sur);
+    const int pk = psf_split_k(psf, mode);
+    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), split ? &sp : nullptr, sur, pk);
     const size_t need = L.fixed + L.per_angle;  // at least one angle per chunk
     if ((s = check_workspace(workspace, workspace_bytes, need))) return s;
     if ((s = check_pending())) return s;
@@ -461,6 +470,12 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
 
     if ((s = prep_tables(spectral, scatter ? scatter->s_bin : nullptr, t, L, workspace, stream))) return s;
     if (split && (s = prep_split(spectral, t, sp, L, workspace, stream))) return s;
+    uint4 *pfrag = at<uint4>(workspace, L.pfrag);
+    if (pk) {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        hipError_t e0 = launch_prep_psf_split(psf->kernels, t.G, pk, pfrag, stream);
+        if (e0 != hipSuccess) return device_fail(e0, "prep_psf_split");
+    }
     MlpTables mt{};
     if (sur && (s = prep_mlp(surrogate, surrogate->params, t, L, workspace, stream, mt))) return s;
     TraceGeom G = make_geom(geometry, phantom);
@@ -521,8 +536,10 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
         if (psf) {
             {
                 StageTimer tm(FCAT_STAGE_PSF, stream);
-                e = launch_psf(Y, n, t.G, geometry->nv, geometry->nu, psf->kernels, psf->k, out + a0 * plane,
-                               stream);
+                e = pk ? launch_psf_split(Y, n, t.G, geometry->nv, geometry->nu, pk, pfrag, out + a0 * plane,
+                                          stream)
+                       : launch_psf(Y, n, t.G, geometry->nv, geometry->nu, psf->kernels, psf->k, out + a0 * plane,
+                                    stream);
             }
             if (e != hipSuccess) return device_fail(e, "psf");
         }

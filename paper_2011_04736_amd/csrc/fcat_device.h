@@ -82,10 +82,11 @@ __device__ __forceinline__ int xcd_block(int nblk_padded)
 struct Ray {
     float t_end;        // exit distance
     float t0[3];        // first voxel-plane crossing per axis (inf if parallel)
-    float dt[3];        // distance between voxel-plane crossings
+    float dt[3];        // distance between voxel-plane crossings (0 if parallel)
     float inv_dt[3];    // 1 / dt (0 if parallel)
     float tc0[3];       // first brick-plane crossing per axis (inf if parallel)
-    float dtc[3];       // distance between brick-plane crossings
+    float dtc[3];       // distance between brick-plane crossings (0 if parallel, so that
+                        // k * dtc + tc0 stays inf without a test)
     int i0[3];          // entry voxel
     int sgn[3];         // direction of travel per axis: +1, -1, or 0 if parallel
 };
@@ -274,7 +275,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                     ia = min(max(r.i0[a] + r.sgn[a] * (int)kk, b0), b0 + kBrickEdge - 1);
                 }
                 k[a] = (float)(r.sgn[a] * (ia - r.i0[a]));
-                t[a] = r.sgn[a] ? fmaf(k[a], r.dt[a], r.t0[a]) : INFINITY;
+                t[a] = fmaf(k[a], r.dt[a], r.t0[a]);
                 loc += (ia - b0) * lstride[a];
             }
             const int8_t *brick = labels_bm + (int64_t)min(max(blin, 0), last_brick) * kBrickVox;
@@ -290,9 +291,9 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                 k[0] += bx ? 1.0f : 0.0f;
                 k[1] += by ? 1.0f : 0.0f;
                 k[2] += bz ? 1.0f : 0.0f;
-                t[0] = r.sgn[0] ? fmaf(k[0], r.dt[0], r.t0[0]) : INFINITY;
-                t[1] = r.sgn[1] ? fmaf(k[1], r.dt[1], r.t0[1]) : INFINITY;
-                t[2] = r.sgn[2] ? fmaf(k[2], r.dt[2], r.t0[2]) : INFINITY;
+                t[0] = fmaf(k[0], r.dt[0], r.t0[0]);      // parallel axis: 0 * 0 + inf
+                t[1] = fmaf(k[1], r.dt[1], r.t0[1]);
+                t[2] = fmaf(k[2], r.dt[2], r.t0[2]);
                 labn = brick[min(max(loc, 0), kBrickVox - 1)];
             };
             float tn;
@@ -330,9 +331,9 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             kc[0] += bx ? 1.0f : 0.0f;
             kc[1] += by ? 1.0f : 0.0f;
             kc[2] += bz ? 1.0f : 0.0f;
-            tc[0] = r.sgn[0] ? fmaf(kc[0], r.dtc[0], r.tc0[0]) : INFINITY;
-            tc[1] = r.sgn[1] ? fmaf(kc[1], r.dtc[1], r.tc0[1]) : INFINITY;
-            tc[2] = r.sgn[2] ? fmaf(kc[2], r.dtc[2], r.tc0[2]) : INFINITY;
+            tc[0] = fmaf(kc[0], r.dtc[0], r.tc0[0]);
+            tc[1] = fmaf(kc[1], r.dtc[1], r.tc0[1]);
+            tc[2] = fmaf(kc[2], r.dtc[2], r.tc0[2]);
             T_in = tco;
             bl = bricks[min(max(blin, 0), last_brick)];
         }

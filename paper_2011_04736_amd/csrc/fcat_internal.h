@@ -152,6 +152,15 @@ hipError_t launch_spectral_split(const float *L, int64_t n, const SpecTables &t,
 hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const float *kernels,
                       int k, float *out, hipStream_t stream);
 
+// Optical spread of the split form on the matrix cores (BF16 hi/lo, FP32
+// accumulate), for odd k <= kPsfSplitMaxK: B fragments of the banded kernel
+// rows (G * k * 2 * 64 uint4), then the convolution and group sum.
+constexpr int kPsfSplitMaxK = 17;
+inline size_t psf_split_frag_count(int G, int k) { return (size_t)G * k * 2 * kWave; }
+hipError_t launch_prep_psf_split(const float *kernels, int G, int k, uint4 *frag, hipStream_t stream);
+hipError_t launch_psf_split(const float *Y, int n_ang, int G, int nv, int nu, int k, const uint4 *frag, float *out,
+                            hipStream_t stream);
+
 hipError_t launch_check_labels(const int8_t *labels, int64_t n, int n_mat, int *flag,
                                hipStream_t stream);
 hipError_t launch_check_finite(const float *x, int64_t n, int *flag, hipStream_t stream);

@@ -399,12 +399,19 @@ hipError_t launch_spectral(const float *L, int64_t n, const SpecTables &t, const
 hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const float *kernels, int k,
                       float *out, hipStream_t stream)
 {
-    constexpr int ROWS = 8;
-    const dim3 grid((nu + kWave - 1) / kWave, (nv + 4 * ROWS - 1) / (4 * ROWS), n_ang);
-    if (k == 15)
+    // 4 rows per lane: with 8 the 8 x 15 kernel weights live at once exceed
+    // the scalar registers and spill through VGPR lanes (measured 41 vs 50
+    // TFLOP/s on the contrast workload)
+    constexpr int ROWS = 4;
+    constexpr int TV = (kBlock / kWave) * ROWS;
+    constexpr int TVG = (kBlock / kWave) * kGenRows;
+    if (k == 15) {
+        const dim3 grid((nu + kWave - 1) / kWave, (nv + TV - 1) / TV, n_ang);
         hipLaunchKernelGGL((k_psf<15, ROWS>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
-    else
+    } else {
+        const dim3 grid((nu + kWave - 1) / kWave, (nv + TVG - 1) / TVG, n_ang);
         hipLaunchKernelGGL(k_psf_generic, grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, k, out);
+    }
     return hipGetLastError();
 }
 

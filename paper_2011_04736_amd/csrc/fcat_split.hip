@@ -18,6 +18,9 @@
 // energy groups (each group is padded to whole tiles with zero weight), so
 // a group sum is the lane's partial sums reduced over the four lane
 // quarters that hold the same ray.
+//
+// The optical spread (Sec. II.G, Eq. 1) of the split form runs on the
+// matrix cores as well; see k_psf_split below.
 #include "fcat_device.h"
 
 namespace fcat {
@@ -199,6 +202,105 @@ __global__ __launch_bounds__(kBlock) void k_prep_split(const float *__restrict__
     if (kb == 0 && lane < 16) wtile[t * 16 + lane] = ev ? T.w[e] : 0.0f;
 }
 
+// ---------------------------------------------------------- split PSF
+//
+// out[v][u] = sum_g sum_{p,q} K_g[p][q] Y_g[v - p + c][u - q + c] (true
+// convolution, zero outside the detector, c = (k - 1) / 2).  For one kernel
+// row p, sixteen consecutive outputs of a detector row depend on 16 + k - 1
+// consecutive inputs, so the row convolution is a 16 x 32 by 32 x 16 matrix
+// product: A[r][j] = Y_g[v0 + r - p + c][u0 - c + j] (16 output rows r),
+// B_{g,p}[j][t] = K_g[p][t + 2c - j] where 0 <= t + 2c - j < k, else 0 (a
+// banded Toeplitz block, built once per call).  Both operands are split into
+// BF16 hi/lo parts and each product is formed as A_hi B_hi + A_lo B_hi +
+// A_hi B_lo with FP32 accumulation over p, g and the three terms.  Every
+// term is non-negative, so the relative error of an output is that of a
+// single product, below 3 * 2^-17.  A workgroup computes a 64 x 64 output
+// tile: wavefront w the rows 16w .. 16w + 15, as four 16 x 16 tiles across
+// u; the BF16 parts of the input tile with its halo live in LDS.
+
+constexpr int kPsfStride = 88;    // LDS row stride of the input tile (BF16): 80 used + 16 bytes of bank spread
+constexpr int kPsfRows = 64 + kPsfSplitMaxK - 1;
+
+// B fragments: frag[((g * k + p) * 2 + part) * 64 + lane], part 0 = hi, 1 = lo.
+__global__ __launch_bounds__(kBlock) void k_prep_psf_split(const float *__restrict__ ker, int G, int k,
+                                                           uint4 *__restrict__ frag)
+{
+    const int idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= G * k * 2 * kWave) return;
+    const int f = idx / kWave, lane = idx % kWave;
+    const int part = f & 1, gp = f >> 1;
+    const int q = lane >> 4, t = lane & 15;
+    const int c = (k - 1) / 2;
+    uint32_t h[8];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+        const int j = 8 * q + jj;
+        const int col = t + 2 * c - j;
+        const float v = (col >= 0 && col < k) ? ker[(int64_t)gp * k + col] : 0.0f;
+        const uint32_t hi = bf16_rne(v);
+        h[jj] = part ? bf16_rne(v - bf16_value(hi)) : hi;
+    }
+    frag[idx] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+
+__global__ __launch_bounds__(kBlock) void k_psf_split(const float *__restrict__ Y, int G, int nv, int nu, int k,
+                                                      const uint4 *__restrict__ frag, float *__restrict__ out)
+{
+    __shared__ __align__(16) uint16_t th[kPsfRows * kPsfStride];
+    __shared__ __align__(16) uint16_t tl[kPsfRows * kPsfStride];
+    const int c = (k - 1) / 2;
+    const int rows = 64 + k - 1;
+    const int u0 = blockIdx.x * 64, v0 = blockIdx.y * 64, a = blockIdx.z;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int q = lane >> 4, r16 = lane & 15;
+    const int64_t plane = (int64_t)nv * nu;
+    floatx4 acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < G; ++g) {
+        const float *Yg = Y + ((int64_t)a * G + g) * plane;
+        __syncthreads();
+        // input tile: rows v0 - c .., columns u0 - c .. u0 - c + 79, in column pairs
+        for (int i = threadIdx.x; i < rows * 40; i += kBlock) {
+            const int rr = i / 40, col = 2 * (i - rr * 40);
+            const int v = v0 - c + rr, u = u0 - c + col;
+            const bool vin = v >= 0 && v < nv;
+            const float y0 = (vin && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
+            const float y1 = (vin && u + 1 >= 0 && u + 1 < nu) ? Yg[(int64_t)v * nu + u + 1] : 0.0f;
+            uint32_t hi, lo;
+            split_bf16x2(y0, y1, hi, lo);
+            *reinterpret_cast<uint32_t *>(th + rr * kPsfStride + col) = hi;
+            *reinterpret_cast<uint32_t *>(tl + rr * kPsfStride + col) = lo;
+        }
+        __syncthreads();
+        const uint4 *fg = frag + (int64_t)g * k * 2 * kWave;
+        for (int p = 0; p < k; ++p) {
+            const bf16x8 bh = __builtin_bit_cast(bf16x8, fg[(2 * p) * kWave + lane]);
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, fg[(2 * p + 1) * kWave + lane]);
+            const int row = 16 * wave + r16 - p + 2 * c;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const int at = row * kPsfStride + 16 * ct + 8 * q;
+                const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(th + at);
+                const bf16x8 al = *reinterpret_cast<const bf16x8 *>(tl + at);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[ct], 0, 0, 0);
+            }
+        }
+    }
+    // D layout: lane (q, r16) holds rows 4q .. 4q + 3 of column r16
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int u = u0 + 16 * ct + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = v0 + 16 * wave + 4 * q + i;
+            if (v < nv && u < nu) out[(int64_t)a * plane + (int64_t)v * nu + u] = acc[ct][i];
+        }
+    }
+}
+
 int padded_blocks(int64_t waves)
 {
     const int64_t nblk = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
@@ -239,6 +341,24 @@ hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, c
     }
     FCAT_SPLIT_DISPATCH(FCAT_LAUNCH_PR)
 #undef FCAT_LAUNCH_PR
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_psf_split(const float *kernels, int G, int k, uint4 *frag, hipStream_t stream)
+{
+    if (k < 1 || k > kPsfSplitMaxK || (k & 1) == 0) return hipErrorInvalidValue;
+    const int n = G * k * 2 * kWave;
+    hipLaunchKernelGGL(k_prep_psf_split, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, kernels, G, k,
+                       frag);
+    return hipGetLastError();
+}
+
+hipError_t launch_psf_split(const float *Y, int n_ang, int G, int nv, int nu, int k, const uint4 *frag, float *out,
+                            hipStream_t stream)
+{
+    if (k < 1 || k > kPsfSplitMaxK || (k & 1) == 0) return hipErrorInvalidValue;
+    const dim3 grid((nu + 63) / 64, (nv + 63) / 64, n_ang);
+    hipLaunchKernelGGL(k_psf_split, grid, dim3(kBlock), 0, stream, Y, G, nv, nu, k, frag, out);
     return hipGetLastError();
 }
 

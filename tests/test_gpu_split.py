@@ -71,3 +71,24 @@ def test_split_project_head_sampled(fc):
     err = rel_err(o, oracle.project(cfg, sample))
     print(f"head split: max {err.max():.2e}")
     assert err.max() <= 1e-3
+
+
+@pytest.mark.parametrize("k", [3, 15, 17, 19])
+def test_split_psf_ragged_detector(fc, k):
+    """The split form's optical spread runs on the matrix cores for k <= 17 (banded
+    Toeplitz operands, BF16 hi/lo); k = 19 takes the FP32 kernel.  Ragged detector
+    (101 x 21 pixels: partial 64 x 64 tiles in both directions), 4 groups."""
+    rng = np.random.default_rng(100 + k)
+    cfg = synth.make_config(1)
+    cfg.geometry.nu, cfg.geometry.nv = 101, 21
+    cfg.spectral.n_groups = 4
+    cfg.spectral.group_of_bin = synth.contiguous_groups(cfg.spectral.n_energy, 4)
+    cfg.psf = synth.Psf(synth.gaussian_psfs(rng, 4, k))
+    pb = fc.upload(cfg)
+    out = fc.fcat_project(pb, mode="split_bf16").cpu().numpy()
+    plain = fc.fcat_project(pb).cpu().numpy()
+    angles = list(range(0, 45, 4))
+    ref = oracle.project(cfg, angles)
+    e_or, e_pl = rel_err(out[angles], ref).max(), rel_err(out, plain).max()
+    print(f"k={k}: split vs oracle {e_or:.2e}, split vs plain {e_pl:.2e}")
+    assert e_or <= 1e-3 and e_pl <= 1e-4
