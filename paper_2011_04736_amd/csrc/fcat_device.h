@@ -169,14 +169,15 @@ struct MatAcc {
     __device__ __forceinline__ void clear()
     {
 #pragma unroll
-        for (int m = 0; m < 2 * MP; ++m) base[m * kWave] = 0.0f;
+        for (int m = 0; m < 2 * (MP + 1); ++m) base[m * kWave] = 0.0f;
     }
-    // Compensated add of x to material m; labels outside 0..MP-1 add nothing.
-    __device__ __forceinline__ void add(int m, float x)
+    // Compensated add of x to material m.  Labels outside 0..MP-1 go to a
+    // spare slot (index MP) that is never read, so no test is needed.
+    __device__ __forceinline__ void add(unsigned m, float x)
     {
-        if (static_cast<unsigned>(m) >= static_cast<unsigned>(MP)) return;
-        float *ps = base + m * kWave;
-        float *pc = base + (MP + m) * kWave;
+        const unsigned k = min(m, static_cast<unsigned>(MP));
+        float *ps = base + k * kWave;
+        float *pc = base + (MP + 1 + k) * kWave;
         const float l = *ps, c = *pc;
         const float y = x - c;
         const float t = l + y;
@@ -192,7 +193,7 @@ struct MatAcc {
 
 // LDS floats per wavefront of MatAcc<MP>.
 template <int MP>
-constexpr int mat_acc_floats() { return 2 * MP * kWave; }
+constexpr int mat_acc_floats() { return 2 * (MP + 1) * kWave; }
 
 // Number of crossings of one axis at or before distance T: the k with
 // t0 + (k-1) dt <= T < t0 + k dt, evaluated with the same rounded formula
@@ -200,10 +201,12 @@ constexpr int mat_acc_floats() { return 2 * MP * kWave; }
 // had stepped through every plane.
 __device__ __forceinline__ float crossings_before(float T, float t0, float dt, float inv_dt)
 {
-    if (!(T >= t0)) return 0.0f;
-    float k = floorf((T - t0) * inv_dt) + 1.0f;
-    if (k > 0.0f && fmaf(k - 1.0f, dt, t0) > T) k -= 1.0f;
-    if (fmaf(k, dt, t0) <= T) k += 1.0f;
+    // Branch-free.  A parallel axis (t0 = inf, dt = inv_dt = 0) gives 0, as
+    // does T < t0: the first estimate is then 1 and the first test takes it
+    // back to 0.
+    float k = floorf(fmaxf(T - t0, 0.0f) * inv_dt) + 1.0f;
+    k -= (fmaf(k - 1.0f, dt, t0) > T) ? 1.0f : 0.0f;
+    k += (fmaf(k, dt, t0) <= T) ? 1.0f : 0.0f;
     return k;
 }
 
@@ -243,7 +246,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
     int bc[3] = {r.i0[0] / kBrickEdge, r.i0[1] / kBrickEdge, r.i0[2] / kBrickEdge};
     int blin = (bc[2] * nby + bc[1]) * nbx + bc[0];
     int bl = bricks[blin];
-    int cur = -1;
+    unsigned cur = MP;       // the spare slot: nothing charged before the first cell
     float run = 0.0f;
     float T_in = 0.0f;
     int budget = G.nb[0] + G.nb[1] + G.nb[2] + 4;
@@ -253,7 +256,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
         const bool last = !(tco < t_end) || --budget < 0;
         const float T_out = last ? t_end : tco;
         if (bl >= 0) {
-            if (bl != cur) {
+            if (static_cast<unsigned>(bl) != cur) {
                 acc.add(cur, T_in - run);
                 cur = bl;
                 run = T_in;
@@ -269,25 +272,25 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int b0 = bc[a] * kBrickEdge;
-                int ia = r.i0[a];
-                if (r.sgn[a]) {
-                    const float kk = crossings_before(T_in, r.t0[a], r.dt[a], r.inv_dt[a]);
-                    ia = min(max(r.i0[a] + r.sgn[a] * (int)kk, b0), b0 + kBrickEdge - 1);
-                }
+                // a parallel axis counts no crossings and stays in its voxel
+                const float kk = crossings_before(T_in, r.t0[a], r.dt[a], r.inv_dt[a]);
+                const int ia = min(max(r.i0[a] + r.sgn[a] * (int)kk, b0), b0 + kBrickEdge - 1);
                 k[a] = (float)(r.sgn[a] * (ia - r.i0[a]));
                 t[a] = fmaf(k[a], r.dt[a], r.t0[a]);
                 loc += (ia - b0) * lstride[a];
             }
-            const int8_t *brick = labels_bm + (int64_t)min(max(blin, 0), last_brick) * kBrickVox;
-            int lab = brick[loc];
+            const uint8_t *brick =
+                reinterpret_cast<const uint8_t *>(labels_bm) + (int64_t)min(max(blin, 0), last_brick) * kBrickVox;
+            unsigned lab = brick[loc];
             // the walk runs one crossing ahead of the label comparison, so
             // each label load has a step's worth of work to arrive
-            auto advance = [&](float &tn, int &labn) {
+            auto advance = [&](float &tn, unsigned &labn) {
                 tn = fminf(t[0], fminf(t[1], t[2]));
                 const bool bx = (t[0] == tn);
-                const bool by = !bx && (t[1] == tn);
-                const bool bz = !bx && !by;
-                loc += (bx ? dl[0] : 0) + (by ? dl[1] : 0) + (bz ? dl[2] : 0);
+                const bool ty = (t[1] == tn);
+                const bool by = !bx && ty;
+                const bool bz = !bx && !ty;
+                loc += bx ? dl[0] : (ty ? dl[1] : dl[2]);
                 k[0] += bx ? 1.0f : 0.0f;
                 k[1] += by ? 1.0f : 0.0f;
                 k[2] += bz ? 1.0f : 0.0f;
@@ -297,7 +300,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                 labn = brick[min(max(loc, 0), kBrickVox - 1)];
             };
             float tn;
-            int labn;
+            unsigned labn;
             advance(tn, labn);
             if (lab != cur) {
                 acc.add(cur, T_in - run);
@@ -307,7 +310,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             for (int f = 0; f < 3 * kBrickEdge + 3; ++f) {
                 if (!(tn < T_out)) break;
                 float tn2;
-                int lab2;
+                unsigned lab2;
                 advance(tn2, lab2);
                 if (labn != cur) {
                     acc.add(cur, tn - run);
@@ -322,9 +325,10 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             active = false;
         } else {
             const bool bx = (tc[0] == tco);
-            const bool by = !bx && (tc[1] == tco);
-            const bool bz = !bx && !by;
-            blin += (bx ? db[0] : 0) + (by ? db[1] : 0) + (bz ? db[2] : 0);
+            const bool ty = (tc[1] == tco);
+            const bool by = !bx && ty;
+            const bool bz = !bx && !ty;
+            blin += bx ? db[0] : (ty ? db[1] : db[2]);
             bc[0] += bx ? r.sgn[0] : 0;
             bc[1] += by ? r.sgn[1] : 0;
             bc[2] += bz ? r.sgn[2] : 0;
