@@ -125,6 +125,22 @@ size_t brick_count(const fcat_phantom_t *p)
 // brick map + brick-major label copy
 size_t brick_bytes(const fcat_phantom_t *p) { return align_up(brick_count(p)) + brick_count(p) * kBrickVox; }
 
+}  // namespace
+
+int tile_log2u_for(const TraceGeom &G)
+{
+    // detector rows covered by the grid's z extent at the largest magnification
+    // (grid corner nearest the source)
+    const double rx = 0.5 * G.n[0] * G.h[0] + fabs(G.lo[0] + 0.5 * G.n[0] * G.h[0]);
+    const double ry = 0.5 * G.n[1] * G.h[1] + fabs(G.lo[1] + 0.5 * G.n[1] * G.h[1]);
+    const double near = G.sid - sqrt(rx * rx + ry * ry);
+    const double mag = near > 0.0 ? (G.sid + G.back) / near : 1e9;
+    const double rows = G.n[2] * G.h[2] * mag / G.dv;
+    return rows < 24.0 ? 4 : 3;
+}
+
+namespace {
+
 TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 {
     TraceGeom G{};
@@ -152,6 +168,7 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
     for (int ax = 0; ax < 3; ++ax) G.nb[ax] = (n[ax] + kBrickEdge - 1) / kBrickEdge;
     G.bricks = nullptr;
     G.labels_bm = nullptr;
+    G.tile_log2u = tile_log2u_for(G);
     return G;
 }
 

@@ -77,6 +77,34 @@ __device__ __forceinline__ int xcd_block(int nblk_padded)
     return (b % kXcds) * per + b / kXcds;
 }
 
+// Pixel of lane `lane` of wavefront gw (see TraceGeom::tile_log2u): tiles of
+// an angle in row-major order, lanes row-major inside a tile.
+struct PixelOf {
+    int al, iv, iu;
+    bool valid;
+};
+
+__device__ __forceinline__ int tiles_per_angle(const TraceGeom &G)
+{
+    const int tu = 1 << G.tile_log2u, tv = kWave >> G.tile_log2u;
+    return ((G.nu + tu - 1) / tu) * ((G.nv + tv - 1) / tv);
+}
+
+__device__ __forceinline__ PixelOf pixel_of(const TraceGeom &G, int gw, int lane)
+{
+    const int tu = 1 << G.tile_log2u;
+    const int tu_n = (G.nu + tu - 1) >> G.tile_log2u;
+    const int per = tiles_per_angle(G);
+    PixelOf p;
+    p.al = gw / per;
+    const int rem = gw - p.al * per;
+    const int tv_i = rem / tu_n, tu_i = rem - tv_i * tu_n;
+    p.iv = (tv_i << (6 - G.tile_log2u)) + (lane >> G.tile_log2u);
+    p.iu = (tu_i << G.tile_log2u) + (lane & (tu - 1));
+    p.valid = p.iv < G.nv && p.iu < G.nu;
+    return p;
+}
+
 // Per-ray constants of the two-level walk.  Distances t are measured in mm
 // from the point where the ray enters the grid.
 struct Ray {

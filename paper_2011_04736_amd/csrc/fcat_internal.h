@@ -33,7 +33,22 @@ struct TraceGeom {
     int nb[3];
     const int8_t *bricks;
     const int8_t *labels_bm;
+    // Detector pixels of one wavefront: a (1 << tile_log2u) x (64 >> tile_log2u)
+    // tile (columns x rows) of one angle.  Compact tiles keep the 64 rays of a
+    // wavefront close in space, so they cross the same bricks at nearly the
+    // same steps (far less divergence than 64 pixels of one row).
+    int tile_log2u;
 };
+
+// Tile shape for a geometry: 8 x 8 pixels, or 16 x 4 where the phantom
+// covers only a few detector rows (a thin slab), so that fewer lanes of a
+// wavefront fall outside it.
+int tile_log2u_for(const TraceGeom &G);
+inline int64_t tiles_per_angle_host(const TraceGeom &G)
+{
+    const int tu = 1 << G.tile_log2u, tv = kWave >> G.tile_log2u;
+    return (int64_t)((G.nu + tu - 1) / tu) * ((G.nv + tv - 1) / tv);
+}
 
 // Spectral tables prepared on the device (in the workspace) from mu, phi,
 // eta and s_bin.  gstart is host-derived from the group map.

@@ -13,21 +13,19 @@ template <int MP>
 __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8_t *__restrict__ labels,
                                                          SpecTables T, const float *__restrict__ flood,
                                                          const float *__restrict__ scatter, int a0,
-                                                         int n_ang, int waves_per_row, int nblk_pad,
-                                                         float *__restrict__ Y, float *__restrict__ out)
+                                                         int n_ang, int nblk_pad, float *__restrict__ Y,
+                                                         float *__restrict__ out)
 {
     __shared__ float acc_all[(kBlock / kWave) * mat_acc_floats<MP>()];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
     const int gw = blk * (kBlock / kWave) + wave;
-    if (gw >= n_ang * G.nv * waves_per_row) return;
-    const int row = gw / waves_per_row;
-    const int iu = (gw - row * waves_per_row) * kWave + lane;
-    const int al = row / G.nv;
-    const int iv = row - al * G.nv;
+    if (gw >= n_ang * tiles_per_angle(G)) return;
+    const PixelOf px = pixel_of(G, gw, lane);
+    const int al = px.al, iv = px.iv, iu = px.iu;
     const int a = a0 + al;
-    const bool valid = iu < G.nu;
+    const bool valid = px.valid;
 
     double st, ct;
     sincos(angle_of(G, a), &st, &ct);
@@ -56,20 +54,18 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
 
 template <int MP>
 __global__ __launch_bounds__(kBlock) void k_pathlengths(TraceGeom G, const int8_t *__restrict__ labels,
-                                                        int n_mat, int a0, int n_ang, int waves_per_row,
-                                                        int nblk_pad, float *__restrict__ Lout)
+                                                        int n_mat, int a0, int n_ang, int nblk_pad,
+                                                        float *__restrict__ Lout)
 {
     __shared__ float acc_all[(kBlock / kWave) * mat_acc_floats<MP>()];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
     const int gw = blk * (kBlock / kWave) + wave;
-    if (gw >= n_ang * G.nv * waves_per_row) return;
-    const int row = gw / waves_per_row;
-    const int iu = (gw - row * waves_per_row) * kWave + lane;
-    const int al = row / G.nv;
-    const int iv = row - al * G.nv;
-    const bool valid = iu < G.nu;
+    if (gw >= n_ang * tiles_per_angle(G)) return;
+    const PixelOf px = pixel_of(G, gw, lane);
+    const int al = px.al, iv = px.iv, iu = px.iu;
+    const bool valid = px.valid;
     double st, ct;
     sincos(angle_of(G, a0 + al), &st, &ct);
     float L[MP];
@@ -325,21 +321,20 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
                                const float *flood, const float *scatter, int a0, int n_ang, float *Y,
                                float *out, hipStream_t stream)
 {
-    const int wpr = (g.nu + kWave - 1) / kWave;
-    const int64_t waves = (int64_t)n_ang * g.nv * wpr;
+    const int64_t waves = (int64_t)n_ang * tiles_per_angle_host(g);
     const int nblk = padded_blocks(waves);
     switch (t.mp) {
     case 8:
         hipLaunchKernelGGL(k_project_rows<8>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, t, flood,
-                           scatter, a0, n_ang, wpr, nblk, Y, out);
+                           scatter, a0, n_ang, nblk, Y, out);
         break;
     case 16:
         hipLaunchKernelGGL(k_project_rows<16>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, t, flood,
-                           scatter, a0, n_ang, wpr, nblk, Y, out);
+                           scatter, a0, n_ang, nblk, Y, out);
         break;
     case 32:
         hipLaunchKernelGGL(k_project_rows<32>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, t, flood,
-                           scatter, a0, n_ang, wpr, nblk, Y, out);
+                           scatter, a0, n_ang, nblk, Y, out);
         break;
     default:
         return hipErrorInvalidValue;
@@ -360,18 +355,17 @@ hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int
 hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0, int n_ang,
                               float *L, hipStream_t stream)
 {
-    const int wpr = (g.nu + kWave - 1) / kWave;
-    const int64_t waves = (int64_t)n_ang * g.nv * wpr;
+    const int64_t waves = (int64_t)n_ang * tiles_per_angle_host(g);
     const int nblk = padded_blocks(waves);
     if (n_mat <= 8)
         hipLaunchKernelGGL(k_pathlengths<8>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
-                           n_ang, wpr, nblk, L);
+                           n_ang, nblk, L);
     else if (n_mat <= 16)
         hipLaunchKernelGGL(k_pathlengths<16>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
-                           n_ang, wpr, nblk, L);
+                           n_ang, nblk, L);
     else
         hipLaunchKernelGGL(k_pathlengths<32>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
-                           n_ang, wpr, nblk, L);
+                           n_ang, nblk, L);
     return hipGetLastError();
 }
 

@@ -99,7 +99,7 @@ template <int MP, int NKB>
 __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, SpecTables T, SplitTables S,
                                                                const float *__restrict__ flood,
                                                                const float *__restrict__ scatter, int a0,
-                                                               int n_ang, int waves_per_row, int nblk_pad,
+                                                               int n_ang, int nblk_pad,
                                                                float *__restrict__ Y, float *__restrict__ out)
 {
     // per wavefront: the traversal's material accumulators, then (after the
@@ -112,13 +112,11 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
     const int gw = blk * (kBlock / kWave) + wave;
-    if (gw >= n_ang * G.nv * waves_per_row) return;
-    const int row = gw / waves_per_row;
-    const int iu = (gw - row * waves_per_row) * kWave + lane;
-    const int al = row / G.nv;
-    const int iv = row - al * G.nv;
+    if (gw >= n_ang * tiles_per_angle(G)) return;
+    const PixelOf px = pixel_of(G, gw, lane);
+    const int al = px.al, iv = px.iv, iu = px.iu;
     const int a = a0 + al;
-    const bool valid = iu < G.nu;
+    const bool valid = px.valid;
 
     double st, ct;
     sincos(angle_of(G, a), &st, &ct);
@@ -131,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
     wave_sync_lds();
 
     const int64_t plane = (int64_t)G.nu * G.nv;
-    const int64_t pix = (int64_t)iv * G.nu + min(iu, G.nu - 1);
+    const int64_t pix = (int64_t)min(iv, G.nv - 1) * G.nu + min(iu, G.nu - 1);   // all lanes take part
     const float i0 = flood ? flood[pix] : 1.0f;
     const float sc = scatter ? scatter[(int64_t)a * plane + pix] : 0.0f;
     float total = 0.0f;
@@ -331,13 +329,12 @@ hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, c
                                      int n_ang, float *Y, float *out, hipStream_t stream)
 {
     (void)labels;
-    const int wpr = (g.nu + kWave - 1) / kWave;
-    const int64_t waves = (int64_t)n_ang * g.nv * wpr;
+    const int64_t waves = (int64_t)n_ang * tiles_per_angle_host(g);
     const int nblk = padded_blocks(waves);
 #define FCAT_LAUNCH_PR(MPV, NKBV)                                                                           \
     {                                                                                                       \
         hipLaunchKernelGGL((k_project_rows_split<MPV, NKBV>), dim3(nblk), dim3(kBlock), 0, stream, g, t, sp, \
-                           flood, scatter, a0, n_ang, wpr, nblk, Y, out);                                   \
+                           flood, scatter, a0, n_ang, nblk, Y, out);                                   \
     }
     FCAT_SPLIT_DISPATCH(FCAT_LAUNCH_PR)
 #undef FCAT_LAUNCH_PR
