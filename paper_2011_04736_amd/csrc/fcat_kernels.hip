@@ -213,6 +213,91 @@ __global__ __launch_bounds__(kBlock) void k_psf(const float *__restrict__ Y, int
     }
 }
 
+// The same convolution with a 4 x 4 output block per lane: lane l of
+// wavefront w owns columns 4l .. 4l + 3 and rows 4w .. 4w + 3 of a 256 x 16
+// output tile.  For each input row it reads its K + 3 inputs with aligned
+// 16-byte LDS loads (immediate offsets, no address arithmetic) and feeds
+// each to up to 4 x 4 outputs; the kernel rows in use at once (at most 4)
+// stay in scalar registers.
+constexpr int kP4Cols = 4 * kWave;              // 256 output columns per tile
+constexpr int kP4Rows = 4 * (kBlock / kWave);   // 16 output rows per tile
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_psf4(const float *__restrict__ Y, int G, int nv, int nu,
+                                                 const float *__restrict__ ker, float *__restrict__ out)
+{
+    constexpr int C = (K - 1) / 2;
+    constexpr int NX = (K + 3 + 3) / 4 * 4;       // inputs read per row, a multiple of 4
+    constexpr int LW = kP4Cols + NX - 4;          // tile width (covers the last lane's reads)
+    constexpr int LH = kP4Rows + K - 1;
+    static_assert(LW % 4 == 0, "aligned rows");
+    __shared__ __align__(16) float tile[LH * LW];
+    const int u0 = blockIdx.x * kP4Cols;
+    const int v0 = blockIdx.y * kP4Rows;
+    const int a = blockIdx.z;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t plane = (int64_t)nv * nu;
+    float acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0f;
+
+    for (int g = 0; g < G; ++g) {
+        const float *Yg = Y + ((int64_t)a * G + g) * plane;
+        __syncthreads();
+        for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+            const int rr = i / LW;
+            const int cc = i - rr * LW;
+            const int v = v0 - C + rr;
+            const int u = u0 - C + cc;
+            tile[i] = (v >= 0 && v < nv && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
+        }
+        __syncthreads();
+        const float *kg = ker + g * K * K;
+        const float *trow = tile + (4 * wave) * LW + 4 * lane;
+#pragma unroll
+        for (int rr = 0; rr < K + 3; ++rr) {
+            float x[NX];
+#pragma unroll
+            for (int j = 0; j < NX; j += 4) {
+                const float4 v4 = *reinterpret_cast<const float4 *>(trow + rr * LW + j);
+                x[j] = v4.x;
+                x[j + 1] = v4.y;
+                x[j + 2] = v4.z;
+                x[j + 3] = v4.w;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = rr - r;
+                if (i >= 0 && i < K) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) {
+                        const float w = kg[(K - 1 - i) * K + (K - 1 - j)];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(w, x[c + j], acc[r][c]);
+                    }
+                }
+            }
+        }
+    }
+    const int ub = u0 + 4 * lane;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int v = v0 + 4 * wave + r;
+        if (v >= nv) continue;
+        float *o = out + (int64_t)a * plane + (int64_t)v * nu + ub;
+        if ((nu & 3) == 0 && ub + 3 < nu) {
+            *reinterpret_cast<float4 *>(o) = make_float4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (ub + c < nu) o[c] = acc[r][c];
+        }
+    }
+}
+
 // Any odd k up to FCAT_MAX_PSF, runtime loops.
 constexpr int kGenRows = 8;
 constexpr int kGenLH = (kBlock / kWave) * kGenRows + FCAT_MAX_PSF - 1;
@@ -400,8 +485,11 @@ hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const fl
     constexpr int TV = (kBlock / kWave) * ROWS;
     constexpr int TVG = (kBlock / kWave) * kGenRows;
     if (k == 15) {
+        const dim3 grid((nu + kP4Cols - 1) / kP4Cols, (nv + kP4Rows - 1) / kP4Rows, n_ang);
+        hipLaunchKernelGGL((k_psf4<15>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
+    } else if (k == 5) {
         const dim3 grid((nu + kWave - 1) / kWave, (nv + TV - 1) / TV, n_ang);
-        hipLaunchKernelGGL((k_psf<15, ROWS>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
+        hipLaunchKernelGGL((k_psf<5, ROWS>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
     } else {
         const dim3 grid((nu + kWave - 1) / kWave, (nv + TVG - 1) / TVG, n_ang);
         hipLaunchKernelGGL(k_psf_generic, grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, k, out);
