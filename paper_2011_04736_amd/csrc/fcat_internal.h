@@ -13,7 +13,7 @@ namespace fcat {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
-constexpr int kBrickEdge = 8;      // edge of the cubic label bricks of the two-level walk
+constexpr int kBrickEdge = 16;     // edge of the cubic label bricks of the two-level walk (8 and 32 measured slower)
 constexpr int kBrickVox = kBrickEdge * kBrickEdge * kBrickEdge;
 
 // Ray geometry of one launch, everything a lane needs to build its ray in

@@ -353,34 +353,41 @@ __global__ __launch_bounds__(kBlock) void k_psf_generic(const float *__restrict_
 }
 
 // Brick map and brick-major copy of the labels.  One workgroup per brick:
-// thread (z, y, x) of the brick copies one label (positions past the grid
-// edge get the nearest voxel inside it) into labels_bm[brick][z][y][x], and
-// the brick is uniform when every voxel inside the grid carries the same
-// non-negative label.  bricks[b] holds that label, or -1.
-__global__ __launch_bounds__(kBrickVox) void k_build_bricks(const int8_t *__restrict__ labels, int nx, int ny,
-                                                            int nz, int nbx, int nby,
-                                                            int8_t *__restrict__ bricks,
-                                                            int8_t *__restrict__ labels_bm)
+// the threads copy the brick's labels (positions past the grid edge get the
+// nearest voxel inside it) into labels_bm[brick][z][y][x], and the brick is
+// uniform when every voxel inside the grid carries the same non-negative
+// label.  bricks[b] holds that label, or -1.
+constexpr int kBuildThreads = kBrickVox < 512 ? kBrickVox : 512;
+
+__global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__restrict__ labels, int nx, int ny,
+                                                                int nz, int nbx, int nby,
+                                                                int8_t *__restrict__ bricks,
+                                                                int8_t *__restrict__ labels_bm)
 {
     const int b = blockIdx.x;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int lx = threadIdx.x & (kBrickEdge - 1);
-    const int ly = (threadIdx.x / kBrickEdge) & (kBrickEdge - 1);
-    const int lz = threadIdx.x / (kBrickEdge * kBrickEdge);
-    const int x = bx * kBrickEdge + lx, y = by * kBrickEdge + ly, z = bz * kBrickEdge + lz;
-    const bool in = x < nx && y < ny && z < nz;
-    const int v = labels[((int64_t)min(z, nz - 1) * ny + min(y, ny - 1)) * nx + min(x, nx - 1)];
-    labels_bm[(int64_t)b * kBrickVox + threadIdx.x] = (int8_t)v;
     __shared__ int first;
     __shared__ int mixed;
     if (threadIdx.x == 0) {
-        first = v;
-        mixed = v < 0;
+        first = labels[((int64_t)(bz * kBrickEdge) * ny + by * kBrickEdge) * nx + bx * kBrickEdge];
+        mixed = first < 0;
     }
     __syncthreads();
-    if (in && v != first) mixed = 1;
+    const int f = first;
+    bool diff = false;
+    for (int i = threadIdx.x; i < kBrickVox; i += kBuildThreads) {
+        const int lx = i & (kBrickEdge - 1);
+        const int ly = (i / kBrickEdge) & (kBrickEdge - 1);
+        const int lz = i / (kBrickEdge * kBrickEdge);
+        const int x = bx * kBrickEdge + lx, y = by * kBrickEdge + ly, z = bz * kBrickEdge + lz;
+        const bool in = x < nx && y < ny && z < nz;
+        const int v = labels[((int64_t)min(z, nz - 1) * ny + min(y, ny - 1)) * nx + min(x, nx - 1)];
+        labels_bm[(int64_t)b * kBrickVox + i] = (int8_t)v;
+        diff = diff || (in && v != f);
+    }
+    if (diff) mixed = 1;
     __syncthreads();
-    if (threadIdx.x == 0) bricks[b] = mixed ? (int8_t)-1 : (int8_t)first;
+    if (threadIdx.x == 0) bricks[b] = mixed ? (int8_t)-1 : (int8_t)f;
 }
 
 int padded_blocks(int64_t waves)
@@ -432,7 +439,7 @@ hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int
 {
     const int nbx = (nx + kBrickEdge - 1) / kBrickEdge, nby = (ny + kBrickEdge - 1) / kBrickEdge;
     const int nbz = (nz + kBrickEdge - 1) / kBrickEdge;
-    hipLaunchKernelGGL(k_build_bricks, dim3(nbx * nby * nbz), dim3(kBrickVox), 0, stream, labels, nx, ny, nz, nbx,
+    hipLaunchKernelGGL(k_build_bricks, dim3(nbx * nby * nbz), dim3(kBuildThreads), 0, stream, labels, nx, ny, nz, nbx,
                        nby, bricks, labels_bm);
     return hipGetLastError();
 }

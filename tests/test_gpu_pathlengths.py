@@ -103,17 +103,19 @@ def test_axis_aligned_and_parallel_rays(fc):
     assert Lref[0, 1, 2, 1] > 5.9                     # central ray runs inside layer z in [0, 1)
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_blocky_phantom_brick_walk(fc, seed):
-    """Piecewise-constant blocks of random sizes (most 8^3 bricks uniform, some
-    mixed, partial bricks at the grid edge) with random noise patches: the
-    two-level walk must match the exact path lengths everywhere."""
+@pytest.mark.parametrize("seed,shape,blocks", [(0, (61, 45, 27), (3, 20)), (1, (61, 45, 27), (3, 20)),
+                                               (2, (97, 83, 53), (16, 48))])
+def test_blocky_phantom_brick_walk(fc, seed, shape, blocks):
+    """Piecewise-constant blocks of random sizes (with the larger blocks many
+    bricks are uniform, others mixed, partial bricks at the grid edge) with
+    random noise patches: the two-level walk must match the exact path
+    lengths everywhere."""
     rng = np.random.default_rng(40 + seed)
-    nx, ny, nz = 61, 45, 27                         # not multiples of the brick edge
+    nx, ny, nz = shape                              # not multiples of the brick edge
     labels = np.zeros((nz, ny, nx), np.int8)
     for _ in range(25):
         x0, y0, z0 = rng.integers(0, [nx, ny, nz])
-        sx, sy, sz = rng.integers(3, 20, size=3)
+        sx, sy, sz = rng.integers(*blocks, size=3)
         labels[z0:z0 + sz, y0:y0 + sy, x0:x0 + sx] = rng.integers(0, 7)
     for _ in range(6):
         x0, y0, z0 = rng.integers(0, [nx - 4, ny - 4, nz - 4])
