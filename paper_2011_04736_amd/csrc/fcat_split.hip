@@ -258,17 +258,23 @@ __global__ __launch_bounds__(kBlock) void k_psf_split(const float *__restrict__ 
     for (int g = 0; g < G; ++g) {
         const float *Yg = Y + ((int64_t)a * G + g) * plane;
         __syncthreads();
-        // input tile: rows v0 - c .., columns u0 - c .. u0 - c + 79, in column pairs
-        for (int i = threadIdx.x; i < rows * 40; i += kBlock) {
-            const int rr = i / 40, col = 2 * (i - rr * 40);
-            const int v = v0 - c + rr, u = u0 - c + col;
-            const bool vin = v >= 0 && v < nv;
-            const float y0 = (vin && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
-            const float y1 = (vin && u + 1 >= 0 && u + 1 < nu) ? Yg[(int64_t)v * nu + u + 1] : 0.0f;
-            uint32_t hi, lo;
-            split_bf16x2(y0, y1, hi, lo);
-            *reinterpret_cast<uint32_t *>(th + rr * kPsfStride + col) = hi;
-            *reinterpret_cast<uint32_t *>(tl + rr * kPsfStride + col) = lo;
+        // input tile: rows v0 - c .., columns u0 - c .. u0 - c + 79; thread t
+        // fills column pair t % 40 of rows t / 40, t / 40 + 6, ...
+        if (threadIdx.x < 240) {
+            const int col = 2 * (threadIdx.x % 40);
+            const int u = u0 - c + col;
+            const bool in0 = u >= 0 && u < nu, in1 = u + 1 >= 0 && u + 1 < nu;
+            for (int rr = threadIdx.x / 40; rr < rows; rr += 6) {
+                const int v = v0 - c + rr;
+                const bool vin = v >= 0 && v < nv;
+                const int64_t row = (int64_t)min(max(v, 0), nv - 1) * nu;
+                const float y0 = (vin && in0) ? Yg[row + u] : 0.0f;
+                const float y1 = (vin && in1) ? Yg[row + u + 1] : 0.0f;
+                uint32_t hi, lo;
+                split_bf16x2(y0, y1, hi, lo);
+                *reinterpret_cast<uint32_t *>(th + rr * kPsfStride + col) = hi;
+                *reinterpret_cast<uint32_t *>(tl + rr * kPsfStride + col) = lo;
+            }
         }
         __syncthreads();
         const uint4 *fg = frag + (int64_t)g * k * 2 * kWave;
@@ -318,6 +324,8 @@ hipError_t launch_prep_split(const float *mu, const SpecTables &t, const SplitTa
 
 #define FCAT_SPLIT_DISPATCH(MACRO) \
     if (t.mp == 8 && sp.nkb == 1) MACRO(8, 1) \
+    else if (t.mp == 12 && sp.nkb == 1) MACRO(12, 1) \
+    else if (t.mp == 12 && sp.nkb == 2) MACRO(12, 2) \
     else if (t.mp == 16 && sp.nkb == 1) MACRO(16, 1) \
     else if (t.mp == 16 && sp.nkb == 2) MACRO(16, 2) \
     else if (t.mp == 32 && sp.nkb == 2) MACRO(32, 2) \
