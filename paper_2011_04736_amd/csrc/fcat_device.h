@@ -187,41 +187,50 @@ __device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double 
 // change label at different steps, so a register file indexed by
 // compare-select (two selects per material and value) would cost the whole
 // wavefront tens of instructions on almost every step.  LDS takes the
-// material as an index instead.  Layout per wavefront: [2][MP][64] floats
-// (sum, then Kahan compensation), lane-contiguous, so accesses are free of
-// bank conflicts.
+// material as an index instead.  Layout per wavefront: FP32 sums [MP+1][64],
+// then the Kahan compensations [MP+1][64] held as BF16 (a compensation is
+// below half an ulp of its sum; BF16 keeps it to 0.4%, which leaves the
+// compensated sum's error far below one FP32 ulp and keeps the block small
+// enough for full occupancy).  Lane-contiguous, free of bank conflicts.
 template <int MP>
 struct MatAcc {
-    float *base;    // this lane's slot: wave block + lane
+    float *sum;          // this lane's slot of the sums
+    uint16_t *comp;      // this lane's slot of the compensations
 
+    __device__ __forceinline__ MatAcc(float *wave_block, int lane)
+        : sum(wave_block + lane), comp(reinterpret_cast<uint16_t *>(wave_block + (MP + 1) * kWave) + lane)
+    {
+    }
     __device__ __forceinline__ void clear()
     {
 #pragma unroll
-        for (int m = 0; m < 2 * (MP + 1); ++m) base[m * kWave] = 0.0f;
+        for (int m = 0; m < MP + 1; ++m) {
+            sum[m * kWave] = 0.0f;
+            comp[m * kWave] = 0;
+        }
     }
     // Compensated add of x to material m.  Labels outside 0..MP-1 go to a
     // spare slot (index MP) that is never read, so no test is needed.
     __device__ __forceinline__ void add(unsigned m, float x)
     {
         const unsigned k = min(m, static_cast<unsigned>(MP));
-        float *ps = base + k * kWave;
-        float *pc = base + (MP + 1 + k) * kWave;
-        const float l = *ps, c = *pc;
+        const float l = sum[k * kWave];
+        const float c = bf16_value(comp[k * kWave]);
         const float y = x - c;
         const float t = l + y;
-        *pc = (t - l) - y;
-        *ps = t;
+        comp[k * kWave] = static_cast<uint16_t>(pack_bf16x2((t - l) - y, 0.0f));
+        sum[k * kWave] = t;
     }
     __device__ __forceinline__ void read(float (&L)[MP]) const
     {
 #pragma unroll
-        for (int m = 0; m < MP; ++m) L[m] = base[m * kWave];
+        for (int m = 0; m < MP; ++m) L[m] = sum[m * kWave];
     }
 };
 
-// LDS floats per wavefront of MatAcc<MP>.
+// LDS floats per wavefront of MatAcc<MP> (sums plus half-size compensations).
 template <int MP>
-constexpr int mat_acc_floats() { return 2 * (MP + 1) * kWave; }
+constexpr int mat_acc_floats() { return (MP + 1) * kWave + ((MP + 1) * kWave + 1) / 2; }
 
 // Number of crossings of one axis at or before distance T: the k with
 // t0 + (k-1) dt <= T < t0 + k dt, evaluated with the same rounded formula
@@ -254,7 +263,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                                              const int8_t *__restrict__ labels_bm,
                                              const int8_t *__restrict__ bricks, float *acc_wave, float (&L)[MP])
 {
-    MatAcc<MP> acc{acc_wave + (threadIdx.x & (kWave - 1))};
+    MatAcc<MP> acc(acc_wave, threadIdx.x & (kWave - 1));
     acc.clear();
     if (!hit) {
 #pragma unroll
