@@ -214,26 +214,29 @@ __global__ __launch_bounds__(kBlock) void k_psf(const float *__restrict__ Y, int
 }
 
 // The same convolution with a 4 x 4 output block per lane: lane l of
-// wavefront w owns columns 4l .. 4l + 3 and rows 4w .. 4w + 3 of a 256 x 16
+// wavefront w owns columns 4l .. 4l + 3 and rows 4w .. 4w + 3 of a 256 x (4 * kP4Waves)
 // output tile.  For each input row it reads its K + 3 inputs with aligned
 // 16-byte LDS loads (immediate offsets, no address arithmetic) and feeds
 // each to up to 4 x 4 outputs; the kernel rows in use at once (at most 4)
 // stay in scalar registers.
 constexpr int kP4Cols = 4 * kWave;              // 256 output columns per tile
-constexpr int kP4Rows = 4 * (kBlock / kWave);   // 16 output rows per tile
+constexpr int kP4Waves = 8;                     // wavefronts per workgroup (4 and 16 measured slower)
+constexpr int kP4Rows = 4 * kP4Waves;           // output rows per tile
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_psf4(const float *__restrict__ Y, int G, int nv, int nu,
-                                                 const float *__restrict__ ker, float *__restrict__ out)
+template <int K, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y, int G, int nv, int nu,
+                                                     const float *__restrict__ ker, float *__restrict__ out)
 {
     constexpr int C = (K - 1) / 2;
     constexpr int NX = (K + 3 + 3) / 4 * 4;       // inputs read per row, a multiple of 4
     constexpr int LW = kP4Cols + NX - 4;          // tile width (covers the last lane's reads)
-    constexpr int LH = kP4Rows + K - 1;
+    constexpr int ROWS = 4 * NW;
+    constexpr int LH = ROWS + K - 1;
+    constexpr int NT = NW * kWave;
     static_assert(LW % 4 == 0, "aligned rows");
     __shared__ __align__(16) float tile[LH * LW];
     const int u0 = blockIdx.x * kP4Cols;
-    const int v0 = blockIdx.y * kP4Rows;
+    const int v0 = blockIdx.y * ROWS;
     const int a = blockIdx.z;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_psf4(const float *__restrict__ Y, in
     for (int g = 0; g < G; ++g) {
         const float *Yg = Y + ((int64_t)a * G + g) * plane;
         __syncthreads();
-        for (int i = threadIdx.x; i < LH * LW; i += kBlock) {
+        for (int i = threadIdx.x; i < LH * LW; i += NT) {
             const int rr = i / LW;
             const int cc = i - rr * LW;
             const int v = v0 - C + rr;
@@ -503,7 +506,7 @@ hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const fl
     constexpr int TVG = (kBlock / kWave) * kGenRows;
     if (k == 15) {
         const dim3 grid((nu + kP4Cols - 1) / kP4Cols, (nv + kP4Rows - 1) / kP4Rows, n_ang);
-        hipLaunchKernelGGL((k_psf4<15>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
+        hipLaunchKernelGGL((k_psf4<15, kP4Waves>), grid, dim3(kP4Waves * kWave), 0, stream, Y, G, nv, nu, kernels, out);
     } else if (k == 5) {
         const dim3 grid((nu + kWave - 1) / kWave, (nv + TV - 1) / TV, n_ang);
         hipLaunchKernelGGL((k_psf<5, ROWS>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
