@@ -243,6 +243,91 @@ fcat_status fcat_check_inputs(const fcat_geometry_t *geometry, const fcat_phanto
                               const fcat_psf_t *psf, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/* ------------------------------------------------- noise and projections */
+/*
+ * Sec. II.G, Eq. 5.  Noise is a Poisson scaling of the counts on the
+ * detector, with the flood field scaled to a height of H counts per pixel
+ * (H = N_gamma / (A / A_p): particles over beam area in pixel areas); the
+ * scatter takes Poisson noise from its pixel's counts; the noisy profiles go
+ * through the optical spread and the group sum and come back as projections
+ * through the flood field.  The paper leaves the details open; this library
+ * computes:
+ *   c_g    = H Phi_g / (Phi W_g)          count scale of group g, with
+ *            Phi_g = sum_{e in g} phi_e, Phi = sum_e phi_e, W_g = sum_{e in g} phi_e eta_e
+ *            (FP64 sums in bin order, rounded to float; 0 if Phi_g or W_g is 0),
+ *            so an open pixel with I0 = 1 holds H Phi_g / Phi photons of group g
+ *            and H in all;
+ *   Y_g   <- n / c_g,  n ~ Poisson(float(c_g * Y_g))   (before the spread; n / c_g
+ *            in FP32 to 2 ulp; the scatter inside Y_g needs no draw of its own,
+ *            a sum of independent Poisson counts being Poisson; a group with
+ *            c_g <= 0 passes unchanged);
+ *   flood  = sum_g K_g (*) (W_g I0)       noiseless, object-free, no scatter;
+ *   proj   = -ln(max(out, floor) / flood).
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), key
+ * (seed mod 2^32, seed div 2^32), counters (pixel, group, angle, j) for
+ * j = 0, 1, ..., each block giving the pairs (u, v) = (w0, w1), (w2, w3) as
+ * (w + 1/2) 2^-32.  Pixel is v * nu + u, angle the index in the full scan.
+ * Poisson variates: for a mean below 16, the smallest k with u <= F(k) (CDF
+ * summed term by term, at most 256 terms); otherwise the transformed
+ * rejection method PTRS (Hormann 1993), one pair per attempt, at most 64
+ * attempts (then floor(mean + 1/2)); FP64 throughout.  A draw therefore
+ * depends only on (seed, pixel, group, angle, mean), never on launch shape,
+ * chunking or stream.
+ */
+typedef struct fcat_noise_t {
+    double counts_per_pixel;  /* H of Eq. 5, > 0 */
+    uint64_t seed;            /* Philox key */
+    float floor;              /* >= 0: lower bound of the detected profile before the log;
+                                 0 lets a pixel with no counts give +inf */
+} fcat_noise_t;
+
+/* c_g of Eq. 5 (see above) into scale (DEVICE float [n_groups]). */
+fcat_status fcat_count_scale(const fcat_spectral_t *spectral, double counts_per_pixel, float *scale, void *stream);
+
+/*
+ * Poisson noise on group signals, in place: Y (DEVICE float
+ * [n_ang][n_groups][plane]) holds angles angle_base .. angle_base + n_ang - 1;
+ * scale is DEVICE float [n_groups].  plane < 2^31, angle_base >= 0.
+ */
+fcat_status fcat_poisson(float *Y, int32_t n_ang, int32_t n_groups, int64_t plane, const float *scale,
+                         uint64_t seed, int32_t angle_base, void *stream);
+
+/* Workspace needed by fcat_flood_profile. */
+size_t fcat_flood_workspace_bytes(const fcat_spectral_t *spectral, int32_t nv, int32_t nu);
+
+/*
+ * Noiseless object-free flood through the spread: flood (DEVICE float
+ * [nv][nu]) = sum_g K_g (*) (W_g I0), I0 = spectral->flood (NULL: 1).
+ * psf NULL gives sum_g W_g I0.
+ */
+fcat_status fcat_flood_profile(const fcat_spectral_t *spectral, const fcat_psf_t *psf, int32_t nv, int32_t nu,
+                               float *flood, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * proj[a][p] = -ln(max(out[a][p], floor) / flood[p]) for out, proj DEVICE
+ * float [n_ang][plane] (proj may equal out) and flood DEVICE float [plane].
+ */
+fcat_status fcat_log_projection(const float *out, const float *flood, int32_t n_ang, int64_t plane, float floor,
+                                float *proj, void *stream);
+
+/* Workspace needed by fcat_projections (arguments as for fcat_project_workspace_bytes). */
+size_t fcat_projections_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                        const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                                        const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk);
+
+/*
+ * The projector followed by the noise and projection stage:
+ * proj[a][v][u] (DEVICE float [n_angles][nv][nu]) = -ln(max(out, floor) / flood)
+ * where out is fcat_project's detected profile with every group signal
+ * replaced by its Poisson draw.  noise NULL gives noiseless projections
+ * (floor 0).  Other arguments as for fcat_project.
+ */
+fcat_status fcat_projections(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                             const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                             const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
+                             const fcat_noise_t *noise, float *proj, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
 /* ------------------------------------------------------------ surrogate */
 /*
  * The learned form of the primary spectral sum (see fcat_surrogate_t).  The
@@ -336,12 +421,14 @@ typedef enum fcat_stage {
     FCAT_STAGE_TRACE = 1,  /* fused traversal + contraction + spectral sum (+ scatter) */
     FCAT_STAGE_PSF = 2,    /* optical spread + group sum */
     FCAT_STAGE_MLP = 3,    /* surrogate training / inference kernels run on their own */
-    FCAT_STAGE_COUNT = 4
+    FCAT_STAGE_NOISE = 4,  /* count scale, Poisson draws, flood profile and log conversion */
+    FCAT_STAGE_COUNT = 5
 } fcat_stage;
 
 /*
  * For benchmarks and profiling.  While enabled (process-wide), every kernel
- * that fcat_project, fcat_spectral and fcat_psf launch is bracketed by two
+ * that fcat_project, fcat_projections, fcat_spectral, fcat_psf and the noise
+ * calls launch is bracketed by two
  * HIP events recorded on the same stream.  fcat_timing_read waits for the
  * recorded events, adds the elapsed milliseconds and launch counts per
  * stage into ms[n_stages] and launches[n_stages] (HOST arrays, either may be

@@ -17,6 +17,7 @@ raise; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -35,7 +36,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfcat.so")
 MODES = {"plain": 0, "split_bf16": 1, "surrogate": 2}
-STAGES = ("prep", "trace", "psf", "mlp")
+STAGES = ("prep", "trace", "psf", "mlp", "noise")
 _lib = None
 
 
@@ -74,6 +75,10 @@ class _CScatter(C.Structure):
 
 class _CPsf(C.Structure):
     _fields_ = [("k", C.c_int32), ("kernels", C.c_void_p)]
+
+
+class _CNoise(C.Structure):
+    _fields_ = [("counts_per_pixel", C.c_double), ("seed", C.c_uint64), ("floor", C.c_float)]
 
 
 class _CSurrogate(C.Structure):
@@ -148,6 +153,21 @@ def load() -> C.CDLL:
     L.fcat_mlp_validate.restype = st
     L.fcat_mlp_setup.argtypes = [sp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
     L.fcat_mlp_setup.restype = st
+    nzp, u64 = C.POINTER(_CNoise), C.c_uint64
+    L.fcat_count_scale.argtypes = [sp, C.c_double, vp, vp]
+    L.fcat_count_scale.restype = st
+    L.fcat_poisson.argtypes = [vp, C.c_int32, C.c_int32, i64, vp, u64, C.c_int32, vp]
+    L.fcat_poisson.restype = st
+    L.fcat_flood_workspace_bytes.argtypes = [sp, C.c_int32, C.c_int32]
+    L.fcat_flood_workspace_bytes.restype = sz
+    L.fcat_flood_profile.argtypes = [sp, psp, C.c_int32, C.c_int32, vp, vp, sz, vp]
+    L.fcat_flood_profile.restype = st
+    L.fcat_log_projection.argtypes = [vp, vp, C.c_int32, i64, C.c_float, vp, vp]
+    L.fcat_log_projection.restype = st
+    L.fcat_projections_workspace_bytes.argtypes = [gp, pp, sp, scp, psp, st, C.c_int32]
+    L.fcat_projections_workspace_bytes.restype = sz
+    L.fcat_projections.argtypes = [gp, pp, sp, scp, psp, st, sup, nzp, vp, vp, sz, vp]
+    L.fcat_projections.restype = st
     L.fcat_timing_enable.argtypes = [C.c_int]
     L.fcat_timing_enable.restype = st
     L.fcat_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int]
@@ -465,6 +485,110 @@ def fcat_timing_read(reset: bool = True) -> dict:
     cnt = (C.c_int64 * n)()
     _check(load().fcat_timing_read(ms, cnt, n, 1 if reset else 0))
     return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+# ------------------------------------------------- noise and projections
+
+@dataclass
+class Noise:
+    """Eq. 5 noise: H = counts_per_pixel flood counts per open pixel."""
+    counts_per_pixel: float
+    seed: int = 0
+    floor: float = 0.0
+
+    def c(self) -> _CNoise:
+        return _CNoise(float(self.counts_per_pixel), int(self.seed) & 0xFFFFFFFFFFFFFFFF, float(self.floor))
+
+
+def fcat_count_scale(spectral: Spectral, counts_per_pixel: float, out=None, stream=None):
+    """c_g = H Phi_g / (Phi W_g) as a device float tensor [G]."""
+    torch = _require_gpu()
+    if out is None:
+        out = torch.empty(spectral.n_groups, dtype=torch.float32, device=spectral.mu.device)
+    cs, _keep = spectral.c()
+    _check(load().fcat_count_scale(C.byref(cs), float(counts_per_pixel), _ptr(out), _stream(stream)))
+    return out
+
+
+def fcat_poisson(Y, scale, seed: int, angle_base: int = 0, stream=None):
+    """In place: Y[a][g][...] <- Poisson(scale[g] Y) / scale[g] for float32 Y [A][G][plane...]."""
+    _require_gpu()
+    A, G = int(Y.shape[0]), int(Y.shape[1])
+    plane = int(Y[0, 0].numel()) if A > 0 else int(math.prod(Y.shape[2:]))
+    _check(load().fcat_poisson(_ptr(Y), A, G, plane, _ptr(scale), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               int(angle_base), _stream(stream)))
+    return Y
+
+
+def fcat_flood_workspace_bytes(spectral: Spectral, nv: int, nu: int) -> int:
+    cs, _keep = spectral.c()
+    return int(load().fcat_flood_workspace_bytes(C.byref(cs), int(nv), int(nu)))
+
+
+def fcat_flood_profile(spectral: Spectral, psf: Optional[Psf], nv: int, nu: int, out=None, workspace=None,
+                       stream=None):
+    """Noiseless object-free flood through the spread, [nv][nu]."""
+    torch = _require_gpu()
+    dev = spectral.mu.device
+    if out is None:
+        out = torch.empty((nv, nu), dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = _workspace(fcat_flood_workspace_bytes(spectral, nv, nu), dev)
+    cs, _keep = spectral.c()
+    ps = psf.c() if psf is not None else None
+    _check(load().fcat_flood_profile(C.byref(cs), C.byref(ps) if ps is not None else None, int(nv), int(nu),
+                                     _ptr(out), _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                                     _stream(stream)))
+    return out
+
+
+def fcat_log_projection(out, flood, floor: float = 0.0, proj=None, stream=None):
+    """-ln(max(out, floor) / flood) for out [A][plane...], flood [plane...]."""
+    torch = _require_gpu()
+    A = int(out.shape[0])
+    plane = int(flood.numel())
+    if proj is None:
+        proj = torch.empty_like(out)
+    _check(load().fcat_log_projection(_ptr(out), _ptr(flood), A, plane, float(floor), _ptr(proj),
+                                      _stream(stream)))
+    return proj
+
+
+def fcat_projections_workspace_bytes(pb: Problem, mode: str = "plain", angles_per_chunk: int = 0) -> int:
+    cs, _keep = pb.spectral.c()
+    g, p = pb.geometry.c(), pb.phantom.c()
+    sc = pb.scatter.c() if pb.scatter else None
+    ps = pb.psf.c() if pb.psf else None
+    return int(load().fcat_projections_workspace_bytes(C.byref(g), C.byref(p), C.byref(cs),
+                                                       C.byref(sc) if sc is not None else None,
+                                                       C.byref(ps) if ps is not None else None,
+                                                       MODES[mode], int(angles_per_chunk)))
+
+
+def fcat_projections(pb: Problem, noise: Optional[Noise] = None, mode: str = "plain", surrogate=None, out=None,
+                     workspace=None, angles_per_chunk: int = 0, stream=None):
+    """Projections -ln(out / flood) of all angles, with Poisson noise when ``noise`` is given."""
+    torch = _require_gpu()
+    lib = load()
+    g = pb.geometry
+    dev = pb.phantom.labels.device
+    if out is None:
+        out = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = _workspace(fcat_projections_workspace_bytes(pb, mode, angles_per_chunk), dev)
+    cs, _keep = pb.spectral.c()
+    cg, cp = g.c(), pb.phantom.c()
+    sc = pb.scatter.c() if pb.scatter else None
+    ps = pb.psf.c() if pb.psf else None
+    su = surrogate.c() if surrogate is not None else None
+    nz = noise.c() if noise is not None else None
+    st = lib.fcat_projections(C.byref(cg), C.byref(cp), C.byref(cs), C.byref(sc) if sc is not None else None,
+                              C.byref(ps) if ps is not None else None, MODES[mode],
+                              C.byref(su) if su is not None else None, C.byref(nz) if nz is not None else None,
+                              _ptr(out), _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                              _stream(stream))
+    _check(st)
+    return out
 
 
 # ------------------------------------------------------------- surrogate

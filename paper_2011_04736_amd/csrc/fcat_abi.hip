@@ -174,6 +174,7 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 
 struct Layout {
     size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, Y, Lbuf, fixed;
+    size_t scale, unitk, flood, yflood;   // projection stage: c_g, unit kernels, flood, its group signals
     size_t per_angle;    // bytes of per-angle chunk buffers (group signals, path lengths)
     size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
 };
@@ -192,7 +193,7 @@ void split_host(const SpecTables &t, SplitTables &sp)
 }
 
 Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size_t nbricks = 0,
-              const SplitTables *sp = nullptr, bool surrogate = false, int psf_split_k = 0)
+              const SplitTables *sp = nullptr, bool surrogate = false, int psf_split_k = 0, bool proj = false)
 {
     Layout L{};
     size_t o = 0;
@@ -218,6 +219,15 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (surrogate) o += align_up((size_t)FCAT_MLP_MAX_IO * sizeof(float));
     L.bricks = o;
     o += align_up(nbricks);
+    const size_t plane = g ? (size_t)g->nu * g->nv : 0;
+    L.scale = o;
+    if (proj) o += align_up((size_t)t.G * sizeof(float));
+    L.unitk = o;
+    if (proj) o += align_up((size_t)t.G * sizeof(float));
+    L.flood = o;
+    if (proj) o += align_up(plane * sizeof(float));
+    L.yflood = o;
+    if (proj) o += align_up((size_t)t.G * plane * sizeof(float));
     L.fixed = o;
     L.y_per_angle = (with_psf && g) ? align_up((size_t)t.G * g->nu * g->nv * sizeof(float)) : 0;
     const size_t l_per_angle = (surrogate && g) ? align_up((size_t)t.M * g->nu * g->nv * sizeof(float)) : 0;
@@ -440,46 +450,80 @@ static int psf_split_k(const fcat_psf_t *psf, fcat_mode mode)
     return (psf && mode == FCAT_MODE_SPLIT_BF16 && psf->k <= kPsfSplitMaxK) ? psf->k : 0;
 }
 
-size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
-                                    const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
-                                    const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk)
+// Workspace of the projector; proj adds the projection stage, noisy the
+// group signals it needs even without the optical spread.
+static size_t project_ws_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                               const fcat_spectral_t *spectral, const fcat_psf_t *psf, fcat_mode mode,
+                               int32_t angles_per_chunk, bool proj, bool noisy)
 {
-    (void)scatter;
     SpecTables t{};
     if (check_geometry(geometry) || check_phantom(phantom) || check_spectral(spectral, false, t) ||
         check_psf(psf))
         return 0;
     SplitTables sp{};
     split_host(t, sp);
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), mode == FCAT_MODE_SPLIT_BF16 ? &sp : nullptr,
-                      mode == FCAT_MODE_SURROGATE, psf_split_k(psf, mode));
+    Layout L = layout(t, geometry, psf != nullptr || noisy, brick_bytes(phantom),
+                      mode == FCAT_MODE_SPLIT_BF16 ? &sp : nullptr, mode == FCAT_MODE_SURROGATE,
+                      psf_split_k(psf, mode), proj);
     int chunk = angles_per_chunk > 0 ? angles_per_chunk : default_chunk(L, geometry->n_angles);
     if (chunk > geometry->n_angles) chunk = geometry->n_angles;
     return L.fixed + (size_t)chunk * L.per_angle;
 }
 
-fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
-                         const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
-                         const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
-                         float *out, void *workspace, size_t workspace_bytes, void *stream_)
+size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                    const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                                    const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk)
 {
-    g_last_error.clear();
+    (void)scatter;
+    return project_ws_bytes(geometry, phantom, spectral, psf, mode, angles_per_chunk, false, false);
+}
+
+size_t fcat_projections_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                        const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                                        const fcat_psf_t *psf, fcat_mode mode, int32_t angles_per_chunk)
+{
+    (void)scatter;
+    // sized for the noisy case, which needs the most
+    return project_ws_bytes(geometry, phantom, spectral, psf, mode, angles_per_chunk, true, true);
+}
+
+static fcat_status check_noise(const fcat_noise_t *n)
+{
+    if (!n) return FCAT_OK;
+    if (!(n->counts_per_pixel > 0.0) || !std::isfinite(n->counts_per_pixel))
+        return fail(FCAT_E_INVALID_ARG, "counts_per_pixel must be finite and > 0");
+    if (!(n->floor >= 0.0f) || !std::isfinite(n->floor)) return fail(FCAT_E_INVALID_ARG, "floor must be finite and >= 0");
+    return FCAT_OK;
+}
+
+// The projector (fcat_project) and, with proj, the noise and projection
+// stage after it (fcat_projections): out then receives projections.
+static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                                const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
+                                bool proj, const fcat_noise_t *noise, float *out, void *workspace,
+                                size_t workspace_bytes, void *stream_)
+{
     SpecTables t{};
     fcat_status s;
     if ((s = check_geometry(geometry)) || (s = check_phantom(phantom)) ||
-        (s = check_spectral(spectral, true, t)) || (s = check_psf(psf)))
+        (s = check_spectral(spectral, true, t)) || (s = check_psf(psf)) || (s = check_noise(noise)))
         return s;
-    if (!out) return fail(FCAT_E_INVALID_ARG, "out is NULL");
+    if (!out) return fail(FCAT_E_INVALID_ARG, "output is NULL");
     if (scatter && !scatter->maps) return fail(FCAT_E_INVALID_ARG, "scatter maps is NULL");
     if (mode != FCAT_MODE_PLAIN && mode != FCAT_MODE_SPLIT_BF16 && mode != FCAT_MODE_SURROGATE)
         return fail(FCAT_E_INVALID_ARG, "unknown mode %d", (int)mode);
     const bool split = mode == FCAT_MODE_SPLIT_BF16;
     const bool sur = mode == FCAT_MODE_SURROGATE;
+    const bool noisy = proj && noise != nullptr;
+    const bool grouped = psf != nullptr || noisy;   // group signals pass through the workspace
     if (sur && (s = check_surrogate(surrogate, t, true))) return s;
+    const int64_t plane = (int64_t)geometry->nu * geometry->nv;
+    if (proj && plane >= ((int64_t)1 << 31)) return fail(FCAT_E_INVALID_ARG, "nu * nv must be < 2^31");
     SplitTables sp{};
     split_host(t, sp);
     const int pk = psf_split_k(psf, mode);
-    Layout L = layout(t, geometry, psf != nullptr, brick_bytes(phantom), split ? &sp : nullptr, sur, pk);
+    Layout L = layout(t, geometry, grouped, brick_bytes(phantom), split ? &sp : nullptr, sur, pk, proj);
     const size_t need = L.fixed + L.per_angle;  // at least one angle per chunk
     if ((s = check_workspace(workspace, workspace_bytes, need))) return s;
     if ((s = check_pending())) return s;
@@ -507,23 +551,54 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     }
     const float *S = scatter ? scatter->maps : nullptr;
     const int A = geometry->n_angles;
-    const int64_t plane = (int64_t)geometry->nu * geometry->nv;
     hipError_t e;
+    float *unitk = at<float>(workspace, L.unitk);
+    // optical spread and group sum of n angles of group signals (unit kernels without psf)
+    auto spread = [&](const float *Yc, int n, float *dst) {
+        StageTimer tm(FCAT_STAGE_PSF, stream);
+        if (pk) return launch_psf_split(Yc, n, t.G, geometry->nv, geometry->nu, pk, pfrag, dst, stream);
+        return launch_psf(Yc, n, t.G, geometry->nv, geometry->nu, psf ? psf->kernels : unitk, psf ? psf->k : 1, dst,
+                          stream);
+    };
+    float *scale = at<float>(workspace, L.scale);
+    float *flood = at<float>(workspace, L.flood);
+    const float floor_ = noise ? noise->floor : 0.0f;
+    if (proj) {
+        {
+            StageTimer tm(FCAT_STAGE_NOISE, stream);
+            e = noisy ? launch_count_scale(spectral->phi, spectral->eta, t.gstart, t.E, t.G, noise->counts_per_pixel,
+                                           scale, stream)
+                      : hipSuccess;
+            if (e == hipSuccess && !psf) e = launch_fill(unitk, t.G, 1.0f, stream);
+            if (e == hipSuccess)
+                e = launch_flood_groups(t.Wg, spectral->flood, plane, t.G, at<float>(workspace, L.yflood), stream);
+        }
+        if (e == hipSuccess) e = spread(at<float>(workspace, L.yflood), 1, flood);
+        if (e != hipSuccess) return device_fail(e, "flood profile");
+    }
+    auto to_projections = [&](float *o, int n) {
+        StageTimer tm(FCAT_STAGE_NOISE, stream);
+        return launch_log_projection(o, flood, n, plane, floor_, o, stream);
+    };
     auto rows = [&](int a0, int n, float *Yc, float *outc) {
         return split ? launch_project_rows_split(G, phantom->labels, t, sp, spectral->flood, S, a0, n, Yc, outc, stream)
                      : launch_project_rows(G, phantom->labels, t, spectral->flood, S, a0, n, Yc, outc, stream);
     };
     if (L.per_angle == 0) {
-        StageTimer tm(FCAT_STAGE_TRACE, stream);
-        e = rows(0, A, nullptr, out);
+        {
+            StageTimer tm(FCAT_STAGE_TRACE, stream);
+            e = rows(0, A, nullptr, out);
+        }
         if (e != hipSuccess) return device_fail(e, "project_rows");
+        if (proj && (e = to_projections(out, A)) != hipSuccess) return device_fail(e, "log_projection");
         return FCAT_OK;
     }
     const int chunk = (int)std::min<size_t>((size_t)A, (workspace_bytes - L.fixed) / L.per_angle);
-    float *Y = psf ? at<float>(workspace, L.Y) : nullptr;
+    float *Y = grouped ? at<float>(workspace, L.Y) : nullptr;
     float *Lbuf = sur ? at<float>(workspace, chunk_lbuf(L, chunk)) : nullptr;
     for (int a0 = 0; a0 < A; a0 += chunk) {
         const int n = std::min(chunk, A - a0);
+        float *outc = out + a0 * plane;
         if (sur) {
             {
                 StageTimer tm(FCAT_STAGE_TRACE, stream);
@@ -537,7 +612,7 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
             io.flood = spectral->flood;
             io.scatter = S ? S + a0 * plane : nullptr;
             io.Y = Y;
-            io.out = psf ? nullptr : out + a0 * plane;
+            io.out = grouped ? nullptr : outc;
             io.counts = surrogate->counts;
             io.force_mlp = 0;
             {
@@ -547,20 +622,140 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
             if (e != hipSuccess) return device_fail(e, "mlp_spectral");
         } else {
             StageTimer tm(FCAT_STAGE_TRACE, stream);
-            e = rows(a0, n, Y, psf ? nullptr : out);
+            e = rows(a0, n, Y, grouped ? nullptr : outc);
             if (e != hipSuccess) return device_fail(e, "project_rows");
         }
-        if (psf) {
-            {
-                StageTimer tm(FCAT_STAGE_PSF, stream);
-                e = pk ? launch_psf_split(Y, n, t.G, geometry->nv, geometry->nu, pk, pfrag, out + a0 * plane,
-                                          stream)
-                       : launch_psf(Y, n, t.G, geometry->nv, geometry->nu, psf->kernels, psf->k, out + a0 * plane,
-                                    stream);
-            }
-            if (e != hipSuccess) return device_fail(e, "psf");
+        if (noisy) {
+            StageTimer tm(FCAT_STAGE_NOISE, stream);
+            e = launch_poisson(Y, n, t.G, plane, scale, noise->seed, a0, stream);
+            if (e != hipSuccess) return device_fail(e, "poisson");
         }
+        if (grouped && (e = spread(Y, n, outc)) != hipSuccess) return device_fail(e, "psf");
+        if (proj && (e = to_projections(outc, n)) != hipSuccess) return device_fail(e, "log_projection");
     }
+    return FCAT_OK;
+}
+
+fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                         const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                         const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
+                         float *out, void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    return project_impl(geometry, phantom, spectral, scatter, psf, mode, surrogate, false, nullptr, out, workspace,
+                        workspace_bytes, stream);
+}
+
+fcat_status fcat_projections(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                             const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
+                             const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
+                             const fcat_noise_t *noise, float *proj, void *workspace, size_t workspace_bytes,
+                             void *stream)
+{
+    g_last_error.clear();
+    return project_impl(geometry, phantom, spectral, scatter, psf, mode, surrogate, true, noise, proj, workspace,
+                        workspace_bytes, stream);
+}
+
+fcat_status fcat_count_scale(const fcat_spectral_t *spectral, double counts_per_pixel, float *scale, void *stream)
+{
+    g_last_error.clear();
+    SpecTables t{};
+    fcat_status s;
+    if ((s = check_spectral(spectral, false, t))) return s;
+    if (!spectral->phi || !spectral->eta) return fail(FCAT_E_INVALID_ARG, "phi and eta must not be NULL");
+    if (!scale) return fail(FCAT_E_INVALID_ARG, "scale is NULL");
+    if (!(counts_per_pixel > 0.0) || !std::isfinite(counts_per_pixel))
+        return fail(FCAT_E_INVALID_ARG, "counts_per_pixel must be finite and > 0");
+    if ((s = check_pending())) return s;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_NOISE, static_cast<hipStream_t>(stream));
+        e = launch_count_scale(spectral->phi, spectral->eta, t.gstart, t.E, t.G, counts_per_pixel, scale,
+                               static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return device_fail(e, "count_scale");
+    return FCAT_OK;
+}
+
+fcat_status fcat_poisson(float *Y, int32_t n_ang, int32_t n_groups, int64_t plane, const float *scale,
+                         uint64_t seed, int32_t angle_base, void *stream)
+{
+    g_last_error.clear();
+    if (n_ang < 0 || n_groups < 1 || n_groups > FCAT_MAX_GROUPS || plane < 0 || plane >= ((int64_t)1 << 31))
+        return fail(FCAT_E_INVALID_ARG, "need n_ang >= 0, 1 <= n_groups <= %d, 0 <= plane < 2^31", FCAT_MAX_GROUPS);
+    if (angle_base < 0) return fail(FCAT_E_INVALID_ARG, "angle_base must be >= 0");
+    if ((int64_t)n_ang * plane > 0 && (!Y || !scale)) return fail(FCAT_E_INVALID_ARG, "Y and scale must not be NULL");
+    fcat_status s;
+    if ((s = check_pending())) return s;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_NOISE, static_cast<hipStream_t>(stream));
+        e = launch_poisson(Y, n_ang, n_groups, plane, scale, seed, angle_base, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return device_fail(e, "poisson");
+    return FCAT_OK;
+}
+
+size_t fcat_flood_workspace_bytes(const fcat_spectral_t *spectral, int32_t nv, int32_t nu)
+{
+    SpecTables t{};
+    if (check_spectral(spectral, false, t) || nv < 1 || nu < 1) return 0;
+    fcat_geometry_t g{};
+    g.nu = nu;
+    g.nv = nv;
+    return layout(t, &g, false, 0, nullptr, false, 0, true).fixed;
+}
+
+fcat_status fcat_flood_profile(const fcat_spectral_t *spectral, const fcat_psf_t *psf, int32_t nv, int32_t nu,
+                               float *flood, void *workspace, size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    SpecTables t{};
+    fcat_status s;
+    if ((s = check_spectral(spectral, true, t)) || (s = check_psf(psf))) return s;
+    if (nv < 1 || nu < 1) return fail(FCAT_E_INVALID_ARG, "nv and nu must be >= 1");
+    if (!flood) return fail(FCAT_E_INVALID_ARG, "flood is NULL");
+    fcat_geometry_t g{};
+    g.nu = nu;
+    g.nv = nv;
+    Layout L = layout(t, &g, false, 0, nullptr, false, 0, true);
+    if ((s = check_workspace(workspace, workspace_bytes, L.fixed))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((s = prep_tables(spectral, nullptr, t, L, workspace, stream))) return s;
+    float *unitk = at<float>(workspace, L.unitk);
+    float *yf = at<float>(workspace, L.yflood);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_NOISE, stream);
+        e = psf ? hipSuccess : launch_fill(unitk, t.G, 1.0f, stream);
+        if (e == hipSuccess) e = launch_flood_groups(t.Wg, spectral->flood, (int64_t)nv * nu, t.G, yf, stream);
+    }
+    if (e == hipSuccess) {
+        StageTimer tm(FCAT_STAGE_PSF, stream);
+        e = launch_psf(yf, 1, t.G, nv, nu, psf ? psf->kernels : unitk, psf ? psf->k : 1, flood, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "flood profile");
+    return FCAT_OK;
+}
+
+fcat_status fcat_log_projection(const float *out, const float *flood, int32_t n_ang, int64_t plane, float floor,
+                                float *proj, void *stream)
+{
+    g_last_error.clear();
+    if (n_ang < 0 || plane < 0) return fail(FCAT_E_INVALID_ARG, "n_ang and plane must be >= 0");
+    if (!(floor >= 0.0f) || !std::isfinite(floor)) return fail(FCAT_E_INVALID_ARG, "floor must be finite and >= 0");
+    if ((int64_t)n_ang * plane > 0 && (!out || !flood || !proj))
+        return fail(FCAT_E_INVALID_ARG, "out, flood and proj must not be NULL");
+    fcat_status s;
+    if ((s = check_pending())) return s;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_NOISE, static_cast<hipStream_t>(stream));
+        e = launch_log_projection(out, flood, n_ang, plane, floor, proj, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return device_fail(e, "log_projection");
     return FCAT_OK;
 }
 

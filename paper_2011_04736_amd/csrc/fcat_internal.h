@@ -176,6 +176,19 @@ hipError_t launch_prep_psf_split(const float *kernels, int G, int k, uint4 *frag
 hipError_t launch_psf_split(const float *Y, int n_ang, int G, int nv, int nu, int k, const uint4 *frag, float *out,
                             hipStream_t stream);
 
+// Noise and projection stage (fcat_noise.hip).  Poisson counts on the
+// group signals of n_ang angles (Y [n_ang][G][plane], in place), the count
+// scale of Eq. 5 per group, the flood's group signals W_g I0, and
+// proj = -ln(max(out, floor) / flood).
+hipError_t launch_poisson(float *Y, int n_ang, int G, int64_t plane, const float *scale, uint64_t seed,
+                          int angle_base, hipStream_t stream);
+hipError_t launch_count_scale(const float *phi, const float *eta, const int *gstart, int E, int G, double H,
+                              float *scale, hipStream_t stream);
+hipError_t launch_flood_groups(const float *Wg, const float *i0, int64_t plane, int G, float *Yf, hipStream_t stream);
+hipError_t launch_log_projection(const float *out, const float *flood, int n_ang, int64_t plane, float floor_,
+                                 float *proj, hipStream_t stream);
+hipError_t launch_fill(float *x, int n, float v, hipStream_t stream);
+
 hipError_t launch_check_labels(const int8_t *labels, int64_t n, int n_mat, int *flag,
                                hipStream_t stream);
 hipError_t launch_check_finite(const float *x, int64_t n, int *flag, hipStream_t stream);
