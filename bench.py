@@ -10,8 +10,10 @@ Prints one JSON line: rays x energy-bins per second of the plain FP32 form,
 the roofline of the dominant kernel (timed live with HIP events on the
 library's stream), the two other forms of the projector (BF16 hi/lo split on
 the same workload; the learned surrogate on the head workload, trained here
-by the library's own kernels) with their error against the plain form, and
-the FP64 oracle timed on the host on a bounded sample of the workload.
+by the library's own kernels) with their error against the plain form, the
+noise and projection stage after the projector (Poisson counts of Eq. 5,
+log conversion through the flood) on the same workload, and the FP64 oracle
+timed on the host on a bounded sample of the workload.
 """
 import argparse
 import hashlib
@@ -45,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-angles", type=int, default=360,
                     help="angles of the workload the FP64 oracle is timed on (0: skip)")
     ap.add_argument("--variant", default="", help="'z' for the 1.5625 mm slab variant")
+    ap.add_argument("--noise-counts", type=float, default=1.0e5,
+                    help="H of Eq. 5 (flood counts per open pixel) for the noise stage; 0 skips it")
     ap.add_argument("--forms", default="split_bf16,surrogate",
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
@@ -101,6 +105,7 @@ def source_digest(files) -> str:
 
 
 TRACE_SOURCES = ["fcat_kernels.hip", "fcat_device.h", "fcat_internal.h"]
+NOISE_SOURCES = ["fcat_noise.hip", "fcat_internal.h"]
 
 
 def profiled_traffic(kernel: str, digest: str):
@@ -118,6 +123,39 @@ def profiled_traffic(kernel: str, digest: str):
 
 
 # ----------------------------------------------------------------- forms
+
+def noise_stage(pb, cfg, args, torch, fc):
+    """Projections with Poisson noise (Eq. 5) on the same workload: the whole
+    fcat_projections call per step, and the roofline of the Poisson kernel
+    (4 B read and 4 B written per draw, one draw per pixel, group and angle)."""
+    g, s = cfg.geometry, cfg.spectral
+    proj = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=pb.phantom.labels.device)
+    ws = torch.empty(fc.fcat_projections_workspace_bytes(pb, "plain"), dtype=torch.uint8, device=proj.device)
+    noise = fc.Noise(counts_per_pixel=args.noise_counts, seed=2011)
+    stream = torch.cuda.current_stream()
+    elapsed, stages = timed_steps(lambda: fc.fcat_projections(pb, noise, out=proj, workspace=ws, stream=stream),
+                                  1, args.form_steps, torch)
+    draws = g.n_angles * s.n_groups * g.nu * g.nv
+    nz_ms, nz_n = stages["noise"]
+    per_launch = draws / max(nz_n / args.form_steps, 1)
+    avg = nz_ms / max(nz_n, 1)
+    ach = 8.0 * per_launch / (avg * 1e-3) / 1e9
+    finite = bool(torch.isfinite(proj).all().item())
+    del ws, proj
+    return {
+        "ms_per_step": round(1e3 * elapsed / args.form_steps, 4),
+        "steps": args.form_steps,
+        "counts_per_pixel": args.noise_counts,
+        "draws_per_step": draws,
+        "draws_per_s": per_launch / (avg * 1e-3),
+        "stages_ms_per_step": {k: round(v[0] / args.form_steps, 4) for k, v in stages.items() if v[1]},
+        "finite": finite,
+        "roofline": {"kernel": "k_poisson", "bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBPS, 4), "avg_launch_ms": round(avg, 4),
+                     "algorithmic_bytes_per_launch": 8.0 * per_launch,
+                     "traffic": profiled_traffic("k_poisson", source_digest(NOISE_SOURCES))},
+    }
+
 
 def timed_steps(fn, warmup, steps, torch):
     for _ in range(warmup):
@@ -326,7 +364,11 @@ def main():
     result["forms"] = {}
     if "split_bf16" in forms:
         result["forms"]["split_bf16"] = form_split(pb, cfg, out, args, torch, fc)
-    del ws, out, pb
+    del ws, out
+    torch.cuda.empty_cache()
+    if args.noise_counts > 0:
+        result["next"] = {"noise_and_projections": noise_stage(pb, cfg, args, torch, fc)}
+    del pb
     torch.cuda.empty_cache()
     if "surrogate" in forms:
         result["forms"]["surrogate"] = form_surrogate(args, torch, fc)

@@ -421,8 +421,9 @@ typedef enum fcat_stage {
     FCAT_STAGE_TRACE = 1,  /* fused traversal + contraction + spectral sum (+ scatter) */
     FCAT_STAGE_PSF = 2,    /* optical spread + group sum */
     FCAT_STAGE_MLP = 3,    /* surrogate training / inference kernels run on their own */
-    FCAT_STAGE_NOISE = 4,  /* count scale, Poisson draws, flood profile and log conversion */
-    FCAT_STAGE_COUNT = 5
+    FCAT_STAGE_NOISE = 4,  /* Poisson draws */
+    FCAT_STAGE_PROJ = 5,   /* count scale, flood profile and log conversion */
+    FCAT_STAGE_COUNT = 6
 } fcat_stage;
 
 /*

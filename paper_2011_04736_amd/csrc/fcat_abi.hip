@@ -565,7 +565,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     const float floor_ = noise ? noise->floor : 0.0f;
     if (proj) {
         {
-            StageTimer tm(FCAT_STAGE_NOISE, stream);
+            StageTimer tm(FCAT_STAGE_PROJ, stream);
             e = noisy ? launch_count_scale(spectral->phi, spectral->eta, t.gstart, t.E, t.G, noise->counts_per_pixel,
                                            scale, stream)
                       : hipSuccess;
@@ -577,7 +577,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
         if (e != hipSuccess) return device_fail(e, "flood profile");
     }
     auto to_projections = [&](float *o, int n) {
-        StageTimer tm(FCAT_STAGE_NOISE, stream);
+        StageTimer tm(FCAT_STAGE_PROJ, stream);
         return launch_log_projection(o, flood, n, plane, floor_, o, stream);
     };
     auto rows = [&](int a0, int n, float *Yc, float *outc) {
@@ -670,7 +670,7 @@ fcat_status fcat_count_scale(const fcat_spectral_t *spectral, double counts_per_
     if ((s = check_pending())) return s;
     hipError_t e;
     {
-        StageTimer tm(FCAT_STAGE_NOISE, static_cast<hipStream_t>(stream));
+        StageTimer tm(FCAT_STAGE_PROJ, static_cast<hipStream_t>(stream));
         e = launch_count_scale(spectral->phi, spectral->eta, t.gstart, t.E, t.G, counts_per_pixel, scale,
                                static_cast<hipStream_t>(stream));
     }
@@ -728,7 +728,7 @@ fcat_status fcat_flood_profile(const fcat_spectral_t *spectral, const fcat_psf_t
     float *yf = at<float>(workspace, L.yflood);
     hipError_t e;
     {
-        StageTimer tm(FCAT_STAGE_NOISE, stream);
+        StageTimer tm(FCAT_STAGE_PROJ, stream);
         e = psf ? hipSuccess : launch_fill(unitk, t.G, 1.0f, stream);
         if (e == hipSuccess) e = launch_flood_groups(t.Wg, spectral->flood, (int64_t)nv * nu, t.G, yf, stream);
     }
@@ -752,7 +752,7 @@ fcat_status fcat_log_projection(const float *out, const float *flood, int32_t n_
     if ((s = check_pending())) return s;
     hipError_t e;
     {
-        StageTimer tm(FCAT_STAGE_NOISE, static_cast<hipStream_t>(stream));
+        StageTimer tm(FCAT_STAGE_PROJ, static_cast<hipStream_t>(stream));
         e = launch_log_projection(out, flood, n_ang, plane, floor, proj, static_cast<hipStream_t>(stream));
     }
     if (e != hipSuccess) return device_fail(e, "log_projection");
