@@ -245,6 +245,31 @@ def detector_response(rng: np.random.Generator, energies: np.ndarray, e_ref: flo
     return np.clip(eta, 1e-6, 1.0).astype(np.float32)
 
 
+def energy_absorption_ratio(rng: np.random.Generator, energies: np.ndarray, e_ref: float) -> np.ndarray:
+    """A smooth water-like mu_en/mu(E) in (0, 1): high where absorption
+    dominates at low energy, a dip in the Compton range, a slow rise above
+    (made up for this synthetic stand-in; no database values)."""
+    x = np.log(energies / e_ref)
+    dip = rng.uniform(0.12, 0.2)
+    width = rng.uniform(1.0, 1.6)
+    low = 1.0 / (1.0 + np.exp(3.0 * (x + rng.uniform(0.8, 1.2))))
+    rise = 0.55 / (1.0 + np.exp(-(x - rng.uniform(2.0, 3.0)) / width))
+    r = dip + (0.9 - dip) * low + rise
+    return np.clip(r, 0.05, 0.99).astype(np.float32)
+
+
+def material_densities(names: Sequence[str]) -> np.ndarray:
+    """Relative densities (g/cm^3) of the synthetic tissues, float64 [M]."""
+    return np.array([_TISSUES[n][0] for n in names], dtype=np.float64)
+
+
+def phantom_mass_kg(phantom: "Phantom", densities: np.ndarray) -> float:
+    """Mass of the labelled phantom: voxel counts x density x voxel volume."""
+    counts = np.bincount(phantom.labels.reshape(-1).astype(np.int64), minlength=densities.size)
+    vox_cm3 = phantom.dx * phantom.dy * phantom.dz * 1e-3
+    return float((counts[:densities.size] * densities).sum() * vox_cm3 * 1e-3)
+
+
 def contiguous_groups(n_energy: int, n_groups: int) -> np.ndarray:
     """group_of_bin[e] = floor(e*G/E)."""
     return (np.arange(n_energy, dtype=np.int64) * n_groups // n_energy).astype(np.int32)
