@@ -328,6 +328,31 @@ fcat_status fcat_projections(const fcat_geometry_t *geometry, const fcat_phantom
                              const fcat_noise_t *noise, float *proj, void *workspace, size_t workspace_bytes,
                              void *stream);
 
+/* ------------------------------------------------------------------ dose */
+/*
+ * Dose per particle (Sec. II.H, Eqs. 6-7) from the rays of angles
+ * a_begin <= a < a_end, every detector pixel a ray (hit or not; N_i counts
+ * them all):
+ *   D0[e] = E_e (mu_en/mu)_e / (N_i M) sum_i (1 - exp(-P_i(e))),
+ *           P_i(e) = sum_m mu[m][e] L_i,m  (the ray's projection; for a water
+ *           phantom mu_water(E) x_i as in Eq. 6),
+ *   Dp    = sum_e phi_e D0[e].
+ * energy (E_e, any unit) and mu_en_over_mu ((mu_en/mu)_e of water, the
+ * phantom's absorption standing in for the paper's water) are DEVICE float
+ * [n_energy]; mass M > 0 in any unit: D0 is in energy units per mass unit
+ * per particle.  D0 is DEVICE double [n_energy]; Dp DEVICE double [1] or
+ * NULL.  Sums run in FP64 in a fixed order (deterministic for a given
+ * workspace).  The paper's empirical fit to Monte Carlo doses, and the
+ * number of particles a requested dose implies (dose / Dp, then Eq. 5 for
+ * the noise), are left to the caller.
+ */
+size_t fcat_dose_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                 const fcat_spectral_t *spectral, int32_t angles_per_chunk);
+fcat_status fcat_dose(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                      const fcat_spectral_t *spectral, const float *energy, const float *mu_en_over_mu,
+                      double mass, int32_t a_begin, int32_t a_end, double *D0, double *Dp, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------ surrogate */
 /*
  * The learned form of the primary spectral sum (see fcat_surrogate_t).  The
@@ -423,7 +448,8 @@ typedef enum fcat_stage {
     FCAT_STAGE_MLP = 3,    /* surrogate training / inference kernels run on their own */
     FCAT_STAGE_NOISE = 4,  /* Poisson draws */
     FCAT_STAGE_PROJ = 5,   /* count scale, flood profile and log conversion */
-    FCAT_STAGE_COUNT = 6
+    FCAT_STAGE_DOSE = 6,   /* dose sums over rays and bins */
+    FCAT_STAGE_COUNT = 7
 } fcat_stage;
 
 /*

@@ -24,19 +24,23 @@ from __future__ import annotations
 import numpy as np
 
 
-def dose_per_particle(L, mu, energies, mu_en_over_mu, phi, mass):
-    """D_0[E] (Eq. 6) and D_p (Eq. 7) from path lengths L [..., M] of all rays.
+def dose_per_particle(L, mu, energies, mu_en_over_mu, phi, mass, n_rays=None):
+    """D_0[E] (Eq. 6) and D_p (Eq. 7) from path lengths L [..., M] of the rays.
 
-    mu [M][E]; energies, mu_en_over_mu, phi [E]; mass > 0.
+    mu [M][E]; energies, mu_en_over_mu, phi [E]; mass > 0.  n_rays (N_i)
+    defaults to the number of rays in L; a larger value stands for rays left
+    out of L because they miss the phantom (L = 0 adds exactly 0).
     """
     L = np.asarray(L, np.float64)
     n_mat = L.shape[-1]
     L2 = L.reshape(-1, n_mat)
-    n_rays = L2.shape[0]
+    n_rays = L2.shape[0] if n_rays is None else int(n_rays)
     mu = np.asarray(mu, np.float64)
-    P = L2 @ mu                                   # [rays][E]: projection per ray and energy
-    interacting = -np.expm1(-P)                   # 1 - exp(-P)
+    S = np.zeros(mu.shape[1])
+    for r0 in range(0, L2.shape[0], 1 << 16):     # blocks of rays, to bound memory
+        P = L2[r0:r0 + (1 << 16)] @ mu            # [rays][E]: projection per ray and energy
+        S += (-np.expm1(-P)).sum(axis=0)          # 1 - exp(-P)
     per_photon = np.asarray(energies, np.float64) * np.asarray(mu_en_over_mu, np.float64)
-    D0 = per_photon * interacting.sum(axis=0) / (n_rays * float(mass))
+    D0 = per_photon * S / (n_rays * float(mass))
     Dp = float((np.asarray(phi, np.float64) * D0).sum())
     return D0, Dp

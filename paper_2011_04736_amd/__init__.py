@@ -36,7 +36,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfcat.so")
 MODES = {"plain": 0, "split_bf16": 1, "surrogate": 2}
-STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj")
+STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose")
 _lib = None
 
 
@@ -168,6 +168,10 @@ def load() -> C.CDLL:
     L.fcat_projections_workspace_bytes.restype = sz
     L.fcat_projections.argtypes = [gp, pp, sp, scp, psp, st, sup, nzp, vp, vp, sz, vp]
     L.fcat_projections.restype = st
+    L.fcat_dose_workspace_bytes.argtypes = [gp, pp, sp, C.c_int32]
+    L.fcat_dose_workspace_bytes.restype = sz
+    L.fcat_dose.argtypes = [gp, pp, sp, vp, vp, C.c_double, C.c_int32, C.c_int32, vp, vp, vp, sz, vp]
+    L.fcat_dose.restype = st
     L.fcat_timing_enable.argtypes = [C.c_int]
     L.fcat_timing_enable.restype = st
     L.fcat_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int]
@@ -589,6 +593,34 @@ def fcat_projections(pb: Problem, noise: Optional[Noise] = None, mode: str = "pl
                               _stream(stream))
     _check(st)
     return out
+
+
+# ------------------------------------------------------------------ dose
+
+def fcat_dose_workspace_bytes(pb: Problem, angles_per_chunk: int = 0) -> int:
+    cs, _keep = pb.spectral.c()
+    g, p = pb.geometry.c(), pb.phantom.c()
+    return int(load().fcat_dose_workspace_bytes(C.byref(g), C.byref(p), C.byref(cs), int(angles_per_chunk)))
+
+
+def fcat_dose(pb: Problem, energy, mu_en_over_mu, mass: float, a_begin: int = 0, a_end: Optional[int] = None,
+              workspace=None, angles_per_chunk: int = 0, stream=None):
+    """(D0 [E] float64 device tensor, Dp [1]) of Eqs. 6-7 over angles a_begin <= a < a_end."""
+    torch = _require_gpu()
+    g = pb.geometry
+    a_end = g.n_angles if a_end is None else a_end
+    dev = pb.phantom.labels.device
+    E = int(pb.spectral.mu.shape[1])
+    D0 = torch.empty(E, dtype=torch.float64, device=dev)
+    Dp = torch.empty(1, dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = _workspace(fcat_dose_workspace_bytes(pb, angles_per_chunk), dev)
+    cs, _keep = pb.spectral.c()
+    cg, cp = g.c(), pb.phantom.c()
+    _check(load().fcat_dose(C.byref(cg), C.byref(cp), C.byref(cs), _ptr(energy), _ptr(mu_en_over_mu), float(mass),
+                            int(a_begin), int(a_end), _ptr(D0), _ptr(Dp), _ptr(workspace),
+                            0 if workspace is None else workspace.numel(), _stream(stream)))
+    return D0, Dp
 
 
 # ------------------------------------------------------------- surrogate

@@ -657,6 +657,98 @@ fcat_status fcat_projections(const fcat_geometry_t *geometry, const fcat_phantom
                         workspace_bytes, stream);
 }
 
+// Workspace of fcat_dose: tables and bricks, then S [E], the workgroup
+// partials, and the path lengths of a chunk of angles.
+struct DoseLayout {
+    Layout base;
+    size_t S, partial, L, fixed, per_angle;
+};
+
+static DoseLayout dose_layout(const SpecTables &t, const fcat_geometry_t *g, const fcat_phantom_t *p)
+{
+    DoseLayout d{};
+    d.base = layout(t, nullptr, false, brick_bytes(p));
+    size_t o = d.base.fixed;
+    d.S = o;
+    o += align_up((size_t)t.E * sizeof(double));
+    d.partial = o;
+    o += align_up((size_t)kDoseBlocks * t.E * sizeof(double));
+    d.L = o;
+    d.fixed = o;
+    d.per_angle = (size_t)g->nu * g->nv * t.M * sizeof(float);
+    return d;
+}
+
+size_t fcat_dose_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                                 const fcat_spectral_t *spectral, int32_t angles_per_chunk)
+{
+    SpecTables t{};
+    if (check_geometry(geometry) || check_phantom(phantom) || check_spectral(spectral, false, t)) return 0;
+    const DoseLayout d = dose_layout(t, geometry, phantom);
+    size_t chunk = angles_per_chunk > 0 ? (size_t)angles_per_chunk : kDefaultChunkBytes / d.per_angle;
+    chunk = std::max<size_t>(1, std::min<size_t>(chunk, (size_t)geometry->n_angles));
+    return d.fixed + align_up(chunk * d.per_angle);
+}
+
+fcat_status fcat_dose(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
+                      const fcat_spectral_t *spectral, const float *energy, const float *mu_en_over_mu,
+                      double mass, int32_t a_begin, int32_t a_end, double *D0, double *Dp, void *workspace,
+                      size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    SpecTables t{};
+    fcat_status s;
+    if ((s = check_geometry(geometry)) || (s = check_phantom(phantom)) || (s = check_spectral(spectral, true, t)))
+        return s;
+    if (!energy || !mu_en_over_mu || !D0) return fail(FCAT_E_INVALID_ARG, "energy, mu_en_over_mu and D0 must not be NULL");
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(FCAT_E_INVALID_ARG, "mass must be finite and > 0");
+    if (a_begin < 0 || a_end > geometry->n_angles || a_begin >= a_end)
+        return fail(FCAT_E_INVALID_ARG, "need 0 <= a_begin < a_end <= n_angles");
+    const DoseLayout d = dose_layout(t, geometry, phantom);
+    if ((s = check_workspace(workspace, workspace_bytes, d.fixed + align_up(d.per_angle)))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if ((s = prep_tables(spectral, nullptr, t, d.base, workspace, stream))) return s;
+    TraceGeom G = make_geom(geometry, phantom);
+    G.bricks = at<int8_t>(workspace, d.base.bricks);
+    G.labels_bm = G.bricks + align_up(brick_count(phantom));
+    double *S = at<double>(workspace, d.S);
+    double *partial = at<double>(workspace, d.partial);
+    float *L = at<float>(workspace, d.L);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz,
+                                const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm), stream);
+        if (e == hipSuccess) e = launch_zero_doubles(S, t.E, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "dose set-up");
+    const int64_t plane = (int64_t)geometry->nu * geometry->nv;
+    const int chunk = (int)std::min<size_t>((size_t)(a_end - a_begin), (workspace_bytes - d.fixed) / d.per_angle);
+    for (int a0 = a_begin; a0 < a_end; a0 += chunk) {
+        const int n = std::min(chunk, a_end - a0);
+        {
+            StageTimer tm(FCAT_STAGE_TRACE, stream);
+            e = launch_pathlengths(G, phantom->labels, t.M, a0, n, L, stream);
+        }
+        if (e != hipSuccess) return device_fail(e, "pathlengths");
+        const int64_t rays = (int64_t)n * plane;
+        {
+            StageTimer tm(FCAT_STAGE_DOSE, stream);
+            e = launch_dose_rays(L, rays, t.M, t, partial, stream);
+            if (e == hipSuccess) e = launch_dose_sum(partial, dose_blocks(rays), t.E, S, stream);
+        }
+        if (e != hipSuccess) return device_fail(e, "dose sums");
+    }
+    const double n_rays = (double)(a_end - a_begin) * (double)plane;
+    {
+        StageTimer tm(FCAT_STAGE_DOSE, stream);
+        e = launch_dose_final(S, energy, mu_en_over_mu, spectral->phi, t.E, 1.0 / (n_rays * mass), D0, Dp, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "dose");
+    return FCAT_OK;
+}
+
 fcat_status fcat_count_scale(const fcat_spectral_t *spectral, double counts_per_pixel, float *scale, void *stream)
 {
     g_last_error.clear();

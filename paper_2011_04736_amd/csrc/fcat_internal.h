@@ -189,6 +189,19 @@ hipError_t launch_log_projection(const float *out, const float *flood, int n_ang
                                  float *proj, hipStream_t stream);
 hipError_t launch_fill(float *x, int n, float v, hipStream_t stream);
 
+// Dose estimate (fcat_dose.hip).  Per chunk of rays with path lengths L
+// [n_rays][M]: partial sums of 1 - exp(-P) per workgroup and energy bin
+// (dose_blocks(n_rays) x E doubles), then S[e] += their sum in a fixed order;
+// finally D0 and Dp from S.
+constexpr int kDoseBlocks = 2048;
+int dose_blocks(int64_t n_rays);
+hipError_t launch_dose_rays(const float *L, int64_t n_rays, int M, const SpecTables &t, double *partial,
+                            hipStream_t stream);
+hipError_t launch_dose_sum(const double *partial, int nblk, int E, double *S, hipStream_t stream);
+hipError_t launch_dose_final(const double *S, const float *energy, const float *ratio, const float *phi, int E,
+                             double inv_nm, double *D0, double *Dp, hipStream_t stream);
+hipError_t launch_zero_doubles(double *x, int n, hipStream_t stream);
+
 hipError_t launch_check_labels(const int8_t *labels, int64_t n, int n_mat, int *flag,
                                hipStream_t stream);
 hipError_t launch_check_finite(const float *x, int64_t n, int *flag, hipStream_t stream);
