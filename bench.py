@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--variant", default="", help="'z' for the 1.5625 mm slab variant")
     ap.add_argument("--noise-counts", type=float, default=1.0e5,
                     help="H of Eq. 5 (flood counts per open pixel) for the noise stage; 0 skips it")
+    ap.add_argument("--dose", type=int, default=1, help="1: time the dose estimate of Eqs. 6-7 (0 skips it)")
     ap.add_argument("--forms", default="split_bf16,surrogate",
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
@@ -106,6 +107,7 @@ def source_digest(files) -> str:
 
 TRACE_SOURCES = ["fcat_kernels.hip", "fcat_device.h", "fcat_internal.h"]
 NOISE_SOURCES = ["fcat_noise.hip", "fcat_internal.h"]
+DOSE_SOURCES = ["fcat_dose.hip", "fcat_internal.h"]
 
 
 def profiled_traffic(kernel: str, digest: str):
@@ -123,6 +125,47 @@ def profiled_traffic(kernel: str, digest: str):
 
 
 # ----------------------------------------------------------------- forms
+
+def dose_stage(pb, cfg, args, torch, fc, hit_rays):
+    """Dose per particle (Eqs. 6-7) over all angles of the workload: the walk
+    writes path lengths, k_dose_rays sums 1 - exp(-P) per bin over the rays
+    that meet the phantom (M FMAs, the negated expm1 as a transcendental of
+    EXP_SLOTS and two operations more per hit ray and bin)."""
+    import synth
+    s = cfg.spectral
+    ratio = synth.energy_absorption_ratio(np.random.default_rng(2011), s.energies, 1.0)
+    energy = torch.as_tensor(s.energies.astype(np.float32)).cuda()
+    ratio = torch.as_tensor(ratio).cuda()
+    mass = synth.phantom_mass_kg(cfg.phantom, synth.material_densities(s.material_names))
+    ws = torch.empty(fc.fcat_dose_workspace_bytes(pb), dtype=torch.uint8, device=energy.device)
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def step():
+        res["d"] = fc.fcat_dose(pb, energy, ratio, mass, workspace=ws, stream=stream)
+
+    elapsed, stages = timed_steps(step, 1, args.form_steps, torch)
+    dose_ms, dose_n = stages["dose"]
+    # the dose stage launches k_dose_rays and k_dose_sum per chunk and k_dose_final once;
+    # the kernel-trace summary gives k_dose_rays alone, the stage time bounds it from above
+    ops = hit_rays * s.n_energy * (s.n_mat + 2 + EXP_SLOTS)
+    per_step = dose_ms / args.form_steps
+    ach = ops / (per_step * 1e-3) / 1e12
+    D0, Dp = res["d"]
+    del ws
+    return {
+        "ms_per_step": round(1e3 * elapsed / args.form_steps, 4),
+        "steps": args.form_steps,
+        "stages_ms_per_step": {k: round(v[0] / args.form_steps, 4) for k, v in stages.items() if v[1]},
+        "mass_kg": mass,
+        "Dp_MeV_per_kg_per_particle": float(Dp.item()),
+        "roofline": {"kernel": "k_dose_rays (+ k_dose_sum)", "bound": "alu", "achieved": round(ach, 3),
+                     "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Top/s",
+                     "frac": round(ach * 1e12 / VALU_LANE_OPS, 4), "stage_ms": round(per_step, 4),
+                     "algorithmic_ops_per_step": ops,
+                     "traffic": profiled_traffic("k_dose_rays", source_digest(DOSE_SOURCES))},
+    }
+
 
 def noise_stage(pb, cfg, args, torch, fc):
     """Projections with Poisson noise (Eq. 5) on the same workload: the whole
@@ -366,8 +409,11 @@ def main():
         result["forms"]["split_bf16"] = form_split(pb, cfg, out, args, torch, fc)
     del ws, out
     torch.cuda.empty_cache()
+    result["next"] = {}
     if args.noise_counts > 0:
-        result["next"] = {"noise_and_projections": noise_stage(pb, cfg, args, torch, fc)}
+        result["next"]["noise_and_projections"] = noise_stage(pb, cfg, args, torch, fc)
+    if args.dose:
+        result["next"]["dose"] = dose_stage(pb, cfg, args, torch, fc, cnt["hit_rays"])
     del pb
     torch.cuda.empty_cache()
     if "surrogate" in forms:

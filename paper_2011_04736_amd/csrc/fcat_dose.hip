@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kDoseTile = 256;   // rays staged per tile (one per lane when loading)
 
+// Workgroup b takes the tiles b, b + gridDim, ... (gridDim = kDoseBlocks or fewer).
 template <int MP>
 __global__ void __launch_bounds__(kBlock) k_dose_rays(const float *__restrict__ L, int64_t n_rays, int M,
                                                       const float *__restrict__ muT, int E, int64_t n_tiles,
@@ -36,9 +37,11 @@ __global__ void __launch_bounds__(kBlock) k_dose_rays(const float *__restrict__ 
         const int64_t r = tile * kDoseTile + threadIdx.x;
         float l[MP];
         bool hit = false;
+        const float *__restrict__ row = L + min(r, n_rays - 1) * M;   // clamped: loads without branches
 #pragma unroll
         for (int m = 0; m < MP; ++m) {
-            l[m] = (r < n_rays && m < M) ? L[r * M + m] : 0.0f;
+            const float v = row[min(m, M - 1)];
+            l[m] = (r < n_rays && m < M) ? v : 0.0f;
             hit |= l[m] != 0.0f;
         }
         const uint64_t mask = __ballot(hit);

@@ -193,7 +193,11 @@ hipError_t launch_fill(float *x, int n, float v, hipStream_t stream);
 // [n_rays][M]: partial sums of 1 - exp(-P) per workgroup and energy bin
 // (dose_blocks(n_rays) x E doubles), then S[e] += their sum in a fixed order;
 // finally D0 and Dp from S.
-constexpr int kDoseBlocks = 2048;
+// A prime, so that the tiles of a workgroup (stride kDoseBlocks) move across
+// the positions of a detector row from one visit to the next: rays that meet
+// the phantom come in bands of rows, and a stride that is a multiple of the
+// row period would hand them all to a few workgroups.
+constexpr int kDoseBlocks = 2039;
 int dose_blocks(int64_t n_rays);
 hipError_t launch_dose_rays(const float *L, int64_t n_rays, int M, const SpecTables &t, double *partial,
                             hipStream_t stream);
