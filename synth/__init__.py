@@ -86,6 +86,22 @@ class Phantom:
 
 
 @dataclass
+class Grid:
+    """Reconstruction grid: nx x ny x nz voxels of dx x dy x dz mm, centred at
+    (cx, cy, cz); voxel (ix, iy, iz) has its centre at
+    c - n h / 2 + (i + 1/2) h per axis, as for a Phantom."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    cx: float = 0.0
+    cy: float = 0.0
+    cz: float = 0.0
+
+
+@dataclass
 class Spectral:
     """Per-material attenuation, source spectrum and detector response.
 
