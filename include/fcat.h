@@ -353,6 +353,57 @@ fcat_status fcat_dose(const fcat_geometry_t *geometry, const fcat_phantom_t *pha
                       double mass, int32_t a_begin, int32_t a_end, double *D0, double *Dp, void *workspace,
                       size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------- reconstruction */
+/*
+ * FDK reconstruction of the circular scan (Sec. II.G: the projections are
+ * reconstructed with the default FDK algorithm; Feldkamp, Davis and Kress,
+ * J. Opt. Soc. Am. A 1 (1984) 612), in the geometry conventions above:
+ *   virtual detector through the axis: a = u_det SID / SDD, c = v_det SID / SDD,
+ *     pitch tau = du SID / SDD;
+ *   q = p SID / sqrt(SID^2 + a^2 + c^2)                  (cosine weight)
+ *   q~[n] = tau sum_k h((n - k) tau) q[k] along each row, zero beyond the
+ *     detector, with the Ram-Lak kernel h(0) = 1/(4 tau^2), h(m tau) = 0 for
+ *     even m != 0 and -1/(m^2 pi^2 tau^2) for odd m;
+ *   f(x, y, z) = (pi / A) sum_a SID^2 / U^2 q~_a(a*, c*), with
+ *     s = x cos b + y sin b, t = -x sin b + y cos b, U = SID - s,
+ *     a* = SID t / U, c* = SID z / U, q~ sampled bilinearly (zero outside);
+ *     A = n_angles and the scan is taken as a full, evenly spaced circle.
+ * p is the line integral of attenuation (for instance fcat_projections'
+ * output); f is then in mm^-1.  All FP32.
+ */
+typedef struct fcat_grid_t {
+    int32_t nx, ny, nz;       /* >= 1 each, nx ny nz < 2^31 */
+    double dx_mm, dy_mm, dz_mm;
+    double cx_mm, cy_mm, cz_mm; /* centre; voxel i of an axis has its centre at c - n d / 2 + (i + 1/2) d */
+} fcat_grid_t;
+
+/*
+ * Cosine weight and ramp filter: filtered (DEVICE float [n_ang][nv][nu]) from
+ * proj (DEVICE float [n_ang][nv][nu]); the two must not overlap.
+ * nu <= 8192.
+ */
+fcat_status fcat_fdk_filter(const fcat_geometry_t *geometry, const float *proj, int32_t n_ang, float *filtered,
+                            void *stream);
+
+/* Workspace needed by fcat_fdk_backproject for n_ang angles. */
+size_t fcat_fdk_backproject_workspace_bytes(int32_t n_ang);
+
+/*
+ * Back-projection of filtered projections of angles a_begin .. a_end - 1
+ * (DEVICE float [a_end - a_begin][nv][nu]) into volume (DEVICE float
+ * [nz][ny][nx]): volume = (accumulate ? volume : 0) + (pi / n_angles) sum_a ...
+ */
+fcat_status fcat_fdk_backproject(const fcat_geometry_t *geometry, const float *filtered, int32_t a_begin,
+                                 int32_t a_end, const fcat_grid_t *grid, float *volume, int32_t accumulate,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace needed by fcat_fdk (angles_per_chunk 0: up to 1 GiB of filtered rows per chunk). */
+size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_per_chunk);
+
+/* The whole reconstruction: volume (DEVICE float [nz][ny][nx]) from proj (DEVICE float [n_angles][nv][nu]). */
+fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------ surrogate */
 /*
  * The learned form of the primary spectral sum (see fcat_surrogate_t).  The
@@ -449,7 +500,9 @@ typedef enum fcat_stage {
     FCAT_STAGE_NOISE = 4,  /* Poisson draws */
     FCAT_STAGE_PROJ = 5,   /* count scale, flood profile and log conversion */
     FCAT_STAGE_DOSE = 6,   /* dose sums over rays and bins */
-    FCAT_STAGE_COUNT = 7
+    FCAT_STAGE_FILTER = 7, /* FDK cosine weight and ramp filter */
+    FCAT_STAGE_BACKPROJECT = 8, /* FDK back-projection */
+    FCAT_STAGE_COUNT = 9
 } fcat_stage;
 
 /*

@@ -36,7 +36,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfcat.so")
 MODES = {"plain": 0, "split_bf16": 1, "surrogate": 2}
-STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose")
+STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose", "filter", "backproject")
 _lib = None
 
 
@@ -75,6 +75,12 @@ class _CScatter(C.Structure):
 
 class _CPsf(C.Structure):
     _fields_ = [("k", C.c_int32), ("kernels", C.c_void_p)]
+
+
+class _CGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx_mm", C.c_double), ("dy_mm", C.c_double), ("dz_mm", C.c_double),
+                ("cx_mm", C.c_double), ("cy_mm", C.c_double), ("cz_mm", C.c_double)]
 
 
 class _CNoise(C.Structure):
@@ -172,6 +178,17 @@ def load() -> C.CDLL:
     L.fcat_dose_workspace_bytes.restype = sz
     L.fcat_dose.argtypes = [gp, pp, sp, vp, vp, C.c_double, C.c_int32, C.c_int32, vp, vp, vp, sz, vp]
     L.fcat_dose.restype = st
+    grp = C.POINTER(_CGrid)
+    L.fcat_fdk_filter.argtypes = [gp, vp, C.c_int32, vp, vp]
+    L.fcat_fdk_filter.restype = st
+    L.fcat_fdk_backproject_workspace_bytes.argtypes = [C.c_int32]
+    L.fcat_fdk_backproject_workspace_bytes.restype = sz
+    L.fcat_fdk_backproject.argtypes = [gp, vp, C.c_int32, C.c_int32, grp, vp, C.c_int32, vp, sz, vp]
+    L.fcat_fdk_backproject.restype = st
+    L.fcat_fdk_workspace_bytes.argtypes = [gp, C.c_int32]
+    L.fcat_fdk_workspace_bytes.restype = sz
+    L.fcat_fdk.argtypes = [gp, vp, grp, vp, vp, sz, vp]
+    L.fcat_fdk.restype = st
     L.fcat_timing_enable.argtypes = [C.c_int]
     L.fcat_timing_enable.restype = st
     L.fcat_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int]
@@ -621,6 +638,57 @@ def fcat_dose(pb: Problem, energy, mu_en_over_mu, mass: float, a_begin: int = 0,
                             int(a_begin), int(a_end), _ptr(D0), _ptr(Dp), _ptr(workspace),
                             0 if workspace is None else workspace.numel(), _stream(stream)))
     return D0, Dp
+
+
+# ------------------------------------------------------------- reconstruction
+
+def _cgrid(grid) -> _CGrid:
+    return _CGrid(int(grid.nx), int(grid.ny), int(grid.nz), float(grid.dx), float(grid.dy), float(grid.dz),
+                  float(grid.cx), float(grid.cy), float(grid.cz))
+
+
+def fcat_fdk_filter(geometry: Geometry, proj, out=None, stream=None):
+    """Cosine-weighted, ramp-filtered projections [n_ang][nv][nu]."""
+    torch = _require_gpu()
+    if out is None:
+        out = torch.empty_like(proj)
+    cg = geometry.c()
+    _check(load().fcat_fdk_filter(C.byref(cg), _ptr(proj), int(proj.shape[0]), _ptr(out), _stream(stream)))
+    return out
+
+
+def fcat_fdk_backproject(geometry: Geometry, filtered, grid, a_begin: int = 0, volume=None, accumulate: bool = False,
+                         workspace=None, stream=None):
+    """FDK back-projection of filtered projections of angles a_begin .. a_begin + n - 1."""
+    torch = _require_gpu()
+    n = int(filtered.shape[0])
+    if volume is None:
+        volume = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float32, device=filtered.device)
+    if workspace is None:
+        workspace = _workspace(int(load().fcat_fdk_backproject_workspace_bytes(n)), filtered.device)
+    cg, cv = geometry.c(), _cgrid(grid)
+    _check(load().fcat_fdk_backproject(C.byref(cg), _ptr(filtered), int(a_begin), int(a_begin) + n, C.byref(cv),
+                                       _ptr(volume), 1 if accumulate else 0, _ptr(workspace),
+                                       0 if workspace is None else workspace.numel(), _stream(stream)))
+    return volume
+
+
+def fcat_fdk_workspace_bytes(geometry: Geometry, angles_per_chunk: int = 0) -> int:
+    cg = geometry.c()
+    return int(load().fcat_fdk_workspace_bytes(C.byref(cg), int(angles_per_chunk)))
+
+
+def fcat_fdk(geometry: Geometry, proj, grid, volume=None, workspace=None, angles_per_chunk: int = 0, stream=None):
+    """FDK reconstruction [nz][ny][nx] (mm^-1) of projections [n_angles][nv][nu]."""
+    torch = _require_gpu()
+    if volume is None:
+        volume = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float32, device=proj.device)
+    if workspace is None:
+        workspace = _workspace(fcat_fdk_workspace_bytes(geometry, angles_per_chunk), proj.device)
+    cg, cv = geometry.c(), _cgrid(grid)
+    _check(load().fcat_fdk(C.byref(cg), _ptr(proj), C.byref(cv), _ptr(volume), _ptr(workspace),
+                           0 if workspace is None else workspace.numel(), _stream(stream)))
+    return volume
 
 
 # ------------------------------------------------------------- surrogate

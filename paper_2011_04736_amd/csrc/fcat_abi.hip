@@ -1,6 +1,7 @@
 // C ABI of libfcat.so: host-side argument validation, workspace layout,
 // angle chunking and kernel launches.  See include/fcat.h for the contract.
 #include "fcat_internal.h"
+#include "fcat_recon.h"
 
 #include <algorithm>
 #include <cmath>
@@ -746,6 +747,157 @@ fcat_status fcat_dose(const fcat_geometry_t *geometry, const fcat_phantom_t *pha
         e = launch_dose_final(S, energy, mu_en_over_mu, spectral->phi, t.E, 1.0 / (n_rays * mass), D0, Dp, stream);
     }
     if (e != hipSuccess) return device_fail(e, "dose");
+    return FCAT_OK;
+}
+
+// ------------------------------------------------------------------ FDK
+
+static FdkGeom fdk_geom(const fcat_geometry_t *g)
+{
+    FdkGeom f{};
+    f.D = (float)g->sid_mm;
+    f.scale = (float)(g->sdd_mm / g->sid_mm);
+    f.du = (float)g->du_mm;
+    f.dv = (float)g->dv_mm;
+    f.off_u = (float)g->off_u_mm;
+    f.off_v = (float)g->off_v_mm;
+    f.cu = 0.5f * (float)(g->nu - 1);
+    f.cv = 0.5f * (float)(g->nv - 1);
+    f.tau = (float)(g->du_mm * g->sid_mm / g->sdd_mm);
+    f.nu = g->nu;
+    f.nv = g->nv;
+    return f;
+}
+
+static fcat_status check_grid(const fcat_grid_t *v, FdkGrid &out)
+{
+    if (!v) return fail(FCAT_E_INVALID_ARG, "grid is NULL");
+    if (v->nx < 1 || v->ny < 1 || v->nz < 1) return fail(FCAT_E_INVALID_ARG, "grid nx, ny, nz must be >= 1");
+    if ((int64_t)v->nx * v->ny * v->nz >= ((int64_t)1 << 31))
+        return fail(FCAT_E_INVALID_ARG, "grid larger than 2^31 - 1 voxels");
+    if (!finite_pos(v->dx_mm) || !finite_pos(v->dy_mm) || !finite_pos(v->dz_mm))
+        return fail(FCAT_E_INVALID_ARG, "grid voxel sizes must be finite and > 0");
+    if (!std::isfinite(v->cx_mm) || !std::isfinite(v->cy_mm) || !std::isfinite(v->cz_mm))
+        return fail(FCAT_E_INVALID_ARG, "grid centre must be finite");
+    out.x0 = (float)(v->cx_mm - 0.5 * v->nx * v->dx_mm + 0.5 * v->dx_mm);
+    out.y0 = (float)(v->cy_mm - 0.5 * v->ny * v->dy_mm + 0.5 * v->dy_mm);
+    out.z0 = (float)(v->cz_mm - 0.5 * v->nz * v->dz_mm + 0.5 * v->dz_mm);
+    out.dx = (float)v->dx_mm;
+    out.dy = (float)v->dy_mm;
+    out.dz = (float)v->dz_mm;
+    out.nx = v->nx;
+    out.ny = v->ny;
+    out.nz = v->nz;
+    return FCAT_OK;
+}
+
+constexpr int kFdkMaxNu = 8192;
+
+fcat_status fcat_fdk_filter(const fcat_geometry_t *geometry, const float *proj, int32_t n_ang, float *filtered,
+                            void *stream)
+{
+    g_last_error.clear();
+    fcat_status s;
+    if ((s = check_geometry(geometry))) return s;
+    if (geometry->nu > kFdkMaxNu) return fail(FCAT_E_UNSUPPORTED, "FDK filter takes nu <= %d", kFdkMaxNu);
+    if (n_ang < 1) return fail(FCAT_E_INVALID_ARG, "n_ang must be >= 1");
+    if (!proj || !filtered) return fail(FCAT_E_INVALID_ARG, "proj and filtered must not be NULL");
+    const size_t bytes = (size_t)n_ang * geometry->nv * geometry->nu * sizeof(float);
+    const char *p0 = reinterpret_cast<const char *>(proj), *f0 = reinterpret_cast<const char *>(filtered);
+    if (p0 < f0 + bytes && f0 < p0 + bytes) return fail(FCAT_E_INVALID_ARG, "proj and filtered overlap");
+    if ((s = check_pending())) return s;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_FILTER, static_cast<hipStream_t>(stream));
+        e = launch_fdk_filter(fdk_geom(geometry), proj, n_ang, filtered, static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return device_fail(e, "fdk_filter");
+    return FCAT_OK;
+}
+
+size_t fcat_fdk_backproject_workspace_bytes(int32_t n_ang)
+{
+    return n_ang < 1 ? 0 : align_up((size_t)n_ang * sizeof(float2));
+}
+
+static fcat_status fdk_backproject(const fcat_geometry_t *geometry, const float *filtered, int a_begin, int a_end,
+                                   const FdkGrid &v, float *volume, int accumulate, float2 *cs, hipStream_t stream)
+{
+    const int n = a_end - a_begin;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_BACKPROJECT, stream);
+        e = launch_fdk_angles(geometry->angles_rad, geometry->n_angles, a_begin, n, cs, stream);
+        if (e == hipSuccess)
+            e = launch_fdk_backproject(fdk_geom(geometry), v, filtered, cs, n,
+                                       (float)(3.141592653589793 / geometry->n_angles), accumulate, volume, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "fdk_backproject");
+    return FCAT_OK;
+}
+
+fcat_status fcat_fdk_backproject(const fcat_geometry_t *geometry, const float *filtered, int32_t a_begin,
+                                 int32_t a_end, const fcat_grid_t *grid, float *volume, int32_t accumulate,
+                                 void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    fcat_status s;
+    FdkGrid v{};
+    if ((s = check_geometry(geometry)) || (s = check_grid(grid, v))) return s;
+    if (a_begin < 0 || a_end > geometry->n_angles || a_begin >= a_end)
+        return fail(FCAT_E_INVALID_ARG, "need 0 <= a_begin < a_end <= n_angles");
+    if (!filtered || !volume) return fail(FCAT_E_INVALID_ARG, "filtered and volume must not be NULL");
+    if ((s = check_workspace(workspace, workspace_bytes, fcat_fdk_backproject_workspace_bytes(a_end - a_begin))))
+        return s;
+    if ((s = check_pending())) return s;
+    return fdk_backproject(geometry, filtered, a_begin, a_end, v, volume, accumulate ? 1 : 0,
+                           static_cast<float2 *>(workspace), static_cast<hipStream_t>(stream));
+}
+
+static size_t fdk_chunk(const fcat_geometry_t *g, int32_t angles_per_chunk)
+{
+    const size_t per = (size_t)g->nu * g->nv * sizeof(float);
+    size_t c = angles_per_chunk > 0 ? (size_t)angles_per_chunk : kDefaultChunkBytes / per;
+    return std::max<size_t>(1, std::min<size_t>(c, (size_t)g->n_angles));
+}
+
+size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_per_chunk)
+{
+    if (check_geometry(geometry)) return 0;
+    const size_t c = fdk_chunk(geometry, angles_per_chunk);
+    return align_up((size_t)geometry->n_angles * sizeof(float2)) +
+           align_up(c * geometry->nu * geometry->nv * sizeof(float));
+}
+
+fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,
+                     void *workspace, size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    fcat_status s;
+    FdkGrid v{};
+    if ((s = check_geometry(geometry)) || (s = check_grid(grid, v))) return s;
+    if (geometry->nu > kFdkMaxNu) return fail(FCAT_E_UNSUPPORTED, "FDK filter takes nu <= %d", kFdkMaxNu);
+    if (!proj || !volume) return fail(FCAT_E_INVALID_ARG, "proj and volume must not be NULL");
+    const size_t per = (size_t)geometry->nu * geometry->nv * sizeof(float);
+    const size_t cs_bytes = align_up((size_t)geometry->n_angles * sizeof(float2));
+    if ((s = check_workspace(workspace, workspace_bytes, cs_bytes + align_up(per)))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    float2 *cs = static_cast<float2 *>(workspace);
+    float *filt = at<float>(workspace, cs_bytes);
+    const int A = geometry->n_angles;
+    const int chunk = (int)std::min<size_t>((size_t)A, (workspace_bytes - cs_bytes) / per);
+    const FdkGeom g = fdk_geom(geometry);
+    for (int a0 = 0; a0 < A; a0 += chunk) {
+        const int n = std::min(chunk, A - a0);
+        hipError_t e;
+        {
+            StageTimer tm(FCAT_STAGE_FILTER, stream);
+            e = launch_fdk_filter(g, proj + (int64_t)a0 * geometry->nu * geometry->nv, n, filt, stream);
+        }
+        if (e != hipSuccess) return device_fail(e, "fdk_filter");
+        if ((s = fdk_backproject(geometry, filt, a0, a0 + n, v, volume, a0 > 0, cs, stream))) return s;
+    }
     return FCAT_OK;
 }
 

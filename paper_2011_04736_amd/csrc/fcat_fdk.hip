@@ -1,0 +1,193 @@
+// FDK reconstruction (Sec. II.G; Feldkamp, Davis and Kress 1984) of the
+// circular cone-beam scan: cosine weight and ramp filter along detector rows,
+// then voxel-driven weighted back-projection with bilinear interpolation.
+//
+// The ramp is the band-limited (Ram-Lak) kernel in the spatial domain: tap 0
+// is 1 / (4 tau), odd taps -1 / (n^2 pi^2 tau), even taps zero.  An output
+// of one parity therefore only sees inputs of the other parity (besides tap
+// 0), so each row is split into its even and odd samples and each half is
+// a plain Toeplitz product with the odd taps.  A lane computes 8 consecutive
+// outputs of one half with the kernel taps in a register window that slides
+// by one per input: one LDS read of an input (shared by the lanes of a row)
+// and one of a tap per 8 FMAs.
+#include "fcat_recon.h"
+
+namespace fcat {
+namespace {
+
+constexpr int kRampOut = 8;   // outputs per lane in the ramp filter
+
+// Work of one lane: outputs i0 .. i0 + kRampOut - 1 of half s (0: even
+// samples, 1: odd samples) of row r of the workgroup.
+__global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *__restrict__ proj, int n_rows,
+                                                       int rows_per_block, float *__restrict__ filt)
+{
+    extern __shared__ float lds[];
+    const int nq = (g.nu + 1) / 2;                   // samples per half (the odd half zero-padded)
+    const int ngrp = (nq + kRampOut - 1) / kRampOut;
+    const int ntab = 2 * nq + kRampOut + 1;
+    float *__restrict__ tab = lds;                   // tab[j] = G[j - nq], G[d] = h((2d - 1) tau) tau
+    float *__restrict__ half = lds + ntab;           // [rows_per_block][2][nq]
+    const float pi2tau = 9.869604401089358f * g.tau;
+    for (int j = (int)threadIdx.x; j < ntab; j += kBlock) {
+        const float m = (float)(2 * (j - nq) - 1);   // odd offset
+        tab[j] = -1.0f / (m * m * pi2tau);
+    }
+    const int row0 = blockIdx.x * rows_per_block;
+    const int nr = min(rows_per_block, n_rows - row0);
+    for (int k = (int)threadIdx.x; k < nr * 2 * nq; k += kBlock) {
+        const int r = k / (2 * nq);
+        const int rem = k - r * 2 * nq;
+        const int s = rem / nq, l = rem - s * nq;
+        const int iu = 2 * l + s;
+        const int row = row0 + r;
+        const int iv = row % g.nv;
+        float v = 0.0f;
+        if (iu < g.nu) {
+            const float a = ((float)iu - g.cu) * g.du + g.off_u;
+            const float c = ((float)iv - g.cv) * g.dv + g.off_v;
+            const float av = a / g.scale, cvv = c / g.scale;
+            v = proj[(int64_t)row * g.nu + iu] * (g.D * rsqrtf(g.D * g.D + av * av + cvv * cvv));
+        }
+        half[(r * 2 + s) * nq + l] = v;
+    }
+    __syncthreads();
+    const float h0 = 0.25f / g.tau;
+    for (int w = (int)threadIdx.x; w < nr * 2 * ngrp; w += kBlock) {
+        const int r = w / (2 * ngrp);
+        const int s = (w / ngrp) & 1;
+        const int i0 = (w % ngrp) * kRampOut;
+        const float *__restrict__ other = half + (r * 2 + (1 - s)) * nq;
+        const float *__restrict__ self = half + (r * 2 + s) * nq;
+        // out half s at i = h0 x_s[i] + sum_l G[i - l + s] x_(1-s)[l]
+        const int base = i0 + s + nq;                // tab index of G[i0 + s - l] at l = 0
+        float win[kRampOut], acc[kRampOut];
+#pragma unroll
+        for (int q = 0; q < kRampOut; ++q) {
+            win[q] = tab[base + q];
+            acc[q] = 0.0f;
+        }
+#pragma unroll 8
+        for (int l = 0; l < nq; ++l) {
+            const float xv = other[l];
+#pragma unroll
+            for (int q = 0; q < kRampOut; ++q) acc[q] = fmaf(win[q], xv, acc[q]);
+#pragma unroll
+            for (int q = kRampOut - 1; q > 0; --q) win[q] = win[q - 1];
+            win[0] = tab[base - l - 1];
+        }
+        const int row = row0 + r;
+#pragma unroll
+        for (int q = 0; q < kRampOut; ++q) {
+            const int i = i0 + q;
+            const int iu = 2 * i + s;
+            if (i < nq && iu < g.nu) filt[(int64_t)row * g.nu + iu] = fmaf(h0, self[i], acc[q]);
+        }
+    }
+}
+
+__global__ void k_fdk_angles(const double *__restrict__ angles, int n_angles, int a0, int n, float2 *__restrict__ cs)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double b = angles ? angles[a0 + i] : 6.283185307179586 * (double)(a0 + i) / (double)n_angles;
+    double sb, cb;
+    sincos(b, &sb, &cb);
+    cs[i] = make_float2((float)cb, (float)sb);
+}
+
+constexpr int kBpZ = 8;        // slices a lane accumulates per pass
+constexpr int kBpTileX = 64;   // workgroup tile: 64 x 4 columns (x fastest, one wavefront per row)
+
+// Voxel-driven back-projection: a lane owns one (x, y) column and kBpZ
+// slices starting at z0 + blockIdx.z kBpZ, and loops over the angles.
+__global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v, const float *__restrict__ filt,
+                                                            const float2 *__restrict__ cs, int n, float weight,
+                                                            int accumulate, float *__restrict__ volume)
+{
+    const int ix = blockIdx.x * kBpTileX + (int)(threadIdx.x % kBpTileX);
+    const int iy = blockIdx.y * (kBlock / kBpTileX) + (int)(threadIdx.x / kBpTileX);
+    const int iz0 = blockIdx.z * kBpZ;
+    if (ix >= v.nx || iy >= v.ny) return;
+    const float x = v.x0 + (float)ix * v.dx;
+    const float y = v.y0 + (float)iy * v.dy;
+    float acc[kBpZ];
+#pragma unroll
+    for (int q = 0; q < kBpZ; ++q) acc[q] = 0.0f;
+    const int64_t plane = (int64_t)g.nu * g.nv;
+    for (int a = 0; a < n; ++a) {
+        const float2 c = cs[a];
+        const float s = x * c.x + y * c.y;
+        const float t = y * c.x - x * c.y;
+        const float inv = 1.0f / (g.D - s);
+        const float mag = g.D * inv;                        // D / U
+        const float w = mag * mag;                          // D^2 / U^2
+        const float uf = (t * mag * g.scale - g.off_u) / g.du + g.cu;
+        const float fu0 = floorf(uf);
+        const float fu = uf - fu0;
+        const int i0 = (int)fu0;
+        const float wu0 = (i0 >= 0 && i0 < g.nu) ? 1.0f - fu : 0.0f;
+        const float wu1 = (i0 + 1 >= 0 && i0 + 1 < g.nu) ? fu : 0.0f;
+        const int c0 = min(max(i0, 0), g.nu - 1), c1 = min(max(i0 + 1, 0), g.nu - 1);
+        const float *__restrict__ p = filt + (int64_t)a * plane;
+        const float zstep = v.dz * mag * g.scale / g.dv;    // detector rows per slice
+        const float vf0 = ((v.z0 + (float)iz0 * v.dz) * mag * g.scale - g.off_v) / g.dv + g.cv;
+#pragma unroll
+        for (int q = 0; q < kBpZ; ++q) {
+            const float vf = vf0 + (float)q * zstep;
+            const float fv0 = floorf(vf);
+            const float fv = vf - fv0;
+            const int j0 = (int)fv0;
+            const float wv0 = (j0 >= 0 && j0 < g.nv) ? 1.0f - fv : 0.0f;
+            const float wv1 = (j0 + 1 >= 0 && j0 + 1 < g.nv) ? fv : 0.0f;
+            const int r0 = min(max(j0, 0), g.nv - 1), r1 = min(max(j0 + 1, 0), g.nv - 1);
+            const float s0 = wu0 * p[r0 * g.nu + c0] + wu1 * p[r0 * g.nu + c1];
+            const float s1 = wu0 * p[r1 * g.nu + c0] + wu1 * p[r1 * g.nu + c1];
+            acc[q] = fmaf(w, wv0 * s0 + wv1 * s1, acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kBpZ; ++q) {
+        const int iz = iz0 + q;
+        if (iz < v.nz) {
+            float *o = volume + ((int64_t)iz * v.ny + iy) * v.nx + ix;
+            *o = (accumulate ? *o : 0.0f) + weight * acc[q];
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, float *filt, hipStream_t stream)
+{
+    const int nq = (g.nu + 1) / 2;
+    const int ngrp = (nq + kRampOut - 1) / kRampOut;
+    const int rows = n_ang * g.nv;
+    int rpb = kBlock / (2 * ngrp);
+    if (rpb < 1) rpb = 1;
+    const size_t lds = (size_t)(2 * nq + kRampOut + 1 + rpb * 2 * nq) * sizeof(float);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const int nblk = (rows + rpb - 1) / rpb;
+    hipLaunchKernelGGL(k_fdk_filter, dim3(nblk), dim3(kBlock), lds, stream, g, proj, rows, rpb, filt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdk_angles(const double *angles, int n_angles, int a0, int n, float2 *cs, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_fdk_angles, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, angles, n_angles, a0, n,
+                       cs);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdk_backproject(const FdkGeom &g, const FdkGrid &v, const float *filt, const float2 *cs, int n,
+                                  float weight, int accumulate, float *volume, hipStream_t stream)
+{
+    const dim3 grid((v.nx + kBpTileX - 1) / kBpTileX, (v.ny + kBlock / kBpTileX - 1) / (kBlock / kBpTileX),
+                    (v.nz + kBpZ - 1) / kBpZ);
+    if (grid.y > 65535 || grid.z > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fdk_backproject, grid, dim3(kBlock), 0, stream, g, v, filt, cs, n, weight, accumulate,
+                       volume);
+    return hipGetLastError();
+}
+
+}  // namespace fcat
