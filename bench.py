@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--noise-counts", type=float, default=1.0e5,
                     help="H of Eq. 5 (flood counts per open pixel) for the noise stage; 0 skips it")
     ap.add_argument("--dose", type=int, default=1, help="1: time the dose estimate of Eqs. 6-7 (0 skips it)")
+    ap.add_argument("--fdk", type=int, default=1, help="1: time the FDK reconstruction of the projections (0 skips it)")
     ap.add_argument("--forms", default="split_bf16,surrogate",
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
@@ -108,6 +109,8 @@ def source_digest(files) -> str:
 TRACE_SOURCES = ["fcat_kernels.hip", "fcat_device.h", "fcat_internal.h"]
 NOISE_SOURCES = ["fcat_noise.hip", "fcat_internal.h"]
 DOSE_SOURCES = ["fcat_dose.hip", "fcat_internal.h"]
+FDK_SOURCES = ["fcat_fdk.hip", "fcat_recon.h"]
+BP_OPS_PER_VOXEL_ANGLE = 10   # axial position 1, floor and fraction 2, four-tap bilinear 6, weighted add 1
 
 
 def profiled_traffic(kernel: str, digest: str):
@@ -125,6 +128,48 @@ def profiled_traffic(kernel: str, digest: str):
 
 
 # ----------------------------------------------------------------- forms
+
+def fdk_stage(pb, cfg, args, torch, fc):
+    """FDK reconstruction of the workload's noiseless projections into the
+    phantom's own grid (1024 x 1024 x 10): ramp filter (nu/2 FMAs per output,
+    the even taps being zero) and back-projection (every voxel from every
+    angle)."""
+    import synth
+    g, ph = cfg.geometry, cfg.phantom
+    proj = fc.fcat_projections(pb, None)
+    grid = synth.Grid(nx=ph.nx, ny=ph.ny, nz=ph.nz, dx=ph.dx, dy=ph.dy, dz=ph.dz)
+    vol = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float32, device=proj.device)
+    ws = torch.empty(fc.fcat_fdk_workspace_bytes(pb.geometry), dtype=torch.uint8, device=proj.device)
+    stream = torch.cuda.current_stream()
+    elapsed, stages = timed_steps(lambda: fc.fcat_fdk(pb.geometry, proj, grid, volume=vol, workspace=ws,
+                                                      stream=stream), 1, args.form_steps, torch)
+    bp_ms = stages["backproject"][0] / args.form_steps
+    fl_ms = stages["filter"][0] / args.form_steps
+    vox_ang = float(grid.nx) * grid.ny * grid.nz * g.n_angles
+    bp_ops = BP_OPS_PER_VOXEL_ANGLE * vox_ang
+    bp_ach = bp_ops / (bp_ms * 1e-3) / 1e12
+    fl_flops = 2.0 * g.n_angles * g.nv * g.nu * ((g.nu + 1) // 2)
+    fl_ach = fl_flops / (fl_ms * 1e-3) / 1e12
+    finite = bool(torch.isfinite(vol).all().item())
+    del ws, vol, proj
+    return {
+        "ms_per_step": round(1e3 * elapsed / args.form_steps, 4),
+        "steps": args.form_steps,
+        "grid": [grid.nx, grid.ny, grid.nz],
+        "stages_ms_per_step": {k: round(v[0] / args.form_steps, 4) for k, v in stages.items() if v[1]},
+        "voxel_angle_updates_per_s": vox_ang / (bp_ms * 1e-3),
+        "finite": finite,
+        "roofline": {"kernel": "k_fdk_backproject", "bound": "alu", "achieved": round(bp_ach, 3),
+                     "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Top/s",
+                     "frac": round(bp_ach * 1e12 / VALU_LANE_OPS, 4), "stage_ms": round(bp_ms, 4),
+                     "algorithmic_ops_per_step": bp_ops,
+                     "traffic": profiled_traffic("k_fdk_backproject", source_digest(FDK_SOURCES))},
+        "filter": {"kernel": "k_fdk_filter", "bound": "alu", "achieved": round(fl_ach, 3),
+                   "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(fl_ach / PEAK_FP32_VECTOR_TFLOPS, 4), "stage_ms": round(fl_ms, 4),
+                   "algorithmic_flops_per_step": fl_flops},
+    }
+
 
 def dose_stage(pb, cfg, args, torch, fc, hit_rays):
     """Dose per particle (Eqs. 6-7) over all angles of the workload: the walk
@@ -414,6 +459,8 @@ def main():
         result["next"]["noise_and_projections"] = noise_stage(pb, cfg, args, torch, fc)
     if args.dose:
         result["next"]["dose"] = dose_stage(pb, cfg, args, torch, fc, cnt["hit_rays"])
+    if args.fdk:
+        result["next"]["fdk"] = fdk_stage(pb, cfg, args, torch, fc)
     del pb
     torch.cuda.empty_cache()
     if "surrogate" in forms:

@@ -764,6 +764,8 @@ static FdkGeom fdk_geom(const fcat_geometry_t *g)
     f.cu = 0.5f * (float)(g->nu - 1);
     f.cv = 0.5f * (float)(g->nv - 1);
     f.tau = (float)(g->du_mm * g->sid_mm / g->sdd_mm);
+    f.inv_du = (float)(1.0 / g->du_mm);
+    f.inv_dv = (float)(1.0 / g->dv_mm);
     f.nu = g->nu;
     f.nv = g->nv;
     return f;

@@ -96,18 +96,23 @@ __global__ void k_fdk_angles(const double *__restrict__ angles, int n_angles, in
     cs[i] = make_float2((float)cb, (float)sb);
 }
 
-constexpr int kBpZ = 8;        // slices a lane accumulates per pass
+constexpr int kBpZ = 16;       // slices a lane accumulates per pass
 constexpr int kBpTileX = 64;   // workgroup tile: 64 x 4 columns (x fastest, one wavefront per row)
 
-// Voxel-driven back-projection: a lane owns one (x, y) column and kBpZ
-// slices starting at z0 + blockIdx.z kBpZ, and loops over the angles.
+// Voxel-driven back-projection: a lane owns one (x, y) column and zc <= kBpZ
+// slices starting at blockIdx.z zc (the slices split evenly over gridDim.z),
+// and loops over the angles.  The taps are read from global memory: the
+// window of the detector a workgroup touches per angle is small and stays in
+// the caches (staging it in LDS, one angle ahead with a barrier per angle,
+// measured twice as slow on the 10-slice contrast grid).
 __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v, const float *__restrict__ filt,
-                                                            const float2 *__restrict__ cs, int n, float weight,
-                                                            int accumulate, float *__restrict__ volume)
+                                                            const float2 *__restrict__ cs, int n, int zc,
+                                                            float weight, int accumulate, float *__restrict__ volume)
 {
     const int ix = blockIdx.x * kBpTileX + (int)(threadIdx.x % kBpTileX);
     const int iy = blockIdx.y * (kBlock / kBpTileX) + (int)(threadIdx.x / kBpTileX);
-    const int iz0 = blockIdx.z * kBpZ;
+    const int iz0 = blockIdx.z * zc;
+    const int nzl = min(zc, v.nz - iz0);         // slices of this workgroup
     if (ix >= v.nx || iy >= v.ny) return;
     const float x = v.x0 + (float)ix * v.dx;
     const float y = v.y0 + (float)iy * v.dy;
@@ -119,10 +124,9 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
         const float2 c = cs[a];
         const float s = x * c.x + y * c.y;
         const float t = y * c.x - x * c.y;
-        const float inv = 1.0f / (g.D - s);
-        const float mag = g.D * inv;                        // D / U
-        const float w = mag * mag;                          // D^2 / U^2
-        const float uf = (t * mag * g.scale - g.off_u) / g.du + g.cu;
+        const float mag = g.D * __builtin_amdgcn_rcpf(g.D - s);   // D / U (1 ulp reciprocal)
+        const float w = mag * mag;                                  // D^2 / U^2
+        const float uf = (t * mag * g.scale - g.off_u) * g.inv_du + g.cu;
         const float fu0 = floorf(uf);
         const float fu = uf - fu0;
         const int i0 = (int)fu0;
@@ -130,10 +134,11 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
         const float wu1 = (i0 + 1 >= 0 && i0 + 1 < g.nu) ? fu : 0.0f;
         const int c0 = min(max(i0, 0), g.nu - 1), c1 = min(max(i0 + 1, 0), g.nu - 1);
         const float *__restrict__ p = filt + (int64_t)a * plane;
-        const float zstep = v.dz * mag * g.scale / g.dv;    // detector rows per slice
-        const float vf0 = ((v.z0 + (float)iz0 * v.dz) * mag * g.scale - g.off_v) / g.dv + g.cv;
+        const float zstep = v.dz * mag * g.scale * g.inv_dv;   // detector rows per slice
+        const float vf0 = ((v.z0 + (float)iz0 * v.dz) * mag * g.scale - g.off_v) * g.inv_dv + g.cv;
 #pragma unroll
         for (int q = 0; q < kBpZ; ++q) {
+            if (q >= nzl) break;
             const float vf = vf0 + (float)q * zstep;
             const float fv0 = floorf(vf);
             const float fv = vf - fv0;
@@ -149,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
 #pragma unroll
     for (int q = 0; q < kBpZ; ++q) {
         const int iz = iz0 + q;
-        if (iz < v.nz) {
+        if (q < nzl) {
             float *o = volume + ((int64_t)iz * v.ny + iy) * v.nx + ix;
             *o = (accumulate ? *o : 0.0f) + weight * acc[q];
         }
@@ -182,10 +187,12 @@ hipError_t launch_fdk_angles(const double *angles, int n_angles, int a0, int n, 
 hipError_t launch_fdk_backproject(const FdkGeom &g, const FdkGrid &v, const float *filt, const float2 *cs, int n,
                                   float weight, int accumulate, float *volume, hipStream_t stream)
 {
+    const int nzb = (v.nz + kBpZ - 1) / kBpZ;        // passes over z
+    const int zc = (v.nz + nzb - 1) / nzb;            // slices per pass, even split
     const dim3 grid((v.nx + kBpTileX - 1) / kBpTileX, (v.ny + kBlock / kBpTileX - 1) / (kBlock / kBpTileX),
-                    (v.nz + kBpZ - 1) / kBpZ);
+                    (v.nz + zc - 1) / zc);
     if (grid.y > 65535 || grid.z > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fdk_backproject, grid, dim3(kBlock), 0, stream, g, v, filt, cs, n, weight, accumulate,
+    hipLaunchKernelGGL(k_fdk_backproject, grid, dim3(kBlock), 0, stream, g, v, filt, cs, n, zc, weight, accumulate,
                        volume);
     return hipGetLastError();
 }

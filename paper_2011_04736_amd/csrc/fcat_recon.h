@@ -12,6 +12,7 @@ struct FdkGeom {
     float scale;          // SDD / SID: virtual (axis) to real detector coordinates
     float du, dv, off_u, off_v, cu, cv;
     float tau;            // pixel pitch on the virtual detector, du SID / SDD
+    float inv_du, inv_dv;
     int nu, nv;
 };
 
