@@ -404,6 +404,53 @@ size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_
 fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------- detector optics */
+/*
+ * Sec. II.D: the energy-dependent optical spread kernels, weighted by the
+ * detector's energy deposition efficiency times the spectrum, give the
+ * effective PSF; convolved with an idealised slit tilted by a small angle it
+ * gives a line spread function, presampled to estimate the detector MTF.
+ * Sec. IV.B: Richardson-Lucy deconvolution (Richardson 1972; Lucy 1974) of
+ * projection images with the PSF.
+ */
+
+/* kernel (DEVICE float [k][k]) = sum_g W_g K_g / sum_g W_g, W_g = sum_{e in g} phi_e eta_e. */
+fcat_status fcat_effective_psf(const fcat_spectral_t *spectral, const fcat_psf_t *psf, float *kernel, void *stream);
+
+/*
+ * Tilted slit.  Pixel (i, j) of an n_rows x n_cols image of pitch p has its
+ * centre at ((j - (n_cols-1)/2) p, (i - (n_rows-1)/2) p) and holds the exact
+ * fraction of its area inside the strip |x cos t + y sin t| <= width / 2
+ * (t = tilt from the columns, 0 < t < 90 degrees); the image is convolved
+ * with the kernel (zero outside).  Each pixel goes to bin
+ * b = floor(d / h + 1/2), d = x cos t + y sin t of its centre, h = p / oversample;
+ * the LSF of a bin is the mean of its pixels, and
+ * mtf[f] = |sum_b LSF_b exp(-2 pi i f b h)| / |sum_b LSF_b| over the bins that
+ * hold pixels (no slit-width or aperture correction).  The slit, bin and
+ * MTF arithmetic is FP64; the images FP32.
+ */
+fcat_status fcat_slit_lsf_range(double pitch_mm, double tilt_deg, int32_t n_rows, int32_t n_cols, int32_t oversample,
+                                int32_t *b_min, int32_t *n_bins);  /* HOST outputs */
+size_t fcat_slit_mtf_workspace_bytes(int32_t n_rows, int32_t n_cols, int32_t n_bins);
+fcat_status fcat_slit_mtf(const float *kernel, int32_t k, double pitch_mm, double width_mm, double tilt_deg,
+                          int32_t n_rows, int32_t n_cols, int32_t oversample, const double *freqs, int32_t n_freq,
+                          double *mtf, double *lsf, int32_t *lsf_count, void *workspace, size_t workspace_bytes,
+                          void *stream);
+/* freqs, mtf DEVICE double [n_freq] (cycles per mm); lsf DEVICE double [n_bins] and lsf_count
+   DEVICE int32 [n_bins] (bins b_min .. b_min + n_bins - 1 of fcat_slit_lsf_range) or NULL. */
+
+/*
+ * Richardson-Lucy deconvolution of n images d (DEVICE float [n][nv][nu],
+ * d >= 0) with one kernel (DEVICE float [k][k], k odd <= FCAT_MAX_PSF):
+ *   u_0 = d;  u <- u (K^T (*) (d / (K (*) u))) / (K^T (*) 1)
+ * with the convolution of the optical spread (zero outside the image), K^T
+ * the flipped kernel, the ratio 0 where K (*) u <= 0.  out DEVICE float
+ * [n][nv][nu] (not overlapping d).  n <= 65535.
+ */
+size_t fcat_richardson_lucy_workspace_bytes(int32_t n, int32_t nv, int32_t nu, int32_t k);
+fcat_status fcat_richardson_lucy(const float *images, int32_t n, int32_t nv, int32_t nu, const float *kernel, int32_t k,
+                                 int32_t iterations, float *out, void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------ surrogate */
 /*
  * The learned form of the primary spectral sum (see fcat_surrogate_t).  The
@@ -502,7 +549,8 @@ typedef enum fcat_stage {
     FCAT_STAGE_DOSE = 6,   /* dose sums over rays and bins */
     FCAT_STAGE_FILTER = 7, /* FDK cosine weight and ramp filter */
     FCAT_STAGE_BACKPROJECT = 8, /* FDK back-projection */
-    FCAT_STAGE_COUNT = 9
+    FCAT_STAGE_OPTICS = 9, /* effective PSF, slit MTF, Richardson-Lucy element-wise steps */
+    FCAT_STAGE_COUNT = 10
 } fcat_stage;
 
 /*

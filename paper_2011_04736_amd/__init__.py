@@ -36,7 +36,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfcat.so")
 MODES = {"plain": 0, "split_bf16": 1, "surrogate": 2}
-STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose", "filter", "backproject")
+STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose", "filter", "backproject", "optics")
 _lib = None
 
 
@@ -189,6 +189,20 @@ def load() -> C.CDLL:
     L.fcat_fdk_workspace_bytes.restype = sz
     L.fcat_fdk.argtypes = [gp, vp, grp, vp, vp, sz, vp]
     L.fcat_fdk.restype = st
+    L.fcat_effective_psf.argtypes = [sp, psp, vp, vp]
+    L.fcat_effective_psf.restype = st
+    L.fcat_slit_lsf_range.argtypes = [C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.fcat_slit_lsf_range.restype = st
+    L.fcat_slit_mtf_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.fcat_slit_mtf_workspace_bytes.restype = sz
+    L.fcat_slit_mtf.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                vp, C.c_int32, vp, vp, vp, vp, sz, vp]
+    L.fcat_slit_mtf.restype = st
+    L.fcat_richardson_lucy_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.fcat_richardson_lucy_workspace_bytes.restype = sz
+    L.fcat_richardson_lucy.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32, C.c_int32, vp, vp, sz, vp]
+    L.fcat_richardson_lucy.restype = st
     L.fcat_timing_enable.argtypes = [C.c_int]
     L.fcat_timing_enable.restype = st
     L.fcat_timing_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int]
@@ -689,6 +703,60 @@ def fcat_fdk(geometry: Geometry, proj, grid, volume=None, workspace=None, angles
     _check(load().fcat_fdk(C.byref(cg), _ptr(proj), C.byref(cv), _ptr(volume), _ptr(workspace),
                            0 if workspace is None else workspace.numel(), _stream(stream)))
     return volume
+
+
+# ------------------------------------------------------------- detector optics
+
+def fcat_effective_psf(spectral: Spectral, psf: Psf, out=None, stream=None):
+    """sum_g W_g K_g / sum_g W_g as a device float tensor [k][k]."""
+    torch = _require_gpu()
+    k = int(psf.kernels.shape[1])
+    if out is None:
+        out = torch.empty((k, k), dtype=torch.float32, device=psf.kernels.device)
+    cs, _keep = spectral.c()
+    cps = psf.c()
+    _check(load().fcat_effective_psf(C.byref(cs), C.byref(cps), _ptr(out), _stream(stream)))
+    return out
+
+
+def fcat_slit_lsf_range(pitch: float, tilt_deg: float, n_rows: int, n_cols: int, oversample: int):
+    """(b_min, n_bins) of the presampled LSF."""
+    b, n = C.c_int32(), C.c_int32()
+    _check(load().fcat_slit_lsf_range(float(pitch), float(tilt_deg), int(n_rows), int(n_cols), int(oversample),
+                                      C.byref(b), C.byref(n)))
+    return int(b.value), int(n.value)
+
+
+def fcat_slit_mtf(kernel, pitch: float, width: float, tilt_deg: float, n_rows: int, n_cols: int, oversample: int,
+                  freqs, stream=None):
+    """(mtf [n_freq], lsf [n_bins], counts [n_bins], b_min) as device tensors (float64, int32)."""
+    torch = _require_gpu()
+    dev = kernel.device
+    b_min, n_bins = fcat_slit_lsf_range(pitch, tilt_deg, n_rows, n_cols, oversample)
+    f = torch.as_tensor(np.asarray(freqs, np.float64), device=dev)
+    mtf = torch.empty(f.numel(), dtype=torch.float64, device=dev)
+    lsf = torch.empty(n_bins, dtype=torch.float64, device=dev)
+    cnt = torch.empty(n_bins, dtype=torch.int32, device=dev)
+    ws = _workspace(int(load().fcat_slit_mtf_workspace_bytes(int(n_rows), int(n_cols), n_bins)), dev)
+    _check(load().fcat_slit_mtf(_ptr(kernel), int(kernel.shape[0]), float(pitch), float(width), float(tilt_deg),
+                                int(n_rows), int(n_cols), int(oversample), _ptr(f), int(f.numel()), _ptr(mtf),
+                                _ptr(lsf), _ptr(cnt), _ptr(ws), ws.numel(), _stream(stream)))
+    return mtf, lsf, cnt, b_min
+
+
+def fcat_richardson_lucy(images, kernel, iterations: int, out=None, workspace=None, stream=None):
+    """Richardson-Lucy deconvolution of images [n][nv][nu] with one kernel [k][k]."""
+    torch = _require_gpu()
+    n, nv, nu = (int(x) for x in images.shape)
+    k = int(kernel.shape[0])
+    if out is None:
+        out = torch.empty_like(images)
+    if workspace is None:
+        workspace = _workspace(int(load().fcat_richardson_lucy_workspace_bytes(n, nv, nu, k)), images.device)
+    _check(load().fcat_richardson_lucy(_ptr(images), n, nv, nu, _ptr(kernel), k, int(iterations), _ptr(out),
+                                       _ptr(workspace), 0 if workspace is None else workspace.numel(),
+                                       _stream(stream)))
+    return out
 
 
 # ------------------------------------------------------------- surrogate

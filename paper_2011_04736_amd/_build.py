@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfcat.so")
-SOURCES = ["fcat_abi.hip", "fcat_kernels.hip", "fcat_split.hip", "fcat_mlp.hip", "fcat_noise.hip", "fcat_dose.hip", "fcat_fdk.hip"]
+SOURCES = ["fcat_abi.hip", "fcat_kernels.hip", "fcat_split.hip", "fcat_mlp.hip", "fcat_noise.hip", "fcat_dose.hip", "fcat_fdk.hip", "fcat_optics.hip"]
 ARCH = os.environ.get("FCAT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for all device code.

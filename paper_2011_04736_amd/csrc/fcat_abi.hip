@@ -2,6 +2,7 @@
 // angle chunking and kernel launches.  See include/fcat.h for the contract.
 #include "fcat_internal.h"
 #include "fcat_recon.h"
+#include "fcat_optics.h"
 
 #include <algorithm>
 #include <cmath>
@@ -900,6 +901,181 @@ fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const f
         if (e != hipSuccess) return device_fail(e, "fdk_filter");
         if ((s = fdk_backproject(geometry, filt, a0, a0 + n, v, volume, a0 > 0, cs, stream))) return s;
     }
+    return FCAT_OK;
+}
+
+// ------------------------------------------------------------ optics
+
+fcat_status fcat_effective_psf(const fcat_spectral_t *spectral, const fcat_psf_t *psf, float *kernel, void *stream)
+{
+    g_last_error.clear();
+    SpecTables t{};
+    fcat_status s;
+    if ((s = check_spectral(spectral, false, t))) return s;
+    if (!psf) return fail(FCAT_E_INVALID_ARG, "psf is NULL");
+    if ((s = check_psf(psf))) return s;
+    if (!spectral->phi || !spectral->eta || !kernel) return fail(FCAT_E_INVALID_ARG, "phi, eta and kernel must not be NULL");
+    if ((s = check_pending())) return s;
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_OPTICS, static_cast<hipStream_t>(stream));
+        e = launch_effective_psf(spectral->phi, spectral->eta, t.gstart, t.G, psf->kernels, psf->k, kernel,
+                                 static_cast<hipStream_t>(stream));
+    }
+    if (e != hipSuccess) return device_fail(e, "effective_psf");
+    return FCAT_OK;
+}
+
+static fcat_status slit_geom(double pitch, double width, double tilt_deg, int n_rows, int n_cols, int oversample,
+                             SlitGeom &sg)
+{
+    if (!finite_pos(pitch)) return fail(FCAT_E_INVALID_ARG, "pitch must be finite and > 0");
+    if (!(width >= 0.0) || !std::isfinite(width)) return fail(FCAT_E_INVALID_ARG, "width must be finite and >= 0");
+    if (!(tilt_deg > 0.0 && tilt_deg < 90.0)) return fail(FCAT_E_INVALID_ARG, "tilt must be in (0, 90) degrees");
+    if (n_rows < 1 || n_cols < 1 || (int64_t)n_rows * n_cols > ((int64_t)1 << 26))
+        return fail(FCAT_E_INVALID_ARG, "need 1 <= n_rows, n_cols and n_rows n_cols <= 2^26");
+    if (oversample < 1 || oversample > 1024) return fail(FCAT_E_INVALID_ARG, "oversample must be in 1..1024");
+    const double t = tilt_deg * 3.141592653589793 / 180.0;
+    sg.pitch = pitch;
+    sg.width = width;
+    sg.cos_t = std::cos(t);
+    sg.sin_t = std::sin(t);
+    sg.h = pitch / (double)oversample;
+    sg.n_rows = n_rows;
+    sg.n_cols = n_cols;
+    double dmin = 1e300, dmax = -1e300;
+    for (int ci = 0; ci < 4; ++ci) {
+        const int i = (ci & 1) ? n_rows - 1 : 0, j = (ci & 2) ? n_cols - 1 : 0;
+        const double x = ((double)j - (double)(n_cols - 1) / 2.0) * pitch;
+        const double y = ((double)i - (double)(n_rows - 1) / 2.0) * pitch;
+        const double d = sg.cos_t * x + sg.sin_t * y;
+        dmin = std::min(dmin, d);
+        dmax = std::max(dmax, d);
+    }
+    const double bl = std::floor(dmin / sg.h + 0.5), bh = std::floor(dmax / sg.h + 0.5);
+    if (bh - bl + 1.0 > 1.0e7) return fail(FCAT_E_INVALID_ARG, "too many LSF bins");
+    sg.b_min = (int)bl;
+    sg.n_bins = (int)(bh - bl) + 1;
+    return FCAT_OK;
+}
+
+fcat_status fcat_slit_lsf_range(double pitch_mm, double tilt_deg, int32_t n_rows, int32_t n_cols, int32_t oversample,
+                                int32_t *b_min, int32_t *n_bins)
+{
+    g_last_error.clear();
+    SlitGeom sg{};
+    fcat_status s;
+    if ((s = slit_geom(pitch_mm, 0.0, tilt_deg, n_rows, n_cols, oversample, sg))) return s;
+    if (!b_min || !n_bins) return fail(FCAT_E_INVALID_ARG, "b_min and n_bins must not be NULL");
+    *b_min = sg.b_min;
+    *n_bins = sg.n_bins;
+    return FCAT_OK;
+}
+
+size_t fcat_slit_mtf_workspace_bytes(int32_t n_rows, int32_t n_cols, int32_t n_bins)
+{
+    if (n_rows < 1 || n_cols < 1 || n_bins < 1) return 0;
+    const size_t img = align_up((size_t)n_rows * n_cols * sizeof(float));
+    return 2 * img + align_up((size_t)n_bins * sizeof(double)) + align_up((size_t)n_bins * sizeof(int));
+}
+
+fcat_status fcat_slit_mtf(const float *kernel, int32_t k, double pitch_mm, double width_mm, double tilt_deg,
+                          int32_t n_rows, int32_t n_cols, int32_t oversample, const double *freqs, int32_t n_freq,
+                          double *mtf, double *lsf, int32_t *lsf_count, void *workspace, size_t workspace_bytes,
+                          void *stream_)
+{
+    g_last_error.clear();
+    SlitGeom sg{};
+    fcat_status s;
+    if ((s = slit_geom(pitch_mm, width_mm, tilt_deg, n_rows, n_cols, oversample, sg))) return s;
+    if (!kernel || k < 1 || k > FCAT_MAX_PSF || (k % 2) == 0)
+        return fail(FCAT_E_INVALID_ARG, "kernel must be given with odd k in 1..%d", FCAT_MAX_PSF);
+    if (n_freq < 0 || (n_freq > 0 && (!freqs || !mtf))) return fail(FCAT_E_INVALID_ARG, "freqs and mtf must be given");
+    const size_t need = fcat_slit_mtf_workspace_bytes(n_rows, n_cols, sg.n_bins);
+    if ((s = check_workspace(workspace, workspace_bytes, need))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const size_t img = align_up((size_t)n_rows * n_cols * sizeof(float));
+    float *slit = at<float>(workspace, 0), *blurred = at<float>(workspace, img);
+    double *lsf_w = lsf ? lsf : at<double>(workspace, 2 * img);
+    int *cnt_w = lsf_count ? lsf_count : at<int>(workspace, 2 * img + align_up((size_t)sg.n_bins * sizeof(double)));
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_OPTICS, stream);
+        e = launch_slit_image(sg, slit, stream);
+    }
+    if (e == hipSuccess) {
+        StageTimer tm(FCAT_STAGE_PSF, stream);
+        e = launch_psf(slit, 1, 1, n_rows, n_cols, kernel, k, blurred, stream);
+    }
+    if (e == hipSuccess) {
+        StageTimer tm(FCAT_STAGE_OPTICS, stream);
+        e = launch_slit_lsf(sg, blurred, lsf_w, cnt_w, stream);
+        if (e == hipSuccess && n_freq > 0) e = launch_slit_mtf(sg, lsf_w, cnt_w, freqs, n_freq, mtf, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "slit_mtf");
+    return FCAT_OK;
+}
+
+size_t fcat_richardson_lucy_workspace_bytes(int32_t n, int32_t nv, int32_t nu, int32_t k)
+{
+    if (n < 1 || nv < 1 || nu < 1 || k < 1) return 0;
+    const size_t plane = (size_t)nv * nu;
+    return 2 * align_up((size_t)n * plane * sizeof(float)) + align_up(plane * sizeof(float)) +
+           align_up((size_t)k * k * sizeof(float));
+}
+
+fcat_status fcat_richardson_lucy(const float *images, int32_t n, int32_t nv, int32_t nu, const float *kernel, int32_t k,
+                                 int32_t iterations, float *out, void *workspace, size_t workspace_bytes,
+                                 void *stream_)
+{
+    g_last_error.clear();
+    fcat_status s;
+    if (n < 1 || n > 65535 || nv < 1 || nu < 1) return fail(FCAT_E_INVALID_ARG, "need 1 <= n <= 65535, nv, nu >= 1");
+    if ((int64_t)nv * nu >= ((int64_t)1 << 31)) return fail(FCAT_E_INVALID_ARG, "nv * nu must be < 2^31");
+    if (!kernel || k < 1 || k > FCAT_MAX_PSF || (k % 2) == 0)
+        return fail(FCAT_E_INVALID_ARG, "kernel must be given with odd k in 1..%d", FCAT_MAX_PSF);
+    if (iterations < 0) return fail(FCAT_E_INVALID_ARG, "iterations must be >= 0");
+    if (!images || !out) return fail(FCAT_E_INVALID_ARG, "images and out must not be NULL");
+    const int64_t plane = (int64_t)nv * nu, total = (int64_t)n * plane;
+    const char *d0 = reinterpret_cast<const char *>(images), *o0 = reinterpret_cast<const char *>(out);
+    if (d0 < o0 + total * 4 && o0 < d0 + total * 4) return fail(FCAT_E_INVALID_ARG, "images and out overlap");
+    if ((s = check_workspace(workspace, workspace_bytes, fcat_richardson_lucy_workspace_bytes(n, nv, nu, k)))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    const size_t big = align_up((size_t)total * sizeof(float));
+    float *c = at<float>(workspace, 0), *t = at<float>(workspace, big);
+    float *norm = at<float>(workspace, 2 * big);
+    float *kt = at<float>(workspace, 2 * big + align_up((size_t)plane * sizeof(float)));
+    hipError_t e = hipMemcpyAsync(out, images, (size_t)total * sizeof(float), hipMemcpyDeviceToDevice, stream);
+    {
+        StageTimer tm(FCAT_STAGE_OPTICS, stream);
+        if (e == hipSuccess) e = launch_flip_kernel(kernel, k, kt, stream);
+        if (e == hipSuccess) e = launch_fill_value(c, plane, 1.0f, stream);
+    }
+    if (e == hipSuccess) {
+        StageTimer tm(FCAT_STAGE_PSF, stream);
+        e = launch_psf(c, 1, 1, nv, nu, kt, k, norm, stream);
+    }
+    for (int it = 0; e == hipSuccess && it < iterations; ++it) {
+        {
+            StageTimer tm(FCAT_STAGE_PSF, stream);
+            e = launch_psf(out, n, 1, nv, nu, kernel, k, c, stream);
+        }
+        if (e == hipSuccess) {
+            StageTimer tm(FCAT_STAGE_OPTICS, stream);
+            e = launch_rl_ratio(images, c, total, stream);
+        }
+        if (e == hipSuccess) {
+            StageTimer tm(FCAT_STAGE_PSF, stream);
+            e = launch_psf(c, n, 1, nv, nu, kt, k, t, stream);
+        }
+        if (e == hipSuccess) {
+            StageTimer tm(FCAT_STAGE_OPTICS, stream);
+            e = launch_rl_update(out, t, norm, plane, total, stream);
+        }
+    }
+    if (e != hipSuccess) return device_fail(e, "richardson_lucy");
     return FCAT_OK;
 }
 
