@@ -51,6 +51,8 @@ def parse():
                     help="H of Eq. 5 (flood counts per open pixel) for the noise stage; 0 skips it")
     ap.add_argument("--dose", type=int, default=1, help="1: time the dose estimate of Eqs. 6-7 (0 skips it)")
     ap.add_argument("--fdk", type=int, default=1, help="1: time the FDK reconstruction of the projections (0 skips it)")
+    ap.add_argument("--rl-iterations", type=int, default=10,
+                    help="Richardson-Lucy iterations on the detected profiles (0 skips the optics stage)")
     ap.add_argument("--forms", default="split_bf16,surrogate",
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
@@ -128,6 +130,42 @@ def profiled_traffic(kernel: str, digest: str):
 
 
 # ----------------------------------------------------------------- forms
+
+def optics_stage(pb, cfg, args, torch, fc):
+    """Effective PSF and its presampled MTF from a 0.3 mm slit tilted by 2.5
+    degrees (Sec. II.D), then Richardson-Lucy deconvolution of the workload's
+    360 detected profiles with it (two 15 x 15 convolutions per iteration)."""
+    g = cfg.geometry
+    out = fc.fcat_project(pb)
+    K = fc.fcat_effective_psf(pb.spectral, pb.psf)
+    freqs = np.linspace(0.0, 1.0 / g.du, 65)
+    mtf, _, _, _ = fc.fcat_slit_mtf(K, g.du, 0.3, 2.5, 256, 64, 10, freqs)
+    m = mtf.cpu().numpy()
+    f50 = float(np.interp(0.5, m[::-1], freqs[::-1])) if m.min() < 0.5 else None
+    k = int(K.shape[0])
+    ws = torch.empty(fc.fcat_richardson_lucy_workspace_bytes(g.n_angles, g.nv, g.nu, k), dtype=torch.uint8,
+                     device=out.device)
+    dec = torch.empty_like(out)
+    stream = torch.cuda.current_stream()
+    elapsed, stages = timed_steps(lambda: fc.fcat_richardson_lucy(out, K, args.rl_iterations, out=dec, workspace=ws,
+                                                                  stream=stream), 1, args.form_steps, torch)
+    psf_ms = stages["psf"][0] / args.form_steps
+    flops = 2.0 * 2 * k * k * g.n_angles * g.nv * g.nu * args.rl_iterations
+    ach = flops / (psf_ms * 1e-3) / 1e12
+    finite = bool(torch.isfinite(dec).all().item())
+    del ws, dec, out
+    return {
+        "ms_per_step": round(1e3 * elapsed / args.form_steps, 4),
+        "steps": args.form_steps,
+        "iterations": args.rl_iterations,
+        "stages_ms_per_step": {kk: round(v[0] / args.form_steps, 4) for kk, v in stages.items() if v[1]},
+        "mtf50_per_mm": f50,
+        "finite": finite,
+        "roofline": {"kernel": "k_psf4<15,8> (one group)", "bound": "alu", "achieved": round(ach, 3),
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "stage_ms": round(psf_ms, 4), "algorithmic_flops_per_step": flops, "traffic": None},
+    }
+
 
 def fdk_stage(pb, cfg, args, torch, fc):
     """FDK reconstruction of the workload's noiseless projections into the
@@ -461,6 +499,8 @@ def main():
         result["next"]["dose"] = dose_stage(pb, cfg, args, torch, fc, cnt["hit_rays"])
     if args.fdk:
         result["next"]["fdk"] = fdk_stage(pb, cfg, args, torch, fc)
+    if args.rl_iterations > 0:
+        result["next"]["optics"] = optics_stage(pb, cfg, args, torch, fc)
     del pb
     torch.cuda.empty_cache()
     if "surrogate" in forms:
