@@ -671,6 +671,10 @@ def fcat_fdk_filter(geometry: Geometry, proj, out=None, stream=None):
     return out
 
 
+def fcat_fdk_backproject_workspace_bytes(n_ang: int) -> int:
+    return int(load().fcat_fdk_backproject_workspace_bytes(int(n_ang)))
+
+
 def fcat_fdk_backproject(geometry: Geometry, filtered, grid, a_begin: int = 0, volume=None, accumulate: bool = False,
                          workspace=None, stream=None):
     """FDK back-projection of filtered projections of angles a_begin .. a_begin + n - 1."""
@@ -679,7 +683,7 @@ def fcat_fdk_backproject(geometry: Geometry, filtered, grid, a_begin: int = 0, v
     if volume is None:
         volume = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float32, device=filtered.device)
     if workspace is None:
-        workspace = _workspace(int(load().fcat_fdk_backproject_workspace_bytes(n)), filtered.device)
+        workspace = _workspace(fcat_fdk_backproject_workspace_bytes(n), filtered.device)
     cg, cv = geometry.c(), _cgrid(grid)
     _check(load().fcat_fdk_backproject(C.byref(cg), _ptr(filtered), int(a_begin), int(a_begin) + n, C.byref(cv),
                                        _ptr(volume), 1 if accumulate else 0, _ptr(workspace),
@@ -737,11 +741,19 @@ def fcat_slit_mtf(kernel, pitch: float, width: float, tilt_deg: float, n_rows: i
     mtf = torch.empty(f.numel(), dtype=torch.float64, device=dev)
     lsf = torch.empty(n_bins, dtype=torch.float64, device=dev)
     cnt = torch.empty(n_bins, dtype=torch.int32, device=dev)
-    ws = _workspace(int(load().fcat_slit_mtf_workspace_bytes(int(n_rows), int(n_cols), n_bins)), dev)
+    ws = _workspace(fcat_slit_mtf_workspace_bytes(n_rows, n_cols, n_bins), dev)
     _check(load().fcat_slit_mtf(_ptr(kernel), int(kernel.shape[0]), float(pitch), float(width), float(tilt_deg),
                                 int(n_rows), int(n_cols), int(oversample), _ptr(f), int(f.numel()), _ptr(mtf),
                                 _ptr(lsf), _ptr(cnt), _ptr(ws), ws.numel(), _stream(stream)))
     return mtf, lsf, cnt, b_min
+
+
+def fcat_richardson_lucy_workspace_bytes(n: int, nv: int, nu: int, k: int) -> int:
+    return int(load().fcat_richardson_lucy_workspace_bytes(int(n), int(nv), int(nu), int(k)))
+
+
+def fcat_slit_mtf_workspace_bytes(n_rows: int, n_cols: int, n_bins: int) -> int:
+    return int(load().fcat_slit_mtf_workspace_bytes(int(n_rows), int(n_cols), int(n_bins)))
 
 
 def fcat_richardson_lucy(images, kernel, iterations: int, out=None, workspace=None, stream=None):
@@ -752,7 +764,7 @@ def fcat_richardson_lucy(images, kernel, iterations: int, out=None, workspace=No
     if out is None:
         out = torch.empty_like(images)
     if workspace is None:
-        workspace = _workspace(int(load().fcat_richardson_lucy_workspace_bytes(n, nv, nu, k)), images.device)
+        workspace = _workspace(fcat_richardson_lucy_workspace_bytes(n, nv, nu, k), images.device)
     _check(load().fcat_richardson_lucy(_ptr(images), n, nv, nu, _ptr(kernel), k, int(iterations), _ptr(out),
                                        _ptr(workspace), 0 if workspace is None else workspace.numel(),
                                        _stream(stream)))
