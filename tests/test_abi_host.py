@@ -129,3 +129,70 @@ def test_other_entry_points_reject_bad_args(fc):
     assert lib.fcat_psf(0x1000, 0, 2, 4, 4, C.byref(ps), 0x2000, None) == 1
     assert lib.fcat_check_inputs(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, 0, None) == 2
     assert lib.fcat_spectral_workspace_bytes(C.byref(sp)) > 0
+
+
+def test_noise_dose_fdk_optics_reject_bad_args(fc):
+    lib = fc.load()
+    geo, ph, sp, ps = _descs(fc)
+    W = 0x10000
+    # noise and projections
+    assert lib.fcat_count_scale(C.byref(sp), 0.0, 0x1000, None) == 1
+    assert lib.fcat_count_scale(C.byref(sp), float("inf"), 0x1000, None) == 1
+    assert lib.fcat_poisson(0x1000, 1, 0, 16, 0x2000, 1, 0, None) == 1          # no groups
+    assert lib.fcat_poisson(0x1000, 1, 2, 1 << 31, 0x2000, 1, 0, None) == 1     # plane too large
+    assert lib.fcat_poisson(0x1000, 1, 2, 16, 0x2000, 1, -1, None) == 1         # negative angle base
+    assert lib.fcat_poisson(None, 1, 2, 16, 0x2000, 1, 0, None) == 1
+    assert lib.fcat_log_projection(0x1000, 0x2000, 1, 16, -1.0, 0x3000, None) == 1
+    assert lib.fcat_log_projection(0x1000, None, 1, 16, 0.0, 0x3000, None) == 1
+    nz = fc._CNoise(-5.0, 1, 0.0)
+    assert lib.fcat_projections(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, None, C.byref(nz),
+                                0x1000, W, 1 << 26, None) == 1
+    nz = fc._CNoise(1e4, 1, -1.0)
+    assert lib.fcat_projections(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, None, C.byref(nz),
+                                0x1000, W, 1 << 26, None) == 1
+    assert lib.fcat_projections_workspace_bytes(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, 0) > \
+        lib.fcat_project_workspace_bytes(C.byref(geo), C.byref(ph), C.byref(sp), None, None, 0, 0)
+    # dose
+    assert lib.fcat_dose(C.byref(geo), C.byref(ph), C.byref(sp), 0x1000, 0x2000, 0.0, 0, 1, 0x3000, None, W,
+                         1 << 26, None) == 1
+    assert lib.fcat_dose(C.byref(geo), C.byref(ph), C.byref(sp), 0x1000, 0x2000, 1.0, 2, 2, 0x3000, None, W,
+                         1 << 26, None) == 1
+    assert lib.fcat_dose(C.byref(geo), C.byref(ph), C.byref(sp), None, 0x2000, 1.0, 0, 1, 0x3000, None, W,
+                         1 << 26, None) == 1
+    assert lib.fcat_dose(C.byref(geo), C.byref(ph), C.byref(sp), 0x1000, 0x2000, 1.0, 0, 1, 0x3000, None, W,
+                         16, None) == 2
+    # FDK
+    grid = fc._CGrid(4, 4, 0, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
+    assert lib.fcat_fdk(C.byref(geo), 0x1000, C.byref(grid), 0x2000, W, 1 << 26, None) == 1
+    grid = fc._CGrid(4, 4, 2, 1.0, -1.0, 1.0, 0.0, 0.0, 0.0)
+    assert lib.fcat_fdk(C.byref(geo), 0x1000, C.byref(grid), 0x2000, W, 1 << 26, None) == 1
+    grid = fc._CGrid(4, 4, 2, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
+    assert lib.fcat_fdk(C.byref(geo), 0x1000, C.byref(grid), 0x2000, W, 64, None) == 2
+    assert lib.fcat_fdk_filter(C.byref(geo), 0x1000, 0, 0x2000, None) == 1
+    assert lib.fcat_fdk_filter(C.byref(geo), 0x1000, 3, 0x1010, None) == 1      # overlapping buffers
+    assert lib.fcat_fdk_backproject(C.byref(geo), 0x1000, 1, 1, C.byref(grid), 0x2000, 0, W, 4096, None) == 1
+    assert lib.fcat_fdk_backproject_workspace_bytes(360) == 3072 and lib.fcat_fdk_backproject_workspace_bytes(0) == 0  # 256-byte aligned
+    big = fc._CGeometry(1000.0, 1500.0, 9000, 4, 1.0, 1.0, 0.0, 0.0, 3, None)
+    assert lib.fcat_fdk_filter(C.byref(big), 0x1000, 3, 0x8000000, None) == 6   # unsupported width
+    # optics
+    assert lib.fcat_effective_psf(C.byref(sp), None, 0x1000, None) == 1
+    b, n = C.c_int32(), C.c_int32()
+    assert lib.fcat_slit_lsf_range(0.4, 0.0, 64, 32, 10, C.byref(b), C.byref(n)) == 1   # tilt must be > 0
+    assert lib.fcat_slit_lsf_range(0.4, 2.5, 64, 32, 0, C.byref(b), C.byref(n)) == 1
+    assert lib.fcat_slit_mtf(0x1000, 4, 0.4, 0.3, 2.5, 64, 32, 10, 0x2000, 5, 0x3000, None, None, W, 1 << 20,
+                             None) == 1                                           # even kernel
+    assert lib.fcat_richardson_lucy(0x1000, 1, 8, 8, 0x2000, 15, -1, 0x9000, W, 1 << 20, None) == 1
+    assert lib.fcat_richardson_lucy(0x1000, 1, 8, 8, 0x2000, 15, 3, 0x1010, W, 1 << 20, None) == 1   # overlap
+    assert lib.fcat_richardson_lucy(0x1000, 1, 8, 8, 0x2000, 15, 3, 0x9000, W, 64, None) == 2
+
+
+def test_slit_bin_range_matches_the_oracle():
+    # the bin range is host arithmetic: it must cover exactly the bins the
+    # oracle's presampling fills
+    import paper_2011_04736_amd as fcm
+    from oracle import optics as op
+    for (p, tilt, nr, nc, over) in [(0.392, 2.5, 160, 48, 10), (0.336, 4.0, 33, 17, 7)]:
+        b_min, n_bins = fcm.fcat_slit_lsf_range(p, tilt, nr, nc, over)
+        d, _ = op.presampled_lsf(np.ones((nr, nc)), p, tilt, over)
+        b = np.round(d / (p / over)).astype(np.int64)
+        assert b.min() == b_min and b.max() == b_min + n_bins - 1
