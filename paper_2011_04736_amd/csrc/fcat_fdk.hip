@@ -26,12 +26,14 @@ __global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *_
     const int nq = (g.nu + 1) / 2;                   // samples per half (the odd half zero-padded)
     const int ngrp = (nq + kRampOut - 1) / kRampOut;
     const int ntab = 2 * nq + kRampOut + 1;
-    float *__restrict__ tab = lds;                   // tab[j] = G[j - nq], G[d] = h((2d - 1) tau) tau
-    float *__restrict__ half = lds + ntab;           // [rows_per_block][2][nq]
+    // tab[j + j / 8] = G[j - nq], G[d] = h((2d - 1) tau) tau: one pad word per 8
+    // makes the lanes' reads (8 entries apart) fall in different banks
+    float *__restrict__ tab = lds;
+    float *__restrict__ half = lds + ntab + ntab / 8 + 1;   // [rows_per_block][2][nq]
     const float pi2tau = 9.869604401089358f * g.tau;
     for (int j = (int)threadIdx.x; j < ntab; j += kBlock) {
         const float m = (float)(2 * (j - nq) - 1);   // odd offset
-        tab[j] = -1.0f / (m * m * pi2tau);
+        tab[j + (j >> 3)] = -1.0f / (m * m * pi2tau);
     }
     const int row0 = blockIdx.x * rows_per_block;
     const int nr = min(rows_per_block, n_rows - row0);
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *_
         float win[kRampOut], acc[kRampOut];
 #pragma unroll
         for (int q = 0; q < kRampOut; ++q) {
-            win[q] = tab[base + q];
+            win[q] = tab[base + q + ((base + q) >> 3)];
             acc[q] = 0.0f;
         }
 #pragma unroll 8
@@ -74,7 +76,8 @@ __global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *_
             for (int q = 0; q < kRampOut; ++q) acc[q] = fmaf(win[q], xv, acc[q]);
 #pragma unroll
             for (int q = kRampOut - 1; q > 0; --q) win[q] = win[q - 1];
-            win[0] = tab[base - l - 1];
+            const int j = base - l - 1;
+            win[0] = tab[j + (j >> 3)];
         }
         const int row = row0 + r;
 #pragma unroll
@@ -170,7 +173,8 @@ hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, flo
     const int rows = n_ang * g.nv;
     int rpb = kBlock / (2 * ngrp);
     if (rpb < 1) rpb = 1;
-    const size_t lds = (size_t)(2 * nq + kRampOut + 1 + rpb * 2 * nq) * sizeof(float);
+    const int ntab = 2 * nq + kRampOut + 1;
+    const size_t lds = (size_t)(ntab + ntab / 8 + 1 + rpb * 2 * nq) * sizeof(float);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     const int nblk = (rows + rpb - 1) / rpb;
     hipLaunchKernelGGL(k_fdk_filter, dim3(nblk), dim3(kBlock), lds, stream, g, proj, rows, rpb, filt);
