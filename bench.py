@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--fdk", type=int, default=1, help="1: time the FDK reconstruction of the projections (0 skips it)")
     ap.add_argument("--rl-iterations", type=int, default=10,
                     help="Richardson-Lucy iterations on the detected profiles (0 skips the optics stage)")
+    ap.add_argument("--ceilings", type=int, default=1,
+                    help="1: run the device-ceiling microbenchmark and add fractions of the measured ceilings")
     ap.add_argument("--forms", default="split_bf16,surrogate",
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
@@ -506,10 +508,53 @@ def main():
     if "surrogate" in forms:
         result["forms"]["surrogate"] = form_surrogate(args, torch, fc)
 
+    if args.ceilings:
+        add_measured_ceilings(result)
     if args.cpu_angles > 0:
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_angles, ray_e / g.n_angles)
 
     print(json.dumps(result))
+
+
+def measured_ceiling(entry: dict, ceil: dict):
+    """The microbenchmark rate that bounds a roofline entry, in the entry's unit."""
+    bound, unit = entry.get("bound"), entry.get("unit")
+    if bound == "hbm" and unit == "GB/s":
+        return ceil["copy_GBps"]
+    if bound == "alu" and unit == "TFLOP/s":
+        return ceil["fma_f32_TFLOPs"]
+    if bound == "alu" and unit == "Top/s":
+        return ceil["fma_f32_TFLOPs"] / 2.0        # one FMA is one lane-operation
+    if bound == "mfma" and unit == "TFLOP/s":
+        return ceil["mfma_bf16_TFLOPs"]
+    return None
+
+
+def add_measured_ceilings(result: dict) -> None:
+    """Run the ceiling microbenchmark (a child process) and add measured_peak / frac_measured
+    beside every roofline entry whose bound it measures."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2011_04736_amd", "fcat_ceilings")
+    if not os.path.exists(exe):
+        result["ceilings"] = {"error": "fcat_ceilings not built"}
+        return
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if r.returncode != 0:
+        result["ceilings"] = {"error": r.stderr.strip()[-300:]}
+        return
+    ceil = json.loads(r.stdout.strip().splitlines()[-1])
+    result["ceilings"] = ceil
+    entries = [result["roofline"], *result["kernels"].values()]
+    for group in ("forms", "next"):
+        for v in result.get(group, {}).values():
+            for key in ("roofline", "filter"):
+                if isinstance(v, dict) and isinstance(v.get(key), dict):
+                    entries.append(v[key])
+    for e in entries:
+        m = measured_ceiling(e, ceil)
+        if m:
+            e["measured_peak"] = round(m, 2)
+            e["frac_measured"] = round(e["achieved"] / m, 4)
 
 
 def cpu_baseline(cfg, n_angles: int, ray_e_per_angle: float) -> dict:

@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfcat.so")
+CEILINGS = os.path.join(HERE, "fcat_ceilings")      # device-ceiling microbenchmark (stand-alone program)
 SOURCES = ["fcat_abi.hip", "fcat_kernels.hip", "fcat_split.hip", "fcat_mlp.hip", "fcat_noise.hip", "fcat_dose.hip", "fcat_fdk.hip", "fcat_optics.hip"]
 ARCH = os.environ.get("FCAT_OFFLOAD_ARCH", "gfx950")
 
@@ -53,8 +54,13 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    cmd = [_hipcc(), *HIPCC_FLAGS, *extra, os.path.join(CSRC, "fcat_ceilings.hip"), "-o", CEILINGS + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for fcat_ceilings.hip:\n{r.stdout}\n{r.stderr}")
+    os.replace(CEILINGS + ".tmp", CEILINGS)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {CEILINGS}")
     return LIB
 
 

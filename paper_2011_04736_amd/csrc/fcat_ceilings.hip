@@ -1,0 +1,183 @@
+// Measured ceilings of the device, beside the published peaks the benchmark
+// prices its kernels against: a streaming copy (HBM), independent FP32 and
+// FP64 FMA chains on the vector units (built like the library: no packed
+// FP32), the hardware base-2 exponential, and BF16 matrix-core products.
+// Each loop keeps enough independent chains per lane, and enough waves per
+// SIMD, to hide latency, and stores a value that depends on every step.
+//
+// Stand-alone program, no arguments: prints one JSON object with the rate of
+// each loop (best of the timed launches).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kChains = 8;
+constexpr int kIters = 4096;
+constexpr int kBlocks = 256 * 8;             // 8 waves of 64 lanes per SIMD on 256 CUs x 4 SIMDs
+constexpr int64_t kCopyBytes = 1ll << 31;    // 2 GiB read, 2 GiB written
+constexpr int kCopyBlocks = 8192;
+constexpr int kTimed = 10;
+
+#define CHECK(x)                                                                               \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) {                                                                \
+            std::fprintf(stderr, "%s:%d %s: %s\n", __FILE__, __LINE__, #x, hipGetErrorString(e_)); \
+            std::exit(1);                                                                      \
+        }                                                                                      \
+    } while (0)
+
+__global__ void __launch_bounds__(kBlock) k_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_fma32(float seed, float *__restrict__ out)
+{
+    float a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = seed + (float)(threadIdx.x + c);
+    const float m = 0.999999f, k = 1e-7f;
+    for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) a[c] = fmaf(a[c], m, k);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s += a[c];
+    out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fma64(double seed, double *__restrict__ out)
+{
+    double a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = seed + (double)(threadIdx.x + c);
+    const double m = 0.999999, k = 1e-7;
+    for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) a[c] = fma(a[c], m, k);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s += a[c];
+    out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// x <- 2^-x converges (to about 0.64) and keeps every step dependent.
+__global__ void __launch_bounds__(kBlock) k_exp2(float seed, float *__restrict__ out)
+{
+    float a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = seed * (float)(c + 1);
+    for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) a[c] = __builtin_amdgcn_exp2f(-a[c]);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s += a[c];
+    out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMfmaChains = 4;
+constexpr int kMfmaIters = kIters / 4;
+
+// Independent 32x32x16 products per wave; the chains start from different
+// values so that the compiler cannot merge them.
+__global__ void __launch_bounds__(kBlock) k_mfma(float seed, float *__restrict__ out)
+{
+    bf16x8 a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = (__bf16)(seed + 1e-3f * (float)(threadIdx.x + j));
+        b[j] = (__bf16)(seed - 2e-3f * (float)j);
+    }
+    f32x16 acc[kMfmaChains];
+#pragma unroll
+    for (int c = 0; c < kMfmaChains; ++c) {
+        acc[c] = f32x16{};
+        acc[c][0] = (float)c;
+    }
+    for (int i = 0; i < kMfmaIters; ++i) {
+#pragma unroll
+        for (int c = 0; c < kMfmaChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kMfmaChains; ++c)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += acc[c][j];
+    out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// Best (shortest) duration in ms of kTimed launches after two untimed ones.
+template <typename F>
+float best_ms(F launch, hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    for (int i = 0; i < 2; ++i) launch();
+    CHECK(hipGetLastError());
+    CHECK(hipStreamSynchronize(s));
+    float best = 1e30f;
+    for (int i = 0; i < kTimed; ++i) {
+        CHECK(hipEventRecord(e0, s));
+        launch();
+        CHECK(hipEventRecord(e1, s));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) best = ms;
+    }
+    CHECK(hipGetLastError());
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    return best;
+}
+
+}  // namespace
+
+int main()
+{
+    hipStream_t s;
+    CHECK(hipStreamCreate(&s));
+    void *buf = nullptr;
+    CHECK(hipMalloc(&buf, 2 * kCopyBytes));
+    CHECK(hipMemsetAsync(buf, 0, 2 * kCopyBytes, s));
+    const int64_t n4 = kCopyBytes / (int64_t)sizeof(float4);
+    float4 *src = static_cast<float4 *>(buf), *dst = src + n4;
+    // every lane of the arithmetic loops stores one value (at most 8 bytes)
+    static_assert((int64_t)kBlocks * kBlock * 8 <= 2 * kCopyBytes, "probe output must fit the buffer");
+
+    const float t_copy = best_ms([&] { hipLaunchKernelGGL(k_copy, dim3(kCopyBlocks), dim3(kBlock), 0, s, src, dst, n4); }, s);
+    const float t_f32 = best_ms([&] { hipLaunchKernelGGL(k_fma32, dim3(kBlocks), dim3(kBlock), 0, s, 1.0f, (float *)buf); }, s);
+    const float t_f64 = best_ms([&] { hipLaunchKernelGGL(k_fma64, dim3(kBlocks), dim3(kBlock), 0, s, 1.0, (double *)buf); }, s);
+    const float t_exp = best_ms([&] { hipLaunchKernelGGL(k_exp2, dim3(kBlocks), dim3(kBlock), 0, s, 0.5f, (float *)buf); }, s);
+    const float t_mma = best_ms([&] { hipLaunchKernelGGL(k_mfma, dim3(kBlocks), dim3(kBlock), 0, s, 0.5f, (float *)buf); }, s);
+
+    const double lanes = (double)kBlocks * kBlock;
+    const double copy_bytes = 2.0 * (double)kCopyBytes;
+    const double fma_flop = 2.0 * lanes * kChains * kIters;
+    const double exps = lanes * kChains * kIters;
+    const double mfma_flop = 2.0 * 32 * 32 * 16 * ((double)kBlocks * (kBlock / kWave)) * kMfmaChains * kMfmaIters;
+
+    std::printf("{\"copy_GBps\": %.1f, \"fma_f32_TFLOPs\": %.2f, \"fma_f64_TFLOPs\": %.2f, "
+                "\"exp2_f32_Gps\": %.1f, \"mfma_bf16_TFLOPs\": %.1f, "
+                "\"ms\": {\"copy\": %.4f, \"fma_f32\": %.4f, \"fma_f64\": %.4f, \"exp2_f32\": %.4f, \"mfma_bf16\": %.4f}}\n",
+                copy_bytes / (t_copy * 1e-3) / 1e9, fma_flop / (t_f32 * 1e-3) / 1e12, fma_flop / (t_f64 * 1e-3) / 1e12,
+                exps / (t_exp * 1e-3) / 1e9, mfma_flop / (t_mma * 1e-3) / 1e12, t_copy, t_f32, t_f64, t_exp, t_mma);
+    CHECK(hipFree(buf));
+    CHECK(hipStreamDestroy(s));
+    return 0;
+}
