@@ -217,8 +217,11 @@ __global__ __launch_bounds__(kBlock) void k_psf(const float *__restrict__ Y, int
 // wavefront w owns columns 4l .. 4l + 3 and rows 4w .. 4w + 3 of a 256 x (4 * kP4Waves)
 // output tile.  For each input row it reads its K + 3 inputs with aligned
 // 16-byte LDS loads (immediate offsets, no address arithmetic) and feeds
-// each to up to 4 x 4 outputs; the kernel rows in use at once (at most 4)
-// stay in scalar registers.
+// each to up to 4 x 4 outputs.  The flipped kernel of the group is staged in
+// LDS beside the tile and each kernel row is read into vector registers
+// (a broadcast LDS read) where it is used: an FMA whose operands are all
+// vector registers can issue at up to about 1.6 times the rate of one that
+// reads a scalar register, given enough wavefronts per SIMD.
 constexpr int kP4Cols = 4 * kWave;              // 256 output columns per tile
 constexpr int kP4Waves = 8;                     // wavefronts per workgroup (4 and 16 measured slower)
 constexpr int kP4Rows = 4 * kP4Waves;           // output rows per tile
@@ -233,8 +236,11 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
     constexpr int ROWS = 4 * NW;
     constexpr int LH = ROWS + K - 1;
     constexpr int NT = NW * kWave;
+    constexpr int KW = (K + 3) / 4 * 4;           // kernel row stride in LDS (zero-padded)
     static_assert(LW % 4 == 0, "aligned rows");
+    static_assert(K * KW <= NT, "one thread per staged weight");
     __shared__ __align__(16) float tile[LH * LW];
+    __shared__ __align__(16) float wl[K * KW];   // wl[i][j] = K_g[K-1-i][K-1-j]
     const int u0 = blockIdx.x * kP4Cols;
     const int v0 = blockIdx.y * ROWS;
     const int a = blockIdx.z;
@@ -257,8 +263,11 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
             const int u = u0 - C + cc;
             tile[i] = (v >= 0 && v < nv && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
         }
+        if (threadIdx.x < K * KW) {
+            const int i = threadIdx.x / KW, j = threadIdx.x - i * KW;
+            wl[threadIdx.x] = j < K ? ker[(int64_t)g * K * K + (K - 1 - i) * K + (K - 1 - j)] : 0.0f;
+        }
         __syncthreads();
-        const float *kg = ker + g * K * K;
         const float *trow = tile + (4 * wave) * LW + 4 * lane;
 #pragma unroll
         for (int rr = 0; rr < K + 3; ++rr) {
@@ -275,12 +284,23 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
             for (int r = 0; r < 4; ++r) {
                 const int i = rr - r;
                 if (i >= 0 && i < K) {
+                    // the kernel row is read again for every output row: the
+                    // compiler barrier stops it from keeping four rows live,
+                    // which would cost 45 registers and with them occupancy
+                    __asm__ volatile("" ::: "memory");
+                    float w[KW];
 #pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const float w = kg[(K - 1 - i) * K + (K - 1 - j)];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(w, x[c + j], acc[r][c]);
+                    for (int j = 0; j < KW; j += 4) {
+                        const float4 w4 = *reinterpret_cast<const float4 *>(wl + i * KW + j);
+                        w[j] = w4.x;
+                        w[j + 1] = w4.y;
+                        w[j + 2] = w4.z;
+                        w[j + 3] = w4.w;
                     }
+#pragma unroll
+                    for (int j = 0; j < K; ++j)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(w[j], x[c + j], acc[r][c]);
                 }
             }
         }
