@@ -25,12 +25,18 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "FcatError", "MODES", "Geometry", "Phantom", "Spectral", "Scatter", "Psf", "Problem", "upload",
-    "fcat_version", "fcat_status_string", "fcat_last_error", "fcat_project_workspace_bytes",
-    "fcat_project", "fcat_pathlengths_workspace_bytes", "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_psf",
-    "fcat_check_inputs", "fcat_timing_enable", "fcat_timing_read", "STAGES", "lib_path", "load",
-    "Surrogate", "MlpTrain", "fcat_mlp_param_count", "fcat_mlp_workspace_bytes", "fcat_mlp_linear_term",
-    "fcat_mlp_forward", "fcat_mlp_gradients", "fcat_mlp_train_step", "fcat_mlp_train_epoch", "fcat_mlp_validate",
+    "FcatError", "MODES", "STAGES", "Geometry", "Phantom", "Spectral", "Scatter", "Psf", "Problem", "Noise",
+    "Surrogate", "MlpTrain", "lib_path", "load", "upload", "project", "fcat_version", "fcat_status_string",
+    "fcat_last_error", "fcat_project_workspace_bytes", "fcat_project", "fcat_pathlengths_workspace_bytes",
+    "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_psf", "fcat_check_inputs",
+    "fcat_timing_enable", "fcat_timing_read", "fcat_count_scale", "fcat_poisson", "fcat_flood_workspace_bytes",
+    "fcat_flood_profile", "fcat_log_projection", "fcat_projections_workspace_bytes", "fcat_projections",
+    "fcat_dose_workspace_bytes", "fcat_dose", "fcat_fdk_filter", "fcat_fdk_backproject_workspace_bytes",
+    "fcat_fdk_backproject", "fcat_fdk_workspace_bytes", "fcat_fdk", "fcat_effective_psf",
+    "fcat_slit_lsf_range", "fcat_slit_mtf", "fcat_richardson_lucy_workspace_bytes",
+    "fcat_slit_mtf_workspace_bytes", "fcat_richardson_lucy", "fcat_mlp_param_count",
+    "fcat_mlp_workspace_bytes", "fcat_mlp_linear_term", "fcat_mlp_forward", "fcat_mlp_gradients",
+    "fcat_mlp_train_step", "fcat_mlp_train_epoch", "fcat_mlp_validate", "fcat_mlp_setup",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -436,6 +442,35 @@ def fcat_project(pb: Problem, mode: str = "plain", surrogate=None, out=None, wor
                           _stream(stream))
     _check(st)
     return out
+
+
+def project(geometry: Geometry, labels, mu, phi, eta, scatter=None, psf=None, mode: str = "plain", *,
+            voxel=None, centre=(0.0, 0.0, 0.0), group_of_bin=None, flood=None, surrogate=None, stream=None):
+    """Projections [A][nv][nu] of one phantom from plain device tensors (marshalling only).
+
+    labels: a Phantom, or a device int8 tensor [nz][ny][nx] with voxel = (dx, dy, dz)
+    in mm and the volume centre ``centre``; mu [M][E], phi [E], eta [E] device
+    float32; scatter: None, a Scatter or a device float32 [A][nv][nu]; psf:
+    None, a Psf or a device float32 [G][k][k].  The number of energy groups is
+    G of the PSF (the groups of ``group_of_bin``, else an even split of the
+    bins); without a PSF it is the number of groups of ``group_of_bin``, else 1.
+    """
+    if isinstance(labels, Phantom):
+        ph = labels
+    else:
+        if voxel is None:
+            raise ValueError("project: voxel=(dx, dy, dz) is required with a labels tensor")
+        ph = Phantom(labels, *(float(v) for v in voxel), *(float(c) for c in centre))
+    sc = scatter if scatter is None or isinstance(scatter, Scatter) else Scatter(scatter)
+    ps = psf if psf is None or isinstance(psf, Psf) else Psf(psf)
+    if ps is not None:
+        n_groups = int(ps.kernels.shape[0])
+    elif group_of_bin is not None:
+        n_groups = int(np.max(np.asarray(group_of_bin))) + 1
+    else:
+        n_groups = 1
+    sp = Spectral(mu, phi, eta, n_groups, None if group_of_bin is None else np.asarray(group_of_bin, np.int32), flood)
+    return fcat_project(Problem(geometry, ph, sp, sc, ps), mode=mode, surrogate=surrogate, stream=stream)
 
 
 def fcat_pathlengths_workspace_bytes(phantom: Phantom) -> int:

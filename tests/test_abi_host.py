@@ -196,3 +196,10 @@ def test_slit_bin_range_matches_the_oracle():
         d, _ = op.presampled_lsf(np.ones((nr, nc)), p, tilt, over)
         b = np.round(d / (p / over)).astype(np.int64)
         assert b.min() == b_min and b.max() == b_min + n_bins - 1
+
+
+def test_tensor_entry_needs_the_voxel_size():
+    """project() with a bare labels tensor and no voxel size is refused before any device call."""
+    import paper_2011_04736_amd as fcat
+    with pytest.raises(ValueError, match="voxel"):
+        fcat.project(None, object(), None, None, None)

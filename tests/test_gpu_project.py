@@ -158,3 +158,29 @@ def test_check_inputs(fc):
     cfg.spectral.mu[2] = 0.0
     ref = oracle.project(cfg, [0, 10])
     assert rel_err(out[[0, 10]], ref).max() <= 1e-5
+
+
+def test_plain_tensor_entry(fc):
+    """project() from plain device tensors equals fcat_project on the uploaded
+    descriptors, bit for bit, and so the oracle: once bare, once with a flood
+    map, scatter, 3 uneven groups and an optical spread."""
+    cfg = synth.make_config(1)
+    for full in (False, True):
+        if full:
+            rng = np.random.default_rng(2)
+            g, s = cfg.geometry, cfg.spectral
+            s.flood = rng.uniform(0.8, 1.2, size=(g.nv, g.nu)).astype(np.float32)
+            s.n_groups = 3
+            s.group_of_bin = np.array([0] * 6 + [1] * 18 + [2] * 8, np.int32)
+            cfg.scatter = synth.scatter_blobs(rng, g.n_angles, g.nu, g.nv, (30, 60), (4, 8))
+            cfg.psf = synth.Psf(synth.gaussian_psfs(rng, 3, 15))
+        pb = fc.upload(cfg)
+        ref = fc.fcat_project(pb).cpu().numpy()
+        ph, sp = pb.phantom, pb.spectral
+        out = fc.project(pb.geometry, ph.labels, sp.mu, sp.phi, sp.eta,
+                         scatter=None if pb.scatter is None else pb.scatter.maps,
+                         psf=None if pb.psf is None else pb.psf.kernels, voxel=(ph.dx, ph.dy, ph.dz),
+                         centre=(ph.cx, ph.cy, ph.cz), group_of_bin=sp.group_of_bin, flood=sp.flood)
+        out = out.cpu().numpy()
+        np.testing.assert_array_equal(out, ref)
+        _check(out, cfg, [0, 22, 44], label=f"project() {'all terms' if full else 'bare'}")
