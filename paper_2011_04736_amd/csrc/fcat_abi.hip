@@ -1058,6 +1058,13 @@ fcat_status fcat_richardson_lucy(const float *images, int32_t n, int32_t nv, int
         e = launch_psf(c, 1, 1, nv, nu, kt, k, norm, stream);
     }
     for (int it = 0; e == hipSuccess && it < iterations; ++it) {
+        if (k == 15) {
+            // both elementwise steps in the convolutions' epilogues
+            StageTimer tm(FCAT_STAGE_PSF, stream);
+            e = launch_psf_rl(1, out, n, nv, nu, kernel, k, c, images, nullptr, stream);
+            if (e == hipSuccess) e = launch_psf_rl(2, c, n, nv, nu, kt, k, out, nullptr, norm, stream);
+            continue;
+        }
         {
             StageTimer tm(FCAT_STAGE_PSF, stream);
             e = launch_psf(out, n, 1, nv, nu, kernel, k, c, stream);

@@ -166,6 +166,11 @@ hipError_t launch_spectral_split(const float *L, int64_t n, const SpecTables &t,
 
 hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const float *kernels,
                       int k, float *out, hipStream_t stream);
+// A Richardson-Lucy step fused into a one-group convolution (k = 15 only):
+// step 1 writes out = c > 0 ? data / c : 0, step 2 writes out = out c / norm
+// (norm one plane [nv][nu]), where c is the convolution of Y with kernel.
+hipError_t launch_psf_rl(int step, const float *Y, int n_ang, int nv, int nu, const float *kernel, int k,
+                         float *out, const float *data, const float *norm, hipStream_t stream);
 
 // Optical spread of the split form on the matrix cores (BF16 hi/lo, FP32
 // accumulate), for odd k <= kPsfSplitMaxK: B fragments of the banded kernel

@@ -225,10 +225,17 @@ __global__ __launch_bounds__(kBlock) void k_psf(const float *__restrict__ Y, int
 constexpr int kP4Cols = 4 * kWave;              // 256 output columns per tile
 constexpr int kP4Waves = 8;                     // wavefronts per workgroup (4 and 16 measured slower)
 constexpr int kP4Rows = 4 * kP4Waves;           // output rows per tile
+constexpr int kPsfStore = 0, kPsfRatio = 1, kPsfUpdate = 2;
 
-template <int K, int NW>
+// EPI selects what is stored for a convolution value c (Richardson-Lucy
+// steps fused into the convolution):
+//   kPsfStore:  out = c
+//   kPsfRatio:  out = c > 0 ? aux[i] / c : 0        (aux = the data d)
+//   kPsfUpdate: out = out[i] * c / norm[pixel]     (out = the iterate u, in place)
+template <int K, int NW, int EPI>
 __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y, int G, int nv, int nu,
-                                                     const float *__restrict__ ker, float *__restrict__ out)
+                                                     const float *__restrict__ ker, float *out,
+                                                     const float *aux, const float *__restrict__ norm)
 {
     constexpr int C = (K - 1) / 2;
     constexpr int NX = (K + 3 + 3) / 4 * 4;       // inputs read per row, a multiple of 4
@@ -310,7 +317,19 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
     for (int r = 0; r < 4; ++r) {
         const int v = v0 + 4 * wave + r;
         if (v >= nv) continue;
-        float *o = out + (int64_t)a * plane + (int64_t)v * nu + ub;
+        const int64_t pix = (int64_t)v * nu + ub;
+        const int64_t at = (int64_t)a * plane + pix;
+        float *o = out + at;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (ub + c >= nu) break;
+            if (EPI == kPsfRatio) {
+                const float d = aux[at + c];
+                acc[r][c] = acc[r][c] > 0.0f ? d / acc[r][c] : 0.0f;
+            } else if (EPI == kPsfUpdate) {
+                acc[r][c] = o[c] * acc[r][c] / norm[pix + c];
+            }
+        }
         if ((nu & 3) == 0 && ub + 3 < nu) {
             *reinterpret_cast<float4 *>(o) = make_float4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
         } else {
@@ -526,7 +545,8 @@ hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const fl
     constexpr int TVG = (kBlock / kWave) * kGenRows;
     if (k == 15) {
         const dim3 grid((nu + kP4Cols - 1) / kP4Cols, (nv + kP4Rows - 1) / kP4Rows, n_ang);
-        hipLaunchKernelGGL((k_psf4<15, kP4Waves>), grid, dim3(kP4Waves * kWave), 0, stream, Y, G, nv, nu, kernels, out);
+        hipLaunchKernelGGL((k_psf4<15, kP4Waves, kPsfStore>), grid, dim3(kP4Waves * kWave), 0, stream, Y, G, nv, nu,
+                           kernels, out, nullptr, nullptr);
     } else if (k == 5) {
         const dim3 grid((nu + kWave - 1) / kWave, (nv + TV - 1) / TV, n_ang);
         hipLaunchKernelGGL((k_psf<5, ROWS>), grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, out);
@@ -534,6 +554,20 @@ hipError_t launch_psf(const float *Y, int n_ang, int G, int nv, int nu, const fl
         const dim3 grid((nu + kWave - 1) / kWave, (nv + TVG - 1) / TVG, n_ang);
         hipLaunchKernelGGL(k_psf_generic, grid, dim3(kBlock), 0, stream, Y, G, nv, nu, kernels, k, out);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_psf_rl(int step, const float *Y, int n_ang, int nv, int nu, const float *kernel, int k,
+                         float *out, const float *data, const float *norm, hipStream_t stream)
+{
+    if (k != 15 || (step != 1 && step != 2)) return hipErrorInvalidValue;
+    const dim3 grid((nu + kP4Cols - 1) / kP4Cols, (nv + kP4Rows - 1) / kP4Rows, n_ang);
+    if (step == 1)
+        hipLaunchKernelGGL((k_psf4<15, kP4Waves, kPsfRatio>), grid, dim3(kP4Waves * kWave), 0, stream, Y, 1, nv, nu,
+                           kernel, out, data, nullptr);
+    else
+        hipLaunchKernelGGL((k_psf4<15, kP4Waves, kPsfUpdate>), grid, dim3(kP4Waves * kWave), 0, stream, Y, 1, nv, nu,
+                           kernel, out, nullptr, norm);
     return hipGetLastError();
 }
 

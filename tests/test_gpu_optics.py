@@ -55,10 +55,11 @@ def test_slit_mtf_parity(fc, k, sig):
     np.testing.assert_allclose(mtf.cpu().numpy(), op.mtf(d, ref_lsf, f), rtol=0, atol=2e-6)
 
 
-def test_richardson_lucy_tiny_parity(fc):
+@pytest.mark.parametrize("k", [7, 15])
+def test_richardson_lucy_tiny_parity(fc, k):
+    # k = 15 runs the ratio and the update inside the convolutions
     rng = np.random.default_rng(3)
-    k = 7
-    r = np.arange(k) - 3
+    r = np.arange(k) - (k - 1) // 2
     K = np.exp(-0.5 * ((r[:, None] - 0.8) ** 2 / 1.2 ** 2 + (r[None, :] + 0.5) ** 2 / 0.9 ** 2))
     K = (K / K.sum()).astype(np.float32)
     d = rng.uniform(0.2, 3.0, (3, 37, 53)).astype(np.float32)
