@@ -133,18 +133,26 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
         const float fu0 = floorf(uf);
         const float fu = uf - fu0;
         const int i0 = (int)fu0;
-        const float wu0 = (i0 >= 0 && i0 < g.nu) ? 1.0f - fu : 0.0f;
-        const float wu1 = (i0 + 1 >= 0 && i0 + 1 < g.nu) ? fu : 0.0f;
+        const bool cin0 = i0 >= 0 && i0 < g.nu, cin1 = i0 + 1 >= 0 && i0 + 1 < g.nu;
         const int c0 = min(max(i0, 0), g.nu - 1), c1 = min(max(i0 + 1, 0), g.nu - 1);
         const float *__restrict__ p = filt + (int64_t)a * plane;
+        // detector row j interpolated along u at this column (taps outside
+        // the detector count as 0); rows are clamped for the loads only
+        auto row_value = [&](int j) {
+            const int r = min(max(j, 0), g.nv - 1);
+            const float a0 = cin0 ? p[r * g.nu + c0] : 0.0f;
+            const float a1 = cin1 ? p[r * g.nu + c1] : 0.0f;
+            const float val = fmaf(fu, a1 - a0, a0);
+            return (j >= 0 && j < g.nv) ? val : 0.0f;
+        };
         const float zstep = v.dz * mag * g.scale * g.inv_dv;   // detector rows per slice
         const float vf0 = ((v.z0 + (float)iz0 * v.dz) * mag * g.scale - g.off_v) * g.inv_dv + g.cv;
         // The slices of a column meet the detector at increasing rows, often
-        // less than a row apart: the two taps of the current row pair stay
-        // in registers, and a step of one row reuses the lower pair as the
-        // upper one, so only the new row is read.
-        int rt = -(1 << 30);                    // row of the upper pair held
-        float t0 = 0.0f, t1 = 0.0f, b0 = 0.0f, b1 = 0.0f;
+        // less than a row apart: the u-interpolated values of the current
+        // row pair stay in registers, and a step of one row reuses the lower
+        // one as the upper, so only the new row is read and interpolated.
+        int rt = -(1 << 30);                    // row of the upper value held
+        float top = 0.0f, bot = 0.0f;
 #pragma unroll
         for (int q = 0; q < kBpZ; ++q) {
             if (q >= nzl) break;
@@ -152,25 +160,15 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
             const float fv0 = floorf(vf);
             const float fv = vf - fv0;
             const int j0 = (int)fv0;
-            const float wv0 = (j0 >= 0 && j0 < g.nv) ? 1.0f - fv : 0.0f;
-            const float wv1 = (j0 + 1 >= 0 && j0 + 1 < g.nv) ? fv : 0.0f;
             if (j0 != rt) {
-                if (j0 == rt + 1) {
-                    t0 = b0;
-                    t1 = b1;
-                } else {
-                    const int r0 = min(max(j0, 0), g.nv - 1);
-                    t0 = p[r0 * g.nu + c0];
-                    t1 = p[r0 * g.nu + c1];
-                }
-                const int r1 = min(max(j0 + 1, 0), g.nv - 1);
-                b0 = p[r1 * g.nu + c0];
-                b1 = p[r1 * g.nu + c1];
+                if (j0 == rt + 1)
+                    top = bot;
+                else
+                    top = row_value(j0);
+                bot = row_value(j0 + 1);
                 rt = j0;
             }
-            const float s0 = wu0 * t0 + wu1 * t1;
-            const float s1 = wu0 * b0 + wu1 * b1;
-            acc[q] = fmaf(w, wv0 * s0 + wv1 * s1, acc[q]);
+            acc[q] = fmaf(w, fmaf(fv, bot - top, top), acc[q]);
         }
     }
 #pragma unroll
