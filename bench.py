@@ -538,11 +538,14 @@ def add_measured_ceilings(result: dict) -> None:
     if not os.path.exists(exe):
         result["ceilings"] = {"error": "fcat_ceilings not built"}
         return
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
-    if r.returncode != 0:
-        result["ceilings"] = {"error": r.stderr.strip()[-300:]}
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        if r.returncode != 0:
+            raise RuntimeError(r.stderr.strip()[-300:] or f"exit status {r.returncode}")
+        ceil = json.loads(r.stdout.strip().splitlines()[-1])
+    except (OSError, RuntimeError, ValueError, IndexError, subprocess.TimeoutExpired) as e:
+        result["ceilings"] = {"error": str(e)[-300:]}
         return
-    ceil = json.loads(r.stdout.strip().splitlines()[-1])
     result["ceilings"] = ceil
     entries = [result["roofline"], *result["kernels"].values()]
     for group in ("forms", "next"):

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
                 if (i >= 0 && i < K) {
                     // the kernel row is read again for every output row: the
                     // compiler barrier stops it from keeping four rows live,
-                    // which would cost 45 registers and with them occupancy
+                    // which would cost about 36 registers and with them occupancy
                     __asm__ volatile("" ::: "memory");
                     float w[KW];
 #pragma unroll
