@@ -8,10 +8,18 @@ optical-depth range of the cells (``fcat_mlp_setup``), forward/backward/Adam
 the network may replace the exact sum (``fcat_mlp_validate``).  This module
 only draws the seeded samples and initial weights (inputs to those kernels),
 slices tensors, loops over epochs and sets the learning-rate schedule.
+
+Checkpoints: with ``checkpoint=path`` the weights, the Adam moments and step,
+the scales and the loss history are written to ``path`` (NumPy ``.npz``,
+arrays only, replaced atomically) after every epoch; with ``resume=True`` a
+run continues after the last epoch the file holds.  Sampling, the epoch
+orders and the schedule are seeded by epoch, so a resumed run reproduces
+the uninterrupted one.
 """
 from __future__ import annotations
 
 import math
+import os
 import time
 from dataclasses import dataclass, field
 from typing import Optional
@@ -78,10 +86,40 @@ class TrainReport:
     holdout_in_ok_cells: float = 0.0
 
 
+def _save_checkpoint(path: str, epoch: int, train: MlpTrain, sur: Surrogate, report: "TrainReport") -> None:
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, epoch=np.int64(epoch), step=np.int64(train.step), params=train.params.cpu().numpy(),
+             adam_m=train.adam_m.cpu().numpy(), adam_v=train.adam_v.cpu().numpy(),
+             in_scale=sur.in_scale.cpu().numpy(), out_scale=sur.out_scale.cpu().numpy(), lin=sur.lin.cpu().numpy(),
+             cell_hi=np.float64(sur.cell_hi), epoch_loss=np.asarray(report.epoch_loss, np.float64))
+    os.replace(tmp, path)
+
+
+def _load_checkpoint(path: str, train: MlpTrain, sur: Surrogate, report: "TrainReport") -> int:
+    """Restore the state of ``path`` into train / sur / report; returns the next epoch."""
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        for name, dst in (("params", train.params), ("adam_m", train.adam_m), ("adam_v", train.adam_v),
+                          ("in_scale", sur.in_scale), ("out_scale", sur.out_scale), ("lin", sur.lin)):
+            src = z[name]
+            if tuple(src.shape) != tuple(dst.shape):
+                raise ValueError(f"checkpoint {path}: {name} has shape {src.shape}, expected {tuple(dst.shape)}")
+            dst.copy_(torch.as_tensor(src, device=dst.device))
+        train.step = int(z["step"])
+        sur.cell_hi = float(z["cell_hi"])
+        report.epoch_loss = [float(x) for x in z["epoch_loss"]]
+        return int(z["epoch"]) + 1
+
+
 def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.1, epochs: int = 120,
                     batch: int = 4096, lr: float = 2e-3, lr_final: float = 2e-5, threshold: float = 1e-3,
-                    min_count: int = 16, angles=None, seed: int = 47365, verbose: bool = False):
-    """Train the surrogate on rays of ``pb`` and validate it; returns (Surrogate, TrainReport)."""
+                    min_count: int = 16, angles=None, seed: int = 47365, verbose: bool = False,
+                    checkpoint: Optional[str] = None, resume: bool = False, stop_after: Optional[int] = None):
+    """Train the surrogate on rays of ``pb`` and validate it; returns (Surrogate, TrainReport).
+
+    ``checkpoint`` / ``resume``: see the module notes.  ``stop_after`` ends
+    the run after that many epochs of this call (the checkpoint then holds a
+    resumable state); the returned surrogate is validated either way."""
     import torch
     sp = pb.spectral
     M, _E = (int(x) for x in sp.mu.shape)
@@ -107,14 +145,20 @@ def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.
     nb = (n_train + batch - 1) // batch
     batch_loss = torch.empty(nb, dtype=torch.float32, device=dev)
     report = TrainReport(n_train, n_hold, epochs, batch, 0.0)
+    first = 0
+    if checkpoint and resume and os.path.exists(checkpoint):
+        first = _load_checkpoint(checkpoint, train, sur, report)
+    last = epochs if stop_after is None else min(epochs, first + stop_after)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for ep in range(epochs):
+    for ep in range(first, last):
         train.lr = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * ep / max(epochs - 1, 1)))
         g = torch.Generator().manual_seed(seed * 1000 + ep)
         order = torch.randperm(n_train, generator=g).to(torch.int32).to(dev)
         fcat_mlp_train_epoch(train, sur, sp, Lt, Yt, order, batch, batch_loss=batch_loss)
         report.epoch_loss.append(float(batch_loss.mean().item()))
+        if checkpoint:
+            _save_checkpoint(checkpoint, ep, train, sur, report)
         if verbose:
             print(f"epoch {ep}: lr {train.lr:.2e} loss {report.epoch_loss[-1]:.3e}", flush=True)
     torch.cuda.synchronize()

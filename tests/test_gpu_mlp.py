@@ -179,3 +179,22 @@ def test_training_and_surrogate_projector(fc):
     err = rel_err(o, oracle.project(cfg, sample))
     print(f"surrogate projector: max rel err {err.max():.2e}; rays by network {counts[0]}, by exact sum {counts[1]}")
     assert counts[0] > 0 and err.max() <= 1e-3
+
+
+def test_training_resumes_from_a_checkpoint(fc, tmp_path):
+    """Two epochs, a checkpoint, then a resumed call for the other two give
+    the same weights, Adam state and loss history as four epochs in one go."""
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(1)
+    pb = fc.upload(cfg)
+    kw = dict(n_samples=20000, epochs=4, batch=1024, angles=np.arange(0, 45, 3), seed=5)
+    sur_a, rep_a = sg.build_surrogate(pb, **kw)
+    ck = str(tmp_path / "surrogate.npz")
+    _, rep_half = sg.build_surrogate(pb, checkpoint=ck, stop_after=2, **kw)
+    assert len(rep_half.epoch_loss) == 2
+    sur_b, rep_b = sg.build_surrogate(pb, checkpoint=ck, resume=True, **kw)
+    np.testing.assert_array_equal(sur_b.params.cpu().numpy(), sur_a.params.cpu().numpy())
+    assert rep_b.epoch_loss == rep_a.epoch_loss
+    np.testing.assert_array_equal(rep_b.cell_ok, rep_a.cell_ok)
+    with np.load(ck, allow_pickle=False) as z:
+        assert int(z["epoch"]) == 3 and int(z["step"]) > 0
