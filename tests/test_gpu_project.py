@@ -184,3 +184,22 @@ def test_plain_tensor_entry(fc):
         out = out.cpu().numpy()
         np.testing.assert_array_equal(out, ref)
         _check(out, cfg, [0, 22, 44], label=f"project() {'all terms' if full else 'bare'}")
+
+
+def test_bit_identical_repeats_and_chunkings(fc):
+    """Race check by repetition: ten calls on the contrast workload (walk with
+    LDS material sums, LDS-tiled spread) and calls with other angle chunkings
+    give bit-identical projections; so do repeated split-form calls."""
+    import torch
+    cfg = synth.make_config(2)
+    pb = fc.upload(cfg)
+    ref = fc.fcat_project(pb)
+    buf = torch.empty_like(ref)
+    for _ in range(10):
+        fc.fcat_project(pb, out=buf)
+        assert torch.equal(buf, ref)
+    for ch in (7, 90):
+        assert torch.equal(fc.fcat_project(pb, angles_per_chunk=ch), ref)
+    sref = fc.fcat_project(pb, mode="split_bf16")
+    for _ in range(3):
+        assert torch.equal(fc.fcat_project(pb, mode="split_bf16", out=buf), sref)
