@@ -206,9 +206,11 @@ __global__ __launch_bounds__(kBlock) void k_prep_split(const float *__restrict__
 // convolution, zero outside the detector, c = (k - 1) / 2).  For one kernel
 // row p, sixteen consecutive outputs of a detector row depend on 16 + k - 1
 // consecutive inputs, so the row convolution is a 16 x 32 by 32 x 16 matrix
-// product: A[r][j] = Y_g[v0 + r - p + c][u0 - c + j] (16 output rows r),
-// B_{g,p}[j][t] = K_g[p][t + 2c - j] where 0 <= t + 2c - j < k, else 0 (a
-// banded Toeplitz block, built once per call).  Both operands are split into
+// product: A[r][j] = Y_g[v0 + r - p + c][u0 - 8 + j] (16 output rows r; the
+// tile starts 8 columns left of the outputs, so that its global loads are
+// 16-byte aligned), B_{g,p}[j][t] = K_g[p][t + c + 8 - j] where
+// 0 <= t + c + 8 - j < k, else 0 (a banded Toeplitz block, built once per
+// call; for odd k <= 17 the band lies inside the 32 columns).  Both operands are split into
 // BF16 hi/lo parts and each product is formed as A_hi B_hi + A_lo B_hi +
 // A_hi B_lo with FP32 accumulation over p, g and the three terms.  Every
 // term is non-negative, so the relative error of an output is that of a
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_psf_split(const float *__restri
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
         const int j = 8 * q + jj;
-        const int col = t + 2 * c - j;
+        const int col = t + c + 8 - j;
         const float v = (col >= 0 && col < k) ? ker[(int64_t)gp * k + col] : 0.0f;
         const uint32_t hi = bf16_rne(v);
         h[jj] = part ? bf16_rne(v - bf16_value(hi)) : hi;
@@ -258,11 +260,26 @@ __global__ __launch_bounds__(kBlock) void k_psf_split(const float *__restrict__ 
     for (int g = 0; g < G; ++g) {
         const float *Yg = Y + ((int64_t)a * G + g) * plane;
         __syncthreads();
-        // input tile: rows v0 - c .., columns u0 - c .. u0 - c + 79; thread t
-        // fills column pair t % 40 of rows t / 40, t / 40 + 6, ...
-        if (threadIdx.x < 240) {
+        // input tile: rows v0 - c .., columns u0 - 8 .. u0 + 71
+        if ((nu & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0) {
+            // whole 16-byte groups: a group is inside the detector or not at all
+            for (int i = threadIdx.x; i < rows * 20; i += kBlock) {
+                const int rr = i / 20, c4 = i - rr * 20;
+                const int v = v0 - c + rr;
+                const int u = u0 - 8 + 4 * c4;
+                float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (v >= 0 && v < nv && u >= 0 && u < nu)
+                    y = *reinterpret_cast<const float4 *>(Yg + (int64_t)v * nu + u);
+                uint32_t h01, l01, h23, l23;
+                split_bf16x2(y.x, y.y, h01, l01);
+                split_bf16x2(y.z, y.w, h23, l23);
+                *reinterpret_cast<uint2 *>(th + rr * kPsfStride + 4 * c4) = make_uint2(h01, h23);
+                *reinterpret_cast<uint2 *>(tl + rr * kPsfStride + 4 * c4) = make_uint2(l01, l23);
+            }
+        } else if (threadIdx.x < 240) {
+            // thread t fills column pair t % 40 of rows t / 40, t / 40 + 6, ...
             const int col = 2 * (threadIdx.x % 40);
-            const int u = u0 - c + col;
+            const int u = u0 - 8 + col;
             const bool in0 = u >= 0 && u < nu, in1 = u + 1 >= 0 && u + 1 < nu;
             for (int rr = threadIdx.x / 40; rr < rows; rr += 6) {
                 const int v = v0 - c + rr;

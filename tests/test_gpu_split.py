@@ -73,14 +73,15 @@ def test_split_project_head_sampled(fc):
     assert err.max() <= 1e-3
 
 
-@pytest.mark.parametrize("k", [3, 15, 17, 19])
-def test_split_psf_ragged_detector(fc, k):
+@pytest.mark.parametrize("k,nu", [(3, 101), (15, 101), (17, 101), (19, 101), (1, 100), (15, 100), (17, 100)])
+def test_split_psf_ragged_detector(fc, k, nu):
     """The split form's optical spread runs on the matrix cores for k <= 17 (banded
     Toeplitz operands, BF16 hi/lo); k = 19 takes the FP32 kernel.  Ragged detector
-    (101 x 21 pixels: partial 64 x 64 tiles in both directions), 4 groups."""
+    (nu x 21 pixels: partial 64 x 64 tiles in both directions), 4 groups; nu = 100
+    takes the 16-byte tile loads, nu = 101 the 4-byte ones."""
     rng = np.random.default_rng(100 + k)
     cfg = synth.make_config(1)
-    cfg.geometry.nu, cfg.geometry.nv = 101, 21
+    cfg.geometry.nu, cfg.geometry.nv = nu, 21
     cfg.spectral.n_groups = 4
     cfg.spectral.group_of_bin = synth.contiguous_groups(cfg.spectral.n_energy, 4)
     cfg.psf = synth.Psf(synth.gaussian_psfs(rng, 4, k))
