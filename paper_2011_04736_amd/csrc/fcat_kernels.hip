@@ -246,6 +246,7 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
     constexpr int KW = (K + 3) / 4 * 4;           // kernel row stride in LDS (zero-padded)
     static_assert(LW % 4 == 0, "aligned rows");
     static_assert(K * KW <= NT, "one thread per staged weight");
+    static_assert(C <= 8, "the aligned tile loads start at most 8 columns left of the tile");
     __shared__ __align__(16) float tile[LH * LW];
     __shared__ __align__(16) float wl[K * KW];   // wl[i][j] = K_g[K-1-i][K-1-j]
     const int u0 = blockIdx.x * kP4Cols;
@@ -254,6 +255,7 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t plane = (int64_t)nv * nu;
+    const bool vec_loads = (nu & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0;
     float acc[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -263,12 +265,34 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
     for (int g = 0; g < G; ++g) {
         const float *Yg = Y + ((int64_t)a * G + g) * plane;
         __syncthreads();
-        for (int i = threadIdx.x; i < LH * LW; i += NT) {
-            const int rr = i / LW;
-            const int cc = i - rr * LW;
-            const int v = v0 - C + rr;
-            const int u = u0 - C + cc;
-            tile[i] = (v >= 0 && v < nv && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
+        if (vec_loads) {
+            // 16-byte global loads from the aligned columns u0 - 8 + 4m, each
+            // value written to tile column u - (u0 - C); with nu a multiple of 4
+            // a group is inside the detector or not at all
+            constexpr int G4 = (LW + 8 - C + 3) / 4;
+            for (int i = threadIdx.x; i < LH * G4; i += NT) {
+                const int rr = i / G4;
+                const int m = i - rr * G4;
+                const int v = v0 - C + rr;
+                const int u = u0 - 8 + 4 * m;
+                float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (v >= 0 && v < nv && u >= 0 && u < nu)
+                    y = *reinterpret_cast<const float4 *>(Yg + (int64_t)v * nu + u);
+                float *trw = tile + rr * LW;
+                const int cc = 4 * m + C - 8;
+                if (cc >= 0) trw[cc] = y.x;
+                if (cc + 1 >= 0 && cc + 1 < LW) trw[cc + 1] = y.y;
+                if (cc + 2 >= 0 && cc + 2 < LW) trw[cc + 2] = y.z;
+                if (cc + 3 < LW) trw[cc + 3] = y.w;
+            }
+        } else {
+            for (int i = threadIdx.x; i < LH * LW; i += NT) {
+                const int rr = i / LW;
+                const int cc = i - rr * LW;
+                const int v = v0 - C + rr;
+                const int u = u0 - C + cc;
+                tile[i] = (v >= 0 && v < nv && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
+            }
         }
         if (threadIdx.x < K * KW) {
             const int i = threadIdx.x / KW, j = threadIdx.x - i * KW;
