@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
         float top = 0.0f, bot = 0.0f;
 #pragma unroll
         for (int q = 0; q < kBpZ; ++q) {
-            if (q >= nzl) break;
+            if (q >= nzl) continue;             // uniform: the workgroup's slice count
             const float vf = vf0 + (float)q * zstep;
             const float fv0 = floorf(vf);
             const float fv = vf - fv0;
