@@ -36,7 +36,7 @@ PEAK_HBM_GBPS = 8000.0
 
 # Algorithmic work per unit (vector lane-operations).
 OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk
-EXP_SLOTS = 4                 # a transcendental issues at quarter rate
+EXP_SLOTS = 4                 # lane-operations counted for one exp (the hardware exp2 is half rate; expf adds its reduction)
 
 
 def parse():
@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--fdk", type=int, default=1, help="1: time the FDK reconstruction of the projections (0 skips it)")
     ap.add_argument("--rl-iterations", type=int, default=10,
                     help="Richardson-Lucy iterations on the detected profiles (0 skips the optics stage)")
+    ap.add_argument("--spectral", type=int, default=1, help="1: time steps a3-a4 alone on the hit rays' path lengths")
     ap.add_argument("--ceilings", type=int, default=1,
                     help="1: run the device-ceiling microbenchmark and add fractions of the measured ceilings")
     ap.add_argument("--forms", default="split_bf16,surrogate",
@@ -166,6 +167,43 @@ def optics_stage(pb, cfg, args, torch, fc):
         "roofline": {"kernel": "k_psf4<15,8> (one group)", "bound": "alu", "achieved": round(ach, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4),
                      "stage_ms": round(psf_ms, 4), "algorithmic_flops_per_step": flops, "traffic": None},
+    }
+
+
+# v_exp_f32 issues at half the 16-lane rate (measured by the ceiling probe)
+EXP_RATE = 256 * 4 * 16 * 2.4e9 / 2
+
+
+def spectral_stage(pb, cfg, args, torch, fc):
+    """Steps a3-a4 on their own: the exact spectral sum (Eq. 3) over the
+    path lengths of the workload's rays that meet the phantom, timed as
+    k_spectral (E exps and E (M + 1) FMAs per ray)."""
+    s = cfg.spectral
+    M, E = s.n_mat, s.n_energy
+    L = fc.fcat_pathlengths(pb, M).reshape(-1, M)
+    Lh = L[L.sum(dim=1) > 0].contiguous()
+    del L
+    n = int(Lh.shape[0])
+    Y = torch.empty((s.n_groups, n), dtype=torch.float32, device=Lh.device)
+    ws = torch.empty(max(fc.fcat_spectral_workspace_bytes(pb.spectral), 1), dtype=torch.uint8, device=Lh.device)
+    stream = torch.cuda.current_stream()
+    elapsed, stages = timed_steps(lambda: fc.fcat_spectral(Lh, pb.spectral, out=Y, workspace=ws, stream=stream),
+                                  1, args.form_steps, torch)
+    t = stages["trace"][0] / args.form_steps
+    exps = float(n) * E
+    ops = exps * (M + 2 + EXP_SLOTS)
+    ach = ops / (t * 1e-3)
+    del Lh, Y, ws
+    return {
+        "rays": n,
+        "energy_bins": E,
+        "ms": round(t, 4),
+        "exp_per_s": exps / (t * 1e-3),
+        "exp_rate_frac": round(exps / (t * 1e-3) / EXP_RATE, 4),
+        "roofline": {"kernel": "k_spectral", "bound": "alu", "achieved": round(ach / 1e12, 3),
+                     "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Top/s", "frac": round(ach / VALU_LANE_OPS, 4),
+                     "note": "per hit ray and bin M FMAs, the weight FMA, the scale and an exp counted as "
+                             "EXP_SLOTS lane-operations; the exp unit itself is far from busy (exp_rate_frac)"},
     }
 
 
@@ -494,6 +532,7 @@ def main():
         result["forms"]["split_bf16"] = form_split(pb, cfg, out, args, torch, fc)
     del ws, out
     torch.cuda.empty_cache()
+    result["stages"] = {"spectral": spectral_stage(pb, cfg, args, torch, fc)} if args.spectral else {}
     result["next"] = {}
     if args.noise_counts > 0:
         result["next"]["noise_and_projections"] = noise_stage(pb, cfg, args, torch, fc)
@@ -548,7 +587,7 @@ def add_measured_ceilings(result: dict) -> None:
         return
     result["ceilings"] = ceil
     entries = [result["roofline"], *result["kernels"].values()]
-    for group in ("forms", "next"):
+    for group in ("forms", "next", "stages"):
         for v in result.get(group, {}).values():
             for key in ("roofline", "filter"):
                 if isinstance(v, dict) and isinstance(v.get(key), dict):
