@@ -203,3 +203,27 @@ def test_bit_identical_repeats_and_chunkings(fc):
     sref = fc.fcat_project(pb, mode="split_bf16")
     for _ in range(3):
         assert torch.equal(fc.fcat_project(pb, mode="split_bf16", out=buf), sref)
+
+
+def test_thin_slab(fc):
+    """A thin slab (a band of a few detector rows of shadow: the 16 x 4 pixel
+    wavefront tiles) with a flood map, scatter, 3 groups and an optical
+    spread, all angles against the oracle, with and without the spread;
+    ragged angle chunks give the same bits."""
+    rng = np.random.default_rng(7)
+    cfg = synth.make_config(1)
+    ph, g, s = cfg.phantom, cfg.geometry, cfg.spectral
+    ph.labels = ph.labels[6:9].copy()                 # 3 slices of 1 mm: a band of ~4.5 detector rows
+    s.flood = rng.uniform(0.8, 1.2, size=(g.nv, g.nu)).astype(np.float32)
+    s.n_groups = 3
+    s.group_of_bin = np.array([0] * 9 + [1] * 13 + [2] * 10, np.int32)
+    cfg.scatter = synth.scatter_blobs(rng, g.n_angles, g.nu, g.nv, (30, 60), (4, 8))
+    cfg.psf = synth.Psf(synth.gaussian_psfs(rng, 3, 15))
+    pb = fc.upload(cfg)
+    out = fc.fcat_project(pb).cpu().numpy()
+    _check(out, cfg, list(range(45)), label="thin slab")
+    np.testing.assert_array_equal(fc.fcat_project(pb, angles_per_chunk=7).cpu().numpy(), out)
+    cfg.psf = None
+    pb = fc.upload(cfg)
+    out = fc.fcat_project(pb).cpu().numpy()
+    _check(out, cfg, [0, 11, 44], label="thin slab, no spread")
