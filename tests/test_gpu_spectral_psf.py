@@ -95,3 +95,19 @@ def test_psf_asymmetric_kernel_and_delta(fc):
     K1[0, 7, 7] = 1.0
     ident = fc.fcat_psf(t(Y[:, :1].copy()), fc.Psf(t(K1))).cpu().numpy()
     np.testing.assert_array_equal(ident, Y[:, 0])
+
+
+def test_exp_accuracy_over_the_optical_depth_range(fc):
+    """One material, one bin, mu = phi = eta = 1: the spectral sum returns
+    exp(-P) for P = L, so this pins the device exponential against FP64 over
+    the optical depths FP32 can hold as normal numbers (P in [0, 87])."""
+    import torch
+    P = np.linspace(0.0, 87.0, 400001).astype(np.float32)
+    L = torch.as_tensor(P[:, None].copy()).cuda()
+    one = lambda *shape: torch.ones(*shape, dtype=torch.float32, device="cuda")
+    sp = fc.Spectral(mu=one(1, 1), phi=one(1), eta=one(1), n_groups=1)
+    Y = fc.fcat_spectral(L, sp).cpu().numpy()[0].astype(np.float64)
+    ref = np.exp(-P.astype(np.float64))
+    rel = np.abs(Y - ref) / ref
+    print(f"exp(-P), P in [0, 87]: max rel err {rel.max():.2e}")
+    assert rel.max() <= 1e-6
