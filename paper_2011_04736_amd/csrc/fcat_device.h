@@ -383,6 +383,27 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
     acc.read(L);
 }
 
+// exp(-P) for the spectral sum, by Cody and Waite's argument reduction
+// (W. J. Cody, W. Waite, Software Manual for the Elementary Functions, 1980):
+// n = rint(P log2 e), r = P - n ln 2 with ln 2 split in a 16-bit head (n times
+// the head is exact for n < 2^8, all n whose result is above the FP32
+// subnormals) and the FP32 rounding of the rest, then 2^-n exp(-r) with the
+// hardware base-2 exponential of -r log2 e (|r log2 e| <= 1/2 up to rounding)
+// and an exact scaling by 2^-n.  P is a non-negative optical depth; only n
+// is clamped (at 2^21, far beyond underflow): a larger P leaves a large r
+// whose exponential is 0 itself, and a NaN or +inf passes through r
+// unchanged (+inf gives 0).
+__device__ __forceinline__ float exp_neg(float P)
+{
+    constexpr float kLog2e = 1.44269504088896341f;
+    constexpr float kLn2Hi = 0.693145751953125f;        // ln 2 rounded to 16 significant bits
+    constexpr float kLn2Lo = 1.428606765330187e-06f;    // ln 2 - kLn2Hi, rounded
+    const float n = rintf(fminf(P * kLog2e, 2097152.0f));
+    float r = fmaf(-n, kLn2Hi, P);
+    r = fmaf(-n, kLn2Lo, r);
+    return ldexpf(__builtin_amdgcn_exp2f(-r * kLog2e), (int)(-n));
+}
+
 // sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3)
 template <int MP>
 __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTables &T, int e0, int e1)
@@ -393,7 +414,7 @@ __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTable
         float P = 0.0f;
 #pragma unroll
         for (int m = 0; m < MP; ++m) P = fmaf(mrow[m], L[m], P);
-        acc = fmaf(T.w[e], expf(-P), acc);
+        acc = fmaf(T.w[e], exp_neg(P), acc);
     }
     return acc;
 }
