@@ -228,6 +228,10 @@ def fdk_stage(pb, cfg, args, torch, fc):
     bp_ach = bp_ops / (bp_ms * 1e-3) / 1e12
     fl_flops = 2.0 * g.n_angles * g.nv * g.nu * ((g.nu + 1) // 2)
     fl_ach = fl_flops / (fl_ms * 1e-3) / 1e12
+    # the sample quads: each padded plane read once, its quads written once
+    su = max(g.nu, 2)
+    ly_bytes = g.n_angles * (4.0 * (g.nv + 3) * su + 16.0 * (g.nv + 2) * (su - 1))
+    ly_ms = stages["layout"][0] / args.form_steps
     finite = bool(torch.isfinite(vol).all().item())
     del ws, vol, proj
     return {
@@ -246,6 +250,10 @@ def fdk_stage(pb, cfg, args, torch, fc):
                    "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                    "frac": round(fl_ach / PEAK_FP32_VECTOR_TFLOPS, 4), "stage_ms": round(fl_ms, 4),
                    "algorithmic_flops_per_step": fl_flops},
+        "layout": {"kernel": "k_fdk_quads (+ k_fdk_pad)", "bound": "hbm",
+                   "achieved": round(ly_bytes / (ly_ms * 1e-3) / 1e9, 2), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                   "frac": round(ly_bytes / (ly_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 4), "stage_ms": round(ly_ms, 4),
+                   "algorithmic_bytes_per_step": ly_bytes},
     }
 
 

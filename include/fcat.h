@@ -397,7 +397,13 @@ fcat_status fcat_fdk_backproject(const fcat_geometry_t *geometry, const float *f
                                  int32_t a_end, const fcat_grid_t *grid, float *volume, int32_t accumulate,
                                  void *workspace, size_t workspace_bytes, void *stream);
 
-/* Workspace needed by fcat_fdk (angles_per_chunk 0: up to 1 GiB of filtered rows per chunk). */
+/*
+ * Workspace needed by fcat_fdk: the angles' (cos, sin), then for each angle
+ * of a chunk its filtered rows, zero-padded ((nv + 3) x max(nu, 2) floats),
+ * and their 2 x 2 bilinear sample quads ((nv + 2) x (max(nu, 2) - 1)
+ * float4); angles_per_chunk 0: as many angles as fit in 1 GiB.  A smaller
+ * workspace than this makes fcat_fdk take fewer angles per chunk.
+ */
 size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_per_chunk);
 
 /* The whole reconstruction: volume (DEVICE float [nz][ny][nx]) from proj (DEVICE float [n_angles][nv][nu]). */
@@ -550,7 +556,8 @@ typedef enum fcat_stage {
     FCAT_STAGE_FILTER = 7, /* FDK cosine weight and ramp filter */
     FCAT_STAGE_BACKPROJECT = 8, /* FDK back-projection */
     FCAT_STAGE_OPTICS = 9, /* effective PSF, slit MTF, Richardson-Lucy element-wise steps */
-    FCAT_STAGE_COUNT = 10
+    FCAT_STAGE_LAYOUT = 10, /* FDK: zero pads and 2 x 2 sample quads of the filtered rows */
+    FCAT_STAGE_COUNT = 11
 } fcat_stage;
 
 /*

@@ -42,7 +42,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfcat.so")
 MODES = {"plain": 0, "split_bf16": 1, "surrogate": 2}
-STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose", "filter", "backproject", "optics")
+STAGES = ("prep", "trace", "psf", "mlp", "noise", "proj", "dose", "filter", "backproject", "optics", "layout")
 _lib = None
 
 

@@ -812,7 +812,7 @@ fcat_status fcat_fdk_filter(const fcat_geometry_t *geometry, const float *proj, 
     hipError_t e;
     {
         StageTimer tm(FCAT_STAGE_FILTER, static_cast<hipStream_t>(stream));
-        e = launch_fdk_filter(fdk_geom(geometry), proj, n_ang, filtered, static_cast<hipStream_t>(stream));
+        e = launch_fdk_filter(fdk_geom(geometry), proj, n_ang, false, filtered, static_cast<hipStream_t>(stream));
     }
     if (e != hipSuccess) return device_fail(e, "fdk_filter");
     return FCAT_OK;
@@ -823,8 +823,9 @@ size_t fcat_fdk_backproject_workspace_bytes(int32_t n_ang)
     return n_ang < 1 ? 0 : align_up((size_t)n_ang * sizeof(float2));
 }
 
-static fcat_status fdk_backproject(const fcat_geometry_t *geometry, const float *filtered, int a_begin, int a_end,
-                                   const FdkGrid &v, float *volume, int accumulate, float2 *cs, hipStream_t stream)
+static fcat_status fdk_backproject(const fcat_geometry_t *geometry, const float *filtered, const float4 *quads,
+                                   int a_begin, int a_end, const FdkGrid &v, float *volume, int accumulate,
+                                   float2 *cs, hipStream_t stream)
 {
     const int n = a_end - a_begin;
     hipError_t e;
@@ -832,7 +833,7 @@ static fcat_status fdk_backproject(const fcat_geometry_t *geometry, const float 
         StageTimer tm(FCAT_STAGE_BACKPROJECT, stream);
         e = launch_fdk_angles(geometry->angles_rad, geometry->n_angles, a_begin, n, cs, stream);
         if (e == hipSuccess)
-            e = launch_fdk_backproject(fdk_geom(geometry), v, filtered, cs, n,
+            e = launch_fdk_backproject(fdk_geom(geometry), v, filtered, quads, cs, n,
                                        (float)(3.141592653589793 / geometry->n_angles), accumulate, volume, stream);
     }
     if (e != hipSuccess) return device_fail(e, "fdk_backproject");
@@ -853,13 +854,27 @@ fcat_status fcat_fdk_backproject(const fcat_geometry_t *geometry, const float *f
     if ((s = check_workspace(workspace, workspace_bytes, fcat_fdk_backproject_workspace_bytes(a_end - a_begin))))
         return s;
     if ((s = check_pending())) return s;
-    return fdk_backproject(geometry, filtered, a_begin, a_end, v, volume, accumulate ? 1 : 0,
+    return fdk_backproject(geometry, filtered, nullptr, a_begin, a_end, v, volume, accumulate ? 1 : 0,
                            static_cast<float2 *>(workspace), static_cast<hipStream_t>(stream));
+}
+
+// bytes of one angle's filtered rows in fcat_fdk: the padded plane and its quads
+static size_t fdk_padded_bytes(const fcat_geometry_t *g)
+{
+    return (size_t)fdk_padded_plane(g->nu, g->nv) * sizeof(float);
+}
+static size_t fdk_quad_bytes(const fcat_geometry_t *g)
+{
+    return (size_t)fdk_quad_plane(g->nu, g->nv) * sizeof(float4);
+}
+static size_t fdk_chunk_bytes(const fcat_geometry_t *g, size_t c)
+{
+    return align_up(c * fdk_padded_bytes(g)) + align_up(c * fdk_quad_bytes(g));
 }
 
 static size_t fdk_chunk(const fcat_geometry_t *g, int32_t angles_per_chunk)
 {
-    const size_t per = (size_t)g->nu * g->nv * sizeof(float);
+    const size_t per = fdk_padded_bytes(g) + fdk_quad_bytes(g);
     size_t c = angles_per_chunk > 0 ? (size_t)angles_per_chunk : kDefaultChunkBytes / per;
     return std::max<size_t>(1, std::min<size_t>(c, (size_t)g->n_angles));
 }
@@ -868,8 +883,7 @@ size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_
 {
     if (check_geometry(geometry)) return 0;
     const size_t c = fdk_chunk(geometry, angles_per_chunk);
-    return align_up((size_t)geometry->n_angles * sizeof(float2)) +
-           align_up(c * geometry->nu * geometry->nv * sizeof(float));
+    return align_up((size_t)geometry->n_angles * sizeof(float2)) + fdk_chunk_bytes(geometry, c);
 }
 
 fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,
@@ -881,25 +895,42 @@ fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const f
     if ((s = check_geometry(geometry)) || (s = check_grid(grid, v))) return s;
     if (geometry->nu > kFdkMaxNu) return fail(FCAT_E_UNSUPPORTED, "FDK filter takes nu <= %d", kFdkMaxNu);
     if (!proj || !volume) return fail(FCAT_E_INVALID_ARG, "proj and volume must not be NULL");
-    const size_t per = (size_t)geometry->nu * geometry->nv * sizeof(float);
     const size_t cs_bytes = align_up((size_t)geometry->n_angles * sizeof(float2));
-    if ((s = check_workspace(workspace, workspace_bytes, cs_bytes + align_up(per)))) return s;
+    if ((s = check_workspace(workspace, workspace_bytes, cs_bytes + fdk_chunk_bytes(geometry, 1)))) return s;
     if ((s = check_pending())) return s;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     float2 *cs = static_cast<float2 *>(workspace);
     float *filt = at<float>(workspace, cs_bytes);
     const int A = geometry->n_angles;
-    const int chunk = (int)std::min<size_t>((size_t)A, (workspace_bytes - cs_bytes) / per);
+    // the most angles whose padded planes and quads fit
+    const size_t room = workspace_bytes - cs_bytes;
+    size_t c = std::min<size_t>((size_t)A, room / (fdk_padded_bytes(geometry) + fdk_quad_bytes(geometry)));
+    c = std::max<size_t>(c, 1);
+    while (c > 1 && fdk_chunk_bytes(geometry, c) > room) --c;
+    const int chunk = (int)c;
+    float4 *quads = at<float4>(workspace, cs_bytes + align_up(c * fdk_padded_bytes(geometry)));
     const FdkGeom g = fdk_geom(geometry);
+    // the filter writes only the rows of the detector: the zero pads of the
+    // chunk buffer are written once and stay
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_LAYOUT, stream);
+        e = launch_fdk_pad(g, chunk, filt, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "fdk_pad");
     for (int a0 = 0; a0 < A; a0 += chunk) {
         const int n = std::min(chunk, A - a0);
-        hipError_t e;
         {
             StageTimer tm(FCAT_STAGE_FILTER, stream);
-            e = launch_fdk_filter(g, proj + (int64_t)a0 * geometry->nu * geometry->nv, n, filt, stream);
+            e = launch_fdk_filter(g, proj + (int64_t)a0 * geometry->nu * geometry->nv, n, true, filt, stream);
         }
         if (e != hipSuccess) return device_fail(e, "fdk_filter");
-        if ((s = fdk_backproject(geometry, filt, a0, a0 + n, v, volume, a0 > 0, cs, stream))) return s;
+        {
+            StageTimer tm(FCAT_STAGE_LAYOUT, stream);
+            e = launch_fdk_quads(g, n, filt, quads, stream);
+        }
+        if (e != hipSuccess) return device_fail(e, "fdk_quads");
+        if ((s = fdk_backproject(geometry, nullptr, quads, a0, a0 + n, v, volume, a0 > 0, cs, stream))) return s;
     }
     return FCAT_OK;
 }

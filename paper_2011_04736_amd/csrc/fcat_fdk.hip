@@ -19,8 +19,10 @@ constexpr int kRampOut = 8;   // outputs per lane in the ramp filter
 
 // Work of one lane: outputs i0 .. i0 + kRampOut - 1 of half s (0: even
 // samples, 1: odd samples) of row r of the workgroup.
+// Output row (a, iv) starts at filt + a plane_out + (iv + row_off) su.
 __global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *__restrict__ proj, int n_rows,
-                                                       int rows_per_block, float *__restrict__ filt)
+                                                       int rows_per_block, int64_t plane_out, int row_off, int su,
+                                                       float *__restrict__ filt)
 {
     extern __shared__ float lds[];
     const int nq = (g.nu + 1) / 2;                   // samples per half (the odd half zero-padded)
@@ -80,11 +82,12 @@ __global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *_
             win[0] = tab[j + (j >> 3)];
         }
         const int row = row0 + r;
+        float *__restrict__ orow = filt + (int64_t)(row / g.nv) * plane_out + (int64_t)(row % g.nv + row_off) * su;
 #pragma unroll
         for (int q = 0; q < kRampOut; ++q) {
             const int i = i0 + q;
             const int iu = 2 * i + s;
-            if (i < nq && iu < g.nu) filt[(int64_t)row * g.nu + iu] = fmaf(h0, self[i], acc[q]);
+            if (i < nq && iu < g.nu) orow[iu] = fmaf(h0, self[i], acc[q]);
         }
     }
 }
@@ -102,15 +105,18 @@ __global__ void k_fdk_angles(const double *__restrict__ angles, int n_angles, in
 constexpr int kBpZ = 16;       // slices a lane accumulates per pass
 constexpr int kBpTileX = 64;   // workgroup tile: 64 x 4 columns (x fastest, one wavefront per row)
 
-// Voxel-driven back-projection: a lane owns one (x, y) column and zc <= kBpZ
+// Voxel-driven back-projection of filtered rows in the dense layout
+// [n][nv][nu] (the caller's own rows): a lane owns one (x, y) column and zc <= kBpZ
 // slices starting at blockIdx.z zc (the slices split evenly over gridDim.z),
 // and loops over the angles.  The taps are read from global memory: the
 // window of the detector a workgroup touches per angle is small and stays in
 // the caches (staging it in LDS, one angle ahead with a barrier per angle,
 // measured twice as slow on the 10-slice contrast grid).
-__global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v, const float *__restrict__ filt,
-                                                            const float2 *__restrict__ cs, int n, int zc,
-                                                            float weight, int accumulate, float *__restrict__ volume)
+__global__ void __launch_bounds__(kBlock) k_fdk_backproject_dense(FdkGeom g, FdkGrid v,
+                                                                  const float *__restrict__ filt,
+                                                                  const float2 *__restrict__ cs, int n, int zc,
+                                                                  float weight, int accumulate,
+                                                                  float *__restrict__ volume)
 {
     const int ix = blockIdx.x * kBpTileX + (int)(threadIdx.x % kBpTileX);
     const int iy = blockIdx.y * (kBlock / kBpTileX) + (int)(threadIdx.x / kBpTileX);
@@ -181,10 +187,132 @@ __global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v
     }
 }
 
+
+// Zero the pad rows (detector rows -1, nv, nv + 1) and pad columns (nu ..
+// su - 1) of n planes in the padded layout.
+__global__ void k_fdk_pad(float *__restrict__ filt, int n, int nu, int nv, int su)
+{
+    const int64_t per = 3 * (int64_t)su + (int64_t)nv * (su - nu);   // pad words per plane
+    const int64_t plane = (int64_t)(nv + 3) * su;
+    const int64_t total = per * n;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < total; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t a = k / per;
+        int64_t r = k - a * per;
+        int64_t idx;
+        if (r < 3 * (int64_t)su) {
+            const int which = (int)(r / su);                 // 0: row -1, 1: row nv, 2: row nv + 1
+            const int c = (int)(r - (int64_t)which * su);
+            idx = (int64_t)(which == 0 ? 0 : nv + which) * su + c;
+        } else {
+            r -= 3 * (int64_t)su;                            // only when su > nu
+            const int w = su - nu;
+            const int j = (int)(r / w);
+            idx = (int64_t)(j + 1) * su + nu + (int)(r - (int64_t)j * w);
+        }
+        filt[a * plane + idx] = 0.0f;
+    }
+}
+
+// Quads of the padded rows: lane per (plane, row j in [0, nv + 1], column c in
+// [0, su - 2]), reading the padded plane coalesced and writing one float4.
+__global__ void k_fdk_quads(const float *__restrict__ filt, int n, int nv, int su, float4 *__restrict__ quads)
+{
+    const int qc = su - 1;
+    const int64_t per = (int64_t)(nv + 2) * qc;
+    const int64_t plane = (int64_t)(nv + 3) * su;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < per * n; k += (int64_t)gridDim.x * kBlock) {
+        const int64_t a = k / per;
+        const int64_t r = k - a * per;
+        const int j = (int)(r / qc), c = (int)(r - (int64_t)j * qc);
+        const float *__restrict__ f = filt + a * plane + (int64_t)j * su + c;
+        quads[k] = make_float4(f[0], f[1], f[su], f[su + 1]);
+    }
+}
+
+// The back-projection of the whole reconstruction, from quads of the padded
+// filtered rows.  A lane owns one (x, y) column and Z slices (Z = zc, the
+// workgroup's share of the z extent; the last z block may own fewer, nzl:
+// its extra slices read in-bounds quads and are not stored), with no branch
+// and no bounds test per slice:
+//  * the two columns of a sample are c0 and c0 + 1 with c0 clamped to
+//    [0, su - 2]; their weights are the bilinear tent weights
+//    max(0, 1 - |u - c|), so a tap off the detector gets weight 0 (or reads
+//    a zero pad column);
+//  * the row coordinate, counted in padded rows (detector row + 1), is
+//    clamped to [0, nv + 1] (a NaN gives offset 0): a sample off the
+//    detector then reads the zero pad rows, the value of a tap outside it.
+// Per slice: the row and its fraction, one 24-bit address, one aligned
+// 16-byte load and seven FMAs/adds; the per-angle terms are shared by the
+// column's slices.  (On the 10-slice contrast grid the same branch-free loop
+// reading the two rows as two 8-byte loads at 4-byte alignment measured
+// 1.2x slower than the dense kernel, bound by its vector memory requests,
+// and the dense kernel's reuse of rows between slices on the padded rows
+// only 2% faster, held up by its load-to-use waits inside the branches.)
+template <int Z>
+__global__ void __launch_bounds__(kBlock) k_fdk_backproject(FdkGeom g, FdkGrid v, const float4 *__restrict__ quads,
+                                                            const float2 *__restrict__ cs, int n, float weight,
+                                                            int accumulate, float *__restrict__ volume)
+{
+    const int ix = blockIdx.x * kBpTileX + (int)(threadIdx.x % kBpTileX);
+    const int iy = blockIdx.y * (kBlock / kBpTileX) + (int)(threadIdx.x / kBpTileX);
+    const int iz0 = blockIdx.z * Z;
+    const int nzl = min(Z, v.nz - iz0);          // slices of this workgroup that exist
+    if (ix >= v.nx || iy >= v.ny) return;
+    const float x = v.x0 + (float)ix * v.dx;
+    const float y = v.y0 + (float)iy * v.dy;
+    float acc[Z];
+#pragma unroll
+    for (int q = 0; q < Z; ++q) acc[q] = 0.0f;
+    const int su = fdk_padded_cols(g.nu);
+    const int64_t plane = fdk_quad_plane(g.nu, g.nv);
+    const uint32_t row_bytes = (uint32_t)(su - 1) * sizeof(float4);   // < 2^24
+    const float vmax = (float)(g.nv + 1);
+    for (int a = 0; a < n; ++a) {
+        const float2 c = cs[a];
+        const float s = x * c.x + y * c.y;
+        const float t = y * c.x - x * c.y;
+        const float mag = g.D * __builtin_amdgcn_rcpf(g.D - s);   // D / U (1 ulp reciprocal)
+        const float w = mag * mag;                                  // D^2 / U^2
+        const float uf = (t * mag * g.scale - g.off_u) * g.inv_du + g.cu;
+        const int c0 = min(max((int)floorf(uf), 0), su - 2);
+        const float d = uf - (float)c0;
+        const float w0 = fmaxf(1.0f - fabsf(d), 0.0f);
+        const float w1 = fmaxf(1.0f - fabsf(d - 1.0f), 0.0f);
+        const char *__restrict__ pa = reinterpret_cast<const char *>(quads + (int64_t)a * plane);
+        const uint32_t cb = (uint32_t)c0 * sizeof(float4);
+        const float zstep = v.dz * mag * g.scale * g.inv_dv;   // detector rows per slice
+        // padded row coordinate (detector row + 1) of the first slice
+        const float vf0 = ((v.z0 + (float)iz0 * v.dz) * mag * g.scale - g.off_v) * g.inv_dv + (g.cv + 1.0f);
+#pragma unroll
+        for (int q = 0; q < Z; ++q) {
+            const float vf = __builtin_amdgcn_fmed3f(vf0 + (float)q * zstep, 0.0f, vmax);
+            const float fl = floorf(vf);
+            const float fv = vf - fl;
+            // quad (row fl, column c0), fl in [0, nv + 1] (0 for a NaN)
+            const float4 p = *reinterpret_cast<const float4 *>(
+                pa + ((uint32_t)__umul24((uint32_t)(int)fl, row_bytes) + cb));
+            const float top = fmaf(w1, p.y, w0 * p.x);
+            const float bot = fmaf(w1, p.w, w0 * p.z);
+            acc[q] = fmaf(w, fmaf(fv, bot - top, top), acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Z; ++q) {
+        const int iz = iz0 + q;
+        if (q < nzl) {
+            float *o = volume + ((int64_t)iz * v.ny + iy) * v.nx + ix;
+            *o = (accumulate ? *o : 0.0f) + weight * acc[q];
+        }
+    }
+}
+
 }  // namespace
 
-hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, float *filt, hipStream_t stream)
+hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, bool padded, float *filt,
+                             hipStream_t stream)
 {
+    const int su = padded ? fdk_padded_cols(g.nu) : g.nu;
+    const int64_t plane_out = padded ? fdk_padded_plane(g.nu, g.nv) : (int64_t)g.nu * g.nv;
     const int nq = (g.nu + 1) / 2;
     const int ngrp = (nq + kRampOut - 1) / kRampOut;
     const int rows = n_ang * g.nv;
@@ -194,7 +322,8 @@ hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, flo
     const size_t lds = (size_t)(ntab + ntab / 8 + 1 + rpb * 2 * nq) * sizeof(float);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     const int nblk = (rows + rpb - 1) / rpb;
-    hipLaunchKernelGGL(k_fdk_filter, dim3(nblk), dim3(kBlock), lds, stream, g, proj, rows, rpb, filt);
+    hipLaunchKernelGGL(k_fdk_filter, dim3(nblk), dim3(kBlock), lds, stream, g, proj, rows, rpb, plane_out,
+                       padded ? 1 : 0, su, filt);
     return hipGetLastError();
 }
 
@@ -205,16 +334,51 @@ hipError_t launch_fdk_angles(const double *angles, int n_angles, int a0, int n, 
     return hipGetLastError();
 }
 
-hipError_t launch_fdk_backproject(const FdkGeom &g, const FdkGrid &v, const float *filt, const float2 *cs, int n,
-                                  float weight, int accumulate, float *volume, hipStream_t stream)
+hipError_t launch_fdk_pad(const FdkGeom &g, int n_ang, float *filt, hipStream_t stream)
+{
+    const int su = fdk_padded_cols(g.nu);
+    const int64_t total = (3 * (int64_t)su + (int64_t)g.nv * (su - g.nu)) * n_ang;
+    if (total == 0) return hipSuccess;
+    const int64_t nblk = std::min<int64_t>((total + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_fdk_pad, dim3((unsigned)nblk), dim3(kBlock), 0, stream, filt, n_ang, g.nu, g.nv, su);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdk_quads(const FdkGeom &g, int n_ang, const float *filt, float4 *quads, hipStream_t stream)
+{
+    const int su = fdk_padded_cols(g.nu);
+    const int64_t total = fdk_quad_plane(g.nu, g.nv) * n_ang;
+    if (total == 0) return hipSuccess;
+    const int64_t nblk = std::min<int64_t>((total + kBlock - 1) / kBlock, 16384);
+    hipLaunchKernelGGL(k_fdk_quads, dim3((unsigned)nblk), dim3(kBlock), 0, stream, filt, n_ang, g.nv, su, quads);
+    return hipGetLastError();
+}
+
+hipError_t launch_fdk_backproject(const FdkGeom &g, const FdkGrid &v, const float *filt, const float4 *quads,
+                                  const float2 *cs, int n, float weight, int accumulate, float *volume,
+                                  hipStream_t stream)
 {
     const int nzb = (v.nz + kBpZ - 1) / kBpZ;        // passes over z
     const int zc = (v.nz + nzb - 1) / nzb;            // slices per pass, even split
     const dim3 grid((v.nx + kBpTileX - 1) / kBpTileX, (v.ny + kBlock / kBpTileX - 1) / (kBlock / kBpTileX),
                     (v.nz + zc - 1) / zc);
     if (grid.y > 65535 || grid.z > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fdk_backproject, grid, dim3(kBlock), 0, stream, g, v, filt, cs, n, zc, weight, accumulate,
-                       volume);
+    if (!filt) {
+#define FCAT_BP_CASE(Z)                                                                                      \
+    case Z:                                                                                                  \
+        hipLaunchKernelGGL(k_fdk_backproject<Z>, grid, dim3(kBlock), 0, stream, g, v, quads, cs, n, weight,  \
+                           accumulate, volume);                                                              \
+        break;
+        switch (zc) {
+            FCAT_BP_CASE(1) FCAT_BP_CASE(2) FCAT_BP_CASE(3) FCAT_BP_CASE(4) FCAT_BP_CASE(5) FCAT_BP_CASE(6)
+            FCAT_BP_CASE(7) FCAT_BP_CASE(8) FCAT_BP_CASE(9) FCAT_BP_CASE(10) FCAT_BP_CASE(11) FCAT_BP_CASE(12)
+            FCAT_BP_CASE(13) FCAT_BP_CASE(14) FCAT_BP_CASE(15) FCAT_BP_CASE(16)
+        default: return hipErrorInvalidValue;
+        }
+#undef FCAT_BP_CASE
+    } else
+        hipLaunchKernelGGL(k_fdk_backproject_dense, grid, dim3(kBlock), 0, stream, g, v, filt, cs, n, zc, weight,
+                           accumulate, volume);
     return hipGetLastError();
 }
 

@@ -22,9 +22,33 @@ struct FdkGrid {
     int nx, ny, nz;
 };
 
-// Cosine-weighted, ramp-filtered rows of n_ang projections (proj and filt
-// [n_ang][nv][nu], filt may not alias proj).
-hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, float *filt, hipStream_t stream);
+// Padded layout of filtered rows, used inside the whole reconstruction: per
+// angle nv + 3 rows of fdk_padded_cols(nu) floats, detector row j at row
+// j + 1; the rows of detector rows -1, nv, nv + 1 and the columns past nu
+// hold zeros.
+__host__ __device__ inline int fdk_padded_cols(int nu) { return nu < 2 ? 2 : nu; }
+__host__ __device__ inline int64_t fdk_padded_plane(int nu, int nv) { return (int64_t)(nv + 3) * fdk_padded_cols(nu); }
+
+// Cosine-weighted, ramp-filtered rows of n_ang projections (proj
+// [n_ang][nv][nu]; filt dense [n_ang][nv][nu] or, if padded, n_ang padded
+// planes whose pads it leaves alone; filt may not alias proj).
+hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, bool padded, float *filt,
+                             hipStream_t stream);
+
+// Zero the pads of n_ang padded planes.
+hipError_t launch_fdk_pad(const FdkGeom &g, int n_ang, float *filt, hipStream_t stream);
+
+// Quad layout of the padded rows, read by the back-projection: per angle
+// nv + 2 rows of fdk_padded_cols(nu) - 1 float4, quad (j, c) = the padded
+// values (j, c), (j, c + 1), (j + 1, c), (j + 1, c + 1): every bilinear
+// sample is one aligned 16-byte load.
+__host__ __device__ inline int64_t fdk_quad_plane(int nu, int nv)
+{
+    return (int64_t)(nv + 2) * (fdk_padded_cols(nu) - 1);
+}
+
+// quads (16-byte aligned) of n_ang padded planes (their pads zero).
+hipError_t launch_fdk_quads(const FdkGeom &g, int n_ang, const float *filt, float4 *quads, hipStream_t stream);
 
 // (cos b, sin b) of angles a0 .. a0 + n - 1 into cs (2 n floats): from the
 // device array angles, or 2 pi a / n_angles when angles is null.
@@ -32,7 +56,9 @@ hipError_t launch_fdk_angles(const double *angles, int n_angles, int a0, int n, 
 
 // volume (+)= (pi / n_angles) sum over the n angles of cs of D^2 / U^2 times
 // the bilinear sample of filt at the voxel's detector position.
-hipError_t launch_fdk_backproject(const FdkGeom &g, const FdkGrid &v, const float *filt, const float2 *cs, int n,
-                                  float weight, int accumulate, float *volume, hipStream_t stream);
+// From dense filtered rows (filt) or, if filt is null, from quads.
+hipError_t launch_fdk_backproject(const FdkGeom &g, const FdkGrid &v, const float *filt, const float4 *quads,
+                                  const float2 *cs, int n, float weight, int accumulate, float *volume,
+                                  hipStream_t stream);
 
 }  // namespace fcat
