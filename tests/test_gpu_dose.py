@@ -66,6 +66,30 @@ def test_dose_contrast_full(fc):
     assert err.max() <= 1e-5 and abs(float(Dp) / refp - 1) <= 1e-5
 
 
+@pytest.mark.parametrize("n_bins", [1, 37, 300])
+def test_dose_bin_counts(fc, n_bins):
+    """Bin counts that do not fill the workgroups (1, an odd 37, 300), whose
+    work is split in stripes of rays; all angles of the tiny case."""
+    rng = np.random.default_rng(65 + n_bins)
+    cfg = synth.make_config(1)
+    s = cfg.spectral
+    idx = np.arange(n_bins) % s.mu.shape[1]
+    s.energies = np.asarray(s.energies)[idx].copy()
+    s.mu = s.mu[:, idx].copy()
+    s.phi = s.phi[idx].copy()
+    s.eta = s.eta[idx].copy()
+    s.n_groups = 1
+    s.group_of_bin = np.zeros(n_bins, np.int32)
+    energy, ratio, mass = _dose_inputs(cfg, rng)
+    pb = fc.upload(cfg, scatter=False, psf=False)
+    D0, Dp = fc.fcat_dose(pb, _dev(energy), _dev(ratio), mass)
+    D0 = D0.cpu().numpy()
+    ref0, refp = _oracle_dose(cfg, list(range(cfg.geometry.n_angles)), energy, ratio, mass)
+    err = np.abs(D0 / ref0 - 1)
+    print(f"{n_bins} bins: max rel err per bin {err.max():.2e}, Dp {abs(float(Dp) / refp - 1):.2e}")
+    assert err.max() <= 1e-5 and abs(float(Dp) / refp - 1) <= 1e-5
+
+
 def test_dose_all_rays_miss(fc):
     # detector shifted far off the phantom: every ray misses, the dose is exactly 0
     rng = np.random.default_rng(63)
