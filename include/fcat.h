@@ -406,7 +406,11 @@ fcat_status fcat_fdk_backproject(const fcat_geometry_t *geometry, const float *f
  */
 size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_per_chunk);
 
-/* The whole reconstruction: volume (DEVICE float [nz][ny][nx]) from proj (DEVICE float [n_angles][nv][nu]). */
+/*
+ * The whole reconstruction: volume (DEVICE float [nz][ny][nx]) from proj
+ * (DEVICE float [n_angles][nv][nu]).  nu <= 8192 and
+ * (nv + 2) (max(nu, 2) - 1) < 2^28, else FCAT_E_UNSUPPORTED.
+ */
 fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,
                      void *workspace, size_t workspace_bytes, void *stream);
 

@@ -895,6 +895,9 @@ fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const f
     if ((s = check_geometry(geometry)) || (s = check_grid(grid, v))) return s;
     if (geometry->nu > kFdkMaxNu) return fail(FCAT_E_UNSUPPORTED, "FDK filter takes nu <= %d", kFdkMaxNu);
     if (!proj || !volume) return fail(FCAT_E_INVALID_ARG, "proj and volume must not be NULL");
+    // the back-projection addresses an angle's quads with 32-bit offsets
+    if (fdk_quad_bytes(geometry) >= ((size_t)1 << 32))
+        return fail(FCAT_E_UNSUPPORTED, "FDK takes detectors with (nv + 2) (max(nu, 2) - 1) < 2^28");
     const size_t cs_bytes = align_up((size_t)geometry->n_angles * sizeof(float2));
     if ((s = check_workspace(workspace, workspace_bytes, cs_bytes + fdk_chunk_bytes(geometry, 1)))) return s;
     if ((s = check_pending())) return s;

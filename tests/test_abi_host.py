@@ -174,6 +174,17 @@ def test_noise_dose_fdk_optics_reject_bad_args(fc):
     assert lib.fcat_fdk_backproject_workspace_bytes(360) == 3072 and lib.fcat_fdk_backproject_workspace_bytes(0) == 0  # 256-byte aligned
     big = fc._CGeometry(1000.0, 1500.0, 9000, 4, 1.0, 1.0, 0.0, 0.0, 3, None)
     assert lib.fcat_fdk_filter(C.byref(big), 0x1000, 3, 0x8000000, None) == 6   # unsupported width
+    tall = fc._CGeometry(1000.0, 1500.0, 8192, 40000, 1.0, 1.0, 0.0, 0.0, 3, None)
+    assert lib.fcat_fdk(C.byref(tall), 0x1000, C.byref(grid), 0x2000, W, 1 << 26, None) == 6   # quad plane >= 4 GiB
+    # workspace of fcat_fdk: (cos, sin) of the angles, then per angle of a
+    # chunk the zero-padded rows and their 2 x 2 sample quads
+    for nu, nv, A, chunk in ((1024, 64, 360, 0), (1, 5, 24, 5), (33, 9, 24, 0)):
+        g = fc._CGeometry(1000.0, 1500.0, nu, nv, 1.0, 1.0, 0.0, 0.0, A, None)
+        su = max(nu, 2)
+        c = chunk if chunk else A
+        up = lambda x: (x + 255) // 256 * 256
+        want = up(8 * A) + up(c * 4 * (nv + 3) * su) + up(c * 16 * (nv + 2) * (su - 1))
+        assert lib.fcat_fdk_workspace_bytes(C.byref(g), chunk) == want
     # optics
     assert lib.fcat_effective_psf(C.byref(sp), None, 0x1000, None) == 1
     b, n = C.c_int32(), C.c_int32()
