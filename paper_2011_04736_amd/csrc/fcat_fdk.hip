@@ -71,8 +71,27 @@ __global__ void __launch_bounds__(kBlock) k_fdk_filter(FdkGeom g, const float *_
             win[q] = tab[base + q + ((base + q) >> 3)];
             acc[q] = 0.0f;
         }
-#pragma unroll 8
-        for (int l = 0; l < nq; ++l) {
+        // After input l the window takes G at j = base - 1 - l, stored at
+        // j + j / 8.  With base - 1 = 8 hb + rho, input l = 8 t + u reads
+        // 9 (hb - t) + rho - u - (u > rho): per block of 8 inputs a base
+        // that steps by 9, and per input one subtraction of a lane constant.
+        const int hb = (base - 1) >> 3, rho = (base - 1) & 7;
+        int dlt[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dlt[u] = u + (u > rho ? 1 : 0);
+        int l = 0;
+        for (int pb = 9 * hb + rho; l + 8 <= nq; l += 8, pb -= 9) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float xv = other[l + u];
+#pragma unroll
+                for (int q = 0; q < kRampOut; ++q) acc[q] = fmaf(win[q], xv, acc[q]);
+#pragma unroll
+                for (int q = kRampOut - 1; q > 0; --q) win[q] = win[q - 1];
+                win[0] = tab[pb - dlt[u]];
+            }
+        }
+        for (; l < nq; ++l) {
             const float xv = other[l];
 #pragma unroll
             for (int q = 0; q < kRampOut; ++q) acc[q] = fmaf(win[q], xv, acc[q]);
