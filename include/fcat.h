@@ -69,7 +69,7 @@ typedef enum fcat_status {
     FCAT_E_LABEL_RANGE = 3,  /* fcat_check_inputs: a label is outside 0..n_mat-1 */
     FCAT_E_NONFINITE = 4,    /* fcat_check_inputs: NaN or Inf in a float table */
     FCAT_E_DEVICE = 5,       /* a HIP runtime error (text in fcat_last_error) */
-    FCAT_E_UNSUPPORTED = 6   /* a valid request this build does not implement */
+    FCAT_E_UNSUPPORTED = 6   /* a valid request this library does not implement */
 } fcat_status;
 
 typedef enum fcat_mode {
