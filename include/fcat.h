@@ -391,7 +391,12 @@ size_t fcat_fdk_backproject_workspace_bytes(int32_t n_ang);
 /*
  * Back-projection of filtered projections of angles a_begin .. a_end - 1
  * (DEVICE float [a_end - a_begin][nv][nu]) into volume (DEVICE float
- * [nz][ny][nx]): volume = (accumulate ? volume : 0) + (pi / n_angles) sum_a ...
+ * [nz][ny][nx]): volume = (accumulate ? volume : 0) + (pi / n_angles) sum_a
+ * (SID / U)^2 times the bilinear sample of the filtered rows at the voxel's
+ * detector position (Sec. II.G; taps off the detector count as 0).  It
+ * reads the caller's rows as they are; fcat_fdk, which lays its own filtered
+ * rows out as zero-padded 2 x 2 sample quads, back-projects about 1.4x
+ * faster.
  */
 fcat_status fcat_fdk_backproject(const fcat_geometry_t *geometry, const float *filtered, int32_t a_begin,
                                  int32_t a_end, const fcat_grid_t *grid, float *volume, int32_t accumulate,
