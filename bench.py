@@ -136,7 +136,7 @@ def profiled_traffic(kernel: str, digest: str):
 
 def optics_stage(pb, cfg, args, torch, fc):
     """Effective PSF and its presampled MTF from a 0.3 mm slit tilted by 2.5
-    degrees (Sec. II.D), then Richardson-Lucy deconvolution of the workload's
+    degrees (Sec. II.B), then Richardson-Lucy deconvolution of the workload's
     360 detected profiles with it (two 15 x 15 convolutions per iteration)."""
     g = cfg.geometry
     out = fc.fcat_project(pb)

@@ -421,7 +421,7 @@ fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const f
 
 /* ---------------------------------------------------------- detector optics */
 /*
- * Sec. II.D: the energy-dependent optical spread kernels, weighted by the
+ * Sec. II.B: the energy-dependent optical spread kernels, weighted by the
  * detector's energy deposition efficiency times the spectrum, give the
  * effective PSF; convolved with an idealised slit tilted by a small angle it
  * gives a line spread function, presampled to estimate the detector MTF.

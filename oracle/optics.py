@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU
 baseline of the benchmark may use it; the product library never does.
 
-Sec. II.D: the energy-dependent optical spread functions, weighted by the
+Sec. II.B: the energy-dependent optical spread functions, weighted by the
 detector's energy deposition efficiency times the incident spectrum, give a
 hypothetical PSF; convolved with an idealised 0.3 mm slit tilted by 2.5
 degrees it gives a line spread function, presampled to estimate the MTF.

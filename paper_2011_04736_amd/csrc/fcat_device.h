@@ -3,9 +3,11 @@
 // spectral group sum.
 //
 // One lane follows one ray (one detector pixel of one angle); one wavefront
-// covers 64 consecutive detector columns of one row, so its rays are
-// neighbours in space (they share voxel cache lines), have nearly equal
-// lengths (little divergence) and write their results with coalesced stores.
+// covers a compact tile of detector pixels of one angle (8 x 8, or 16 x 4
+// where the phantom covers few detector rows), so its rays are neighbours in
+// space: they cross the same bricks at nearly the same steps (little
+// divergence), share voxel cache lines and write their results as short
+// coalesced row segments.
 //
 // Ray traversal (Sec. II.F: a projection is the line integral of the
 // attenuation along the ray; Sec. II.C: the phantom holds material labels,
@@ -299,8 +301,8 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                 run = T_in;
             }
         } else {
-            // fine walk over [T_in, T_out) inside brick `blin`, whose 512
-            // labels are contiguous in the brick-major copy: resume the
+            // fine walk over [T_in, T_out) inside brick `blin`, whose
+            // kBrickVox labels are contiguous in the brick-major copy: resume the
             // voxel counters at T_in, then step plane by plane
             // The voxel is kept inside the brick: where rounding of the two
             // levels disagrees about a plane at T_in, the brick decides.

@@ -1,4 +1,4 @@
-// Detector optics (Sec. II.D, Sec. IV.B): the spectrum-weighted effective
+// Detector optics (Sec. II.B, Sec. IV.B): the spectrum-weighted effective
 // PSF, the presampled MTF of a tilted slit, and Richardson-Lucy
 // deconvolution (Richardson 1972; Lucy 1974) with the PSF.  The slit and LSF
 // arithmetic runs in FP64 with no fused multiply-adds, so that the bin a

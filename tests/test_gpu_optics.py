@@ -1,4 +1,4 @@
-"""GPU parity of the detector-optics stage (Sec. II.D, Sec. IV.B) with the oracle.
+"""GPU parity of the detector-optics stage (Sec. II.B, Sec. IV.B) with the oracle.
 
 * Effective PSF: FP64 sums, one float rounding: 1e-6 relative.
 * Slit MTF: bin counts are integer work (exact); the LSF comes from the

@@ -162,6 +162,48 @@ def test_mean_attenuation_and_setup_stats():
     np.testing.assert_allclose(o_s, np.sqrt((wt * r * r).sum(0) / wt.sum(0)), rtol=1e-12)
 
 
+def test_setup_stats_hand_example():
+    """Set-up statistics on a hand-worked three-ray example whose group
+    signals have closed forms, exercising each floor and the masking.
+
+    Two materials, five bins with phi = eta = 1 (so w_e = 1), groups
+    {0, 1}, {2, 3}, {4}.  Material 0 has mu = (1, 3, 0, 1, 0.7); material 1
+    never meets a ray (its max L is 0, below the 1e-6 mm floor).  For a ray
+    with L = (l, 0):
+      Y0 = e^-l + e^-3l,  W0 = 2, lin0 = 2    => r0 = ln 2 - l - ln(1 + e^-2l)
+      Y1 = 1 + e^-l,      W1 = 2, lin1 = 1/2  => r1 = ln 2 - ln(1 + e^-l) - l/2
+      Y2 = e^-0.7l,       W2 = 1, lin2 = 0.7  => r2 = 0 (one bin), so the RMS
+                                                  of group 2 takes the 1e-3 floor.
+    At l = 800 group 0 underflows to 0 (absorbed: weight 0, its infinite
+    residual must not reach the statistics); at l = 8 group 0 carries a third
+    of the 0.1% share floor, so its weight is (Y0 / (1e-3 sum Y))^2 ~ 0.112.
+    The mean attenuation is (1 + 3 + 0 + 1 + 0.7) / 5 = 1.14 for material 0,
+    so the top of the optical-depth range is 1.14 * 800.
+    """
+    mu = np.array([[1.0, 3.0, 0.0, 1.0, 0.7], [0.3, 0.3, 0.3, 0.3, 0.3]])
+    phi = eta = np.ones(5)
+    grp = np.array([0, 0, 1, 1, 2])
+    W = mlp.group_weights(phi, eta, grp, 3)
+    lin = mlp.linear_term(mu, phi, eta, grp, 3)
+    l = np.array([1.0, 8.0, 800.0])
+    L = np.stack([l, np.zeros(3)], axis=1)
+    Y = np.stack([np.exp(-l) + np.exp(-3 * l), 1 + np.exp(-l), np.exp(-0.7 * l)])
+    assert Y[0, 2] == 0.0                                    # the absorbed group
+    i_s, o_s, tmax = mlp.setup_stats(L, Y, W, lin)
+
+    assert np.all(np.isfinite(i_s)) and np.all(np.isfinite(o_s))
+    np.testing.assert_allclose(i_s, [1 / 800, 1e6], rtol=1e-14)
+    assert tmax == pytest.approx(1.14 * 800, rel=1e-14)
+    r0 = [math.log(2) - x - math.log1p(math.exp(-2 * x)) for x in l]
+    r1 = [math.log(2) - math.log1p(math.exp(-x)) - x / 2 for x in l]
+    share = Y[0, 1] / (1e-3 * Y[:, 1].sum())                 # ~0.334 at l = 8
+    w0 = [1.0, share ** 2, 0.0]
+    assert 0.1 < w0[1] < 0.12
+    rms0 = math.sqrt(sum(w * r * r for w, r in zip(w0, r0)) / sum(w0))
+    rms1 = math.sqrt(sum(r * r for r in r1) / 3)
+    np.testing.assert_allclose(o_s, [rms0, rms1, 1e-3], rtol=1e-12)
+
+
 def test_validation_errors():
     Y = np.array([[1.0, 2.0], [1e-6, 1.0]])          # [G][n]
     P = Y.copy()

@@ -1,5 +1,5 @@
 """Pins of the detector-optics oracle (oracle/optics.py): effective PSF,
-tilted-slit presampled MTF (Sec. II.D) and Richardson-Lucy deconvolution
+tilted-slit presampled MTF (Sec. II.B) and Richardson-Lucy deconvolution
 (Sec. IV.B; Richardson 1972, Lucy 1974).
 
 Expected values: brute-force supersampling of the slit's pixel coverage;
