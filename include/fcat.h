@@ -42,7 +42,11 @@
  *    fcat_last_error() then gives a description.  Device-side failures of
  *    earlier work surface as FCAT_E_DEVICE from a later call.
  *  - Labels outside 0..n_mat-1 are never used as an index: such voxels add
- *    no path length to any material.  fcat_check_inputs reports them.
+ *    no path length to any material.  Non-finite inputs are used as given
+ *    (a NaN in mu makes the output of every ray that meets the phantom NaN,
+ *    since the contraction multiplies it by each path length, zero or not).  fcat_project and fcat_projections note both while they read
+ *    their inputs, without synchronising; fcat_project_status reports what
+ *    the last such call found.  fcat_check_inputs checks them up front.
  */
 #ifndef FCAT_H
 #define FCAT_H
@@ -66,8 +70,8 @@ typedef enum fcat_status {
     FCAT_OK = 0,
     FCAT_E_INVALID_ARG = 1,  /* null pointer, bad size, SDD <= SID, even k, bad group map ... */
     FCAT_E_WORKSPACE = 2,    /* workspace missing, misaligned or too small */
-    FCAT_E_LABEL_RANGE = 3,  /* fcat_check_inputs: a label is outside 0..n_mat-1 */
-    FCAT_E_NONFINITE = 4,    /* fcat_check_inputs: NaN or Inf in a float table */
+    FCAT_E_LABEL_RANGE = 3,  /* a label is outside 0..n_mat-1 (fcat_project_status, fcat_check_inputs) */
+    FCAT_E_NONFINITE = 4,    /* NaN or Inf in a float input (fcat_project_status, fcat_check_inputs) */
     FCAT_E_DEVICE = 5,       /* a HIP runtime error (text in fcat_last_error) */
     FCAT_E_UNSUPPORTED = 6   /* a valid request this library does not implement */
 } fcat_status;
@@ -86,7 +90,8 @@ typedef struct fcat_geometry_t {
     double du_mm, dv_mm;      /* pixel pitch, > 0 */
     double off_u_mm, off_v_mm;/* detector shift along u and v */
     int32_t n_angles;         /* >= 1 */
-    const double *angles_rad; /* DEVICE [n_angles] radians, or NULL for 2 pi a / n_angles */
+    const double *angles_rad; /* DEVICE [n_angles] radians, or NULL for 2 pi a / n_angles (device
+                                 memory so that every lane reads its angle where it builds its ray) */
 } fcat_geometry_t;
 
 /* Labelled voxel phantom (Sec. II.C). */
@@ -107,7 +112,9 @@ typedef struct fcat_spectral_t {
     const float *eta;         /* DEVICE [n_energy] energy deposition efficiency */
     const float *flood;       /* DEVICE [nv][nu] flood intensity I0, or NULL for 1 */
     const int32_t *group_of_bin; /* HOST [n_energy], non-decreasing, each group non-empty,
-                                    or NULL for floor(e * n_groups / n_energy) */
+                                    or NULL for floor(e * n_groups / n_energy); host memory
+                                    because it is validated and turned into group bounds on the
+                                    host before anything is launched */
 } fcat_spectral_t;
 
 /* Pre-tabulated scatter (Sec. II.E), added to the primary profiles. */
@@ -198,6 +205,22 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
                          const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
                          const fcat_psf_t *psf, fcat_mode mode, const fcat_surrogate_t *surrogate,
                          float *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Input problems found by the last fcat_project or fcat_projections call that
+ * used `workspace` (the same pointer, on the same stream): labels outside
+ * 0..n_mat-1 (FCAT_E_LABEL_RANGE, checked first: Sec. II.C numbers the
+ * materials 0..n-1) and non-finite values in mu, phi, eta, s_bin, flood, the
+ * scatter maps or the spread kernels (FCAT_E_NONFINITE).  The projector call
+ * itself returns as soon as its work is enqueued, so it cannot know; its
+ * kernels set two flags at the start of the workspace as they read each
+ * input (the labels when the brick map is built, the tables when they are
+ * prepared, flood and scatter where each ray reads them), after clearing
+ * them at the start of the call.  This call waits for the stream
+ * (hipStreamSynchronize) and reads the flags; it launches nothing and
+ * changes nothing.  Returns FCAT_OK when none is set.
+ */
+fcat_status fcat_project_status(const void *workspace, size_t workspace_bytes, void *stream);
 
 /* Workspace needed by fcat_pathlengths (the brick map of the labels). */
 size_t fcat_pathlengths_workspace_bytes(const fcat_phantom_t *phantom);
@@ -380,7 +403,8 @@ typedef struct fcat_grid_t {
 /*
  * Cosine weight and ramp filter: filtered (DEVICE float [n_ang][nv][nu]) from
  * proj (DEVICE float [n_ang][nv][nu]); the two must not overlap.
- * nu <= 8192.
+ * nu <= 7704 (a row and the filter taps are held in 64 KiB of LDS), else
+ * FCAT_E_UNSUPPORTED.
  */
 fcat_status fcat_fdk_filter(const fcat_geometry_t *geometry, const float *proj, int32_t n_ang, float *filtered,
                             void *stream);
@@ -413,7 +437,7 @@ size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_
 
 /*
  * The whole reconstruction: volume (DEVICE float [nz][ny][nx]) from proj
- * (DEVICE float [n_angles][nv][nu]).  nu <= 8192 and
+ * (DEVICE float [n_angles][nv][nu]).  nu <= 7704 and
  * (nv + 2) (max(nu, 2) - 1) < 2^28, else FCAT_E_UNSUPPORTED.
  */
 fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,

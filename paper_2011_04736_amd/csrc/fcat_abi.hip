@@ -310,14 +310,14 @@ template <typename T>
 T *at(void *base, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(base) + off); }
 
 fcat_status prep_tables(const fcat_spectral_t *s, const float *s_bin, SpecTables &t, const Layout &L,
-                        void *ws, hipStream_t stream)
+                        void *ws, hipStream_t stream, const InputCheck &chk = InputCheck())
 {
     float *muT = at<float>(ws, L.muT), *w = at<float>(ws, L.w);
     float *Wg = at<float>(ws, L.Wg), *Wsg = at<float>(ws, L.Wsg);
     hipError_t e;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
-        e = launch_prep_tables(s->mu, s->phi, s->eta, s_bin, t, muT, w, Wg, Wsg, stream);
+        e = launch_prep_tables(s->mu, s->phi, s->eta, s_bin, t, muT, w, Wg, Wsg, stream, chk);
     }
     if (e != hipSuccess) return device_fail(e, "prep_tables");
     t.muT = muT;
@@ -531,7 +531,19 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     if ((s = check_pending())) return s;
     hipStream_t stream = static_cast<hipStream_t>(stream_);
 
-    if ((s = prep_tables(spectral, scatter ? scatter->s_bin : nullptr, t, L, workspace, stream))) return s;
+    // input problems found on the way (see fcat_project_status): cleared here,
+    // set by the kernels that read each input anyway
+    int *bad = at<int>(workspace, L.flags);
+    {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        hipError_t e0 = launch_zero_ints(bad, kInputFlags, stream);
+        if (e0 != hipSuccess) return device_fail(e0, "clear input flags");
+    }
+    InputCheck chk;
+    chk.bad = bad;
+    chk.psf = psf ? psf->kernels : nullptr;
+    chk.n_psf = psf ? t.G * psf->k * psf->k : 0;
+    if ((s = prep_tables(spectral, scatter ? scatter->s_bin : nullptr, t, L, workspace, stream, chk))) return s;
     if (split && (s = prep_split(spectral, t, sp, L, workspace, stream))) return s;
     uint4 *pfrag = at<uint4>(workspace, L.pfrag);
     if (pk) {
@@ -544,11 +556,12 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     TraceGeom G = make_geom(geometry, phantom);
     G.bricks = at<int8_t>(workspace, L.bricks);
     G.labels_bm = G.bricks + align_up(brick_count(phantom));
+    G.bad = bad;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
         hipError_t e0 = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz,
                                             const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm),
-                                            stream);
+                                            stream, t.M, bad);
         if (e0 != hipSuccess) return device_fail(e0, "build_bricks");
     }
     const float *S = scatter ? scatter->maps : nullptr;
@@ -617,6 +630,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
             io.out = grouped ? nullptr : outc;
             io.counts = surrogate->counts;
             io.force_mlp = 0;
+            io.bad = bad;
             {
                 StageTimer tm(FCAT_STAGE_MLP, stream);
                 e = launch_mlp_spectral(t, mt, io, stream);
@@ -646,6 +660,21 @@ fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *
     g_last_error.clear();
     return project_impl(geometry, phantom, spectral, scatter, psf, mode, surrogate, false, nullptr, out, workspace,
                         workspace_bytes, stream);
+}
+
+fcat_status fcat_project_status(const void *workspace, size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    fcat_status s;
+    if ((s = check_workspace(const_cast<void *>(workspace), workspace_bytes, kAlign))) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    int host[kInputFlags] = {0, 0};
+    hipError_t e = hipMemcpyAsync(host, workspace, sizeof host, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_fail(e, "input flags readback");
+    if (host[0]) return fail(FCAT_E_LABEL_RANGE, "a phantom label is outside 0..n_mat-1 (those voxels added no path length)");
+    if (host[1]) return fail(FCAT_E_NONFINITE, "mu, phi, eta, s_bin, flood, scatter or a spread kernel holds NaN or Inf");
+    return FCAT_OK;
 }
 
 fcat_status fcat_projections(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
@@ -794,7 +823,8 @@ static fcat_status check_grid(const fcat_grid_t *v, FdkGrid &out)
     return FCAT_OK;
 }
 
-constexpr int kFdkMaxNu = 8192;
+// Widest detector row the ramp filter's workgroup holds in LDS: 7704 columns.
+static bool fdk_nu_supported(int nu) { return fdk_filter_lds_bytes(nu) <= kFdkFilterMaxLds; }
 
 fcat_status fcat_fdk_filter(const fcat_geometry_t *geometry, const float *proj, int32_t n_ang, float *filtered,
                             void *stream)
@@ -802,7 +832,8 @@ fcat_status fcat_fdk_filter(const fcat_geometry_t *geometry, const float *proj, 
     g_last_error.clear();
     fcat_status s;
     if ((s = check_geometry(geometry))) return s;
-    if (geometry->nu > kFdkMaxNu) return fail(FCAT_E_UNSUPPORTED, "FDK filter takes nu <= %d", kFdkMaxNu);
+    if (!fdk_nu_supported(geometry->nu))
+        return fail(FCAT_E_UNSUPPORTED, "the FDK filter takes nu <= 7704 (its rows are held in 64 KiB of LDS)");
     if (n_ang < 1) return fail(FCAT_E_INVALID_ARG, "n_ang must be >= 1");
     if (!proj || !filtered) return fail(FCAT_E_INVALID_ARG, "proj and filtered must not be NULL");
     const size_t bytes = (size_t)n_ang * geometry->nv * geometry->nu * sizeof(float);
@@ -893,7 +924,8 @@ fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const f
     fcat_status s;
     FdkGrid v{};
     if ((s = check_geometry(geometry)) || (s = check_grid(grid, v))) return s;
-    if (geometry->nu > kFdkMaxNu) return fail(FCAT_E_UNSUPPORTED, "FDK filter takes nu <= %d", kFdkMaxNu);
+    if (!fdk_nu_supported(geometry->nu))
+        return fail(FCAT_E_UNSUPPORTED, "the FDK filter takes nu <= 7704 (its rows are held in 64 KiB of LDS)");
     if (!proj || !volume) return fail(FCAT_E_INVALID_ARG, "proj and volume must not be NULL");
     // the back-projection addresses an angle's quads with 32-bit offsets
     if (fdk_quad_bytes(geometry) >= ((size_t)1 << 32))

@@ -421,6 +421,13 @@ __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTable
     return acc;
 }
 
+// Reports a non-finite flood or scatter value read for this ray
+// (bad[1] |= 1).  Only the error case pays for the atomic.
+__device__ __forceinline__ void flag_nonfinite(int *bad, float i0, float sc)
+{
+    if (bad && !(isfinite(i0) && isfinite(sc))) atomicOr(bad + 1, 1);
+}
+
 __device__ __forceinline__ double angle_of(const TraceGeom &G, int a)
 {
     return G.angles ? G.angles[a] : (2.0 * M_PI) * (double)a / (double)G.n_angles;

@@ -15,7 +15,6 @@
 namespace fcat {
 namespace {
 
-constexpr int kRampOut = 8;   // outputs per lane in the ramp filter
 
 // Work of one lane: outputs i0 .. i0 + kRampOut - 1 of half s (0: even
 // samples, 1: odd samples) of row r of the workgroup.
@@ -332,14 +331,10 @@ hipError_t launch_fdk_filter(const FdkGeom &g, const float *proj, int n_ang, boo
 {
     const int su = padded ? fdk_padded_cols(g.nu) : g.nu;
     const int64_t plane_out = padded ? fdk_padded_plane(g.nu, g.nv) : (int64_t)g.nu * g.nv;
-    const int nq = (g.nu + 1) / 2;
-    const int ngrp = (nq + kRampOut - 1) / kRampOut;
     const int rows = n_ang * g.nv;
-    int rpb = kBlock / (2 * ngrp);
-    if (rpb < 1) rpb = 1;
-    const int ntab = 2 * nq + kRampOut + 1;
-    const size_t lds = (size_t)(ntab + ntab / 8 + 1 + rpb * 2 * nq) * sizeof(float);
-    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const int rpb = fdk_filter_rows_per_block(g.nu);
+    const size_t lds = fdk_filter_lds_bytes(g.nu);
+    if (lds > kFdkFilterMaxLds) return hipErrorInvalidValue;
     const int nblk = (rows + rpb - 1) / rpb;
     hipLaunchKernelGGL(k_fdk_filter, dim3(nblk), dim3(kBlock), lds, stream, g, proj, rows, rpb, plane_out,
                        padded ? 1 : 0, su, filt);

@@ -38,6 +38,21 @@ struct TraceGeom {
     // wavefront close in space, so they cross the same bricks at nearly the
     // same steps (far less divergence than 64 pixels of one row).
     int tile_log2u;
+    // Input problems found while reading the inputs, or null: bad[0] |= 1 for
+    // a label outside 0..n_mat-1, bad[1] |= 1 for a non-finite table value.
+    int *bad;
+};
+
+// Input-problem flags at the start of a projector workspace: [0] label out
+// of range, [1] non-finite table value.
+constexpr int kInputFlags = 2;
+
+// Where the preparation kernels report input problems (see TraceGeom::bad):
+// psf kernels (n_psf floats) are checked beside the spectral tables.
+struct InputCheck {
+    const float *psf = nullptr;
+    int n_psf = 0;
+    int *bad = nullptr;
 };
 
 // Tile shape for a geometry: 8 x 8 pixels, or 16 x 4 where the phantom
@@ -108,6 +123,7 @@ struct SurrogateIO {
     float *out;                    // [n] (sum over groups) or null
     int *counts;                   // [2]: rays by the network, rays by the exact sum; or null
     int force_mlp;                 // 1: no fallback (validation and training checks)
+    int *bad;                      // bad[1] |= 1 for a non-finite flood or scatter value; or null
 };
 
 int mlp_param_count(int n_in, int n_out);
@@ -133,7 +149,7 @@ hipError_t launch_mlp_cells(const unsigned *err_bits, const int *count, int ncel
 // hipError_t of the launch.
 hipError_t launch_prep_tables(const float *mu, const float *phi, const float *eta,
                               const float *s_bin, const SpecTables &t, float *muT, float *w,
-                              float *Wg, float *Wsg, hipStream_t stream);
+                              float *Wg, float *Wsg, hipStream_t stream, const InputCheck &chk = InputCheck());
 
 // Fused traversal + spectral sum for angles [a0, a0 + n_ang).  When Y is
 // non-null the group signals go to Y[a - a0][g][v][u]; otherwise
@@ -154,7 +170,7 @@ hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, c
 
 // Brick map and brick-major label copy (see TraceGeom::bricks).
 hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int8_t *bricks, int8_t *labels_bm,
-                               hipStream_t stream);
+                               hipStream_t stream, int n_mat = 0, int *bad = nullptr);
 
 hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0,
                               int n_ang, float *L, hipStream_t stream);

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
     const int64_t pix = (int64_t)iv * G.nu + iu;
     const float i0 = flood ? flood[pix] : 1.0f;
     const float sc = scatter ? scatter[(int64_t)a * plane + pix] : 0.0f;
+    flag_nonfinite(G.bad, i0, sc);
     float total = 0.0f;
     for (int g = 0; g < T.G; ++g) {
         const float acc = any_hit ? group_sum<MP>(L, T, T.gstart[g], T.gstart[g + 1]) : T.Wg[g];
@@ -104,11 +105,25 @@ __global__ __launch_bounds__(kBlock) void k_prep_tables(const float *__restrict_
                                                         const float *__restrict__ eta,
                                                         const float *__restrict__ s_bin, SpecTables T,
                                                         float *__restrict__ muT, float *__restrict__ w,
-                                                        float *__restrict__ Wg, float *__restrict__ Wsg)
+                                                        float *__restrict__ Wg, float *__restrict__ Wsg,
+                                                        const float *__restrict__ psf_k, int n_psf, int *bad)
 {
+    // The tables are read here once per call, so this is where their
+    // finiteness is checked (bad[1] |= 1), together with the spread kernels.
+    bool nonfinite = false;
     for (int e = threadIdx.x; e < T.E; e += kBlock) {
-        w[e] = phi[e] * eta[e];
-        for (int m = 0; m < T.mp; ++m) muT[e * T.mp + m] = m < T.M ? mu[(int64_t)m * T.E + e] : 0.0f;
+        const float p = phi[e], q = eta[e];
+        w[e] = p * q;
+        nonfinite = nonfinite || !isfinite(p) || !isfinite(q) || (s_bin && !isfinite(s_bin[e]));
+        for (int m = 0; m < T.mp; ++m) {
+            const float v = m < T.M ? mu[(int64_t)m * T.E + e] : 0.0f;
+            nonfinite = nonfinite || !isfinite(v);
+            muT[e * T.mp + m] = v;
+        }
+    }
+    if (bad) {
+        for (int i = threadIdx.x; i < n_psf; i += kBlock) nonfinite = nonfinite || !isfinite(psf_k[i]);
+        if (__syncthreads_or(nonfinite) && threadIdx.x == 0) atomicOr(bad + 1, 1);
     }
     const int g = threadIdx.x;
     if (g < T.G) {
@@ -422,25 +437,24 @@ __global__ __launch_bounds__(kBlock) void k_psf_generic(const float *__restrict_
 // the threads copy the brick's labels (positions past the grid edge get the
 // nearest voxel inside it) into labels_bm[brick][z][y][x], and the brick is
 // uniform when every voxel inside the grid carries the same non-negative
-// label.  bricks[b] holds that label, or -1.
+// label.  bricks[b] holds that label, or -1.  Every label is read here once
+// per call, so with bad non-null a label outside 0..n_mat-1 sets bad[0].
 constexpr int kBuildThreads = kBrickVox < 512 ? kBrickVox : 512;
 
 __global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__restrict__ labels, int nx, int ny,
                                                                 int nz, int nbx, int nby,
                                                                 int8_t *__restrict__ bricks,
-                                                                int8_t *__restrict__ labels_bm)
+                                                                int8_t *__restrict__ labels_bm, int n_mat, int *bad)
 {
     const int b = blockIdx.x;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     __shared__ int first;
-    __shared__ int mixed;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         first = labels[((int64_t)(bz * kBrickEdge) * ny + by * kBrickEdge) * nx + bx * kBrickEdge];
-        mixed = first < 0;
-    }
     __syncthreads();
     const int f = first;
-    bool diff = false;
+    bool diff = f < 0;
+    bool out_of_range = false;
     for (int i = threadIdx.x; i < kBrickVox; i += kBuildThreads) {
         const int lx = i & (kBrickEdge - 1);
         const int ly = (i / kBrickEdge) & (kBrickEdge - 1);
@@ -450,9 +464,10 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__
         const int v = labels[((int64_t)min(z, nz - 1) * ny + min(y, ny - 1)) * nx + min(x, nx - 1)];
         labels_bm[(int64_t)b * kBrickVox + i] = (int8_t)v;
         diff = diff || (in && v != f);
+        out_of_range = out_of_range || (in && (v < 0 || v >= n_mat));
     }
-    if (diff) mixed = 1;
-    __syncthreads();
+    const bool mixed = __syncthreads_or(diff);
+    if (bad && __syncthreads_or(out_of_range) && threadIdx.x == 0) atomicOr(bad, 1);
     if (threadIdx.x == 0) bricks[b] = mixed ? (int8_t)-1 : (int8_t)f;
 }
 
@@ -468,10 +483,10 @@ int padded_blocks(int64_t waves)
 
 hipError_t launch_prep_tables(const float *mu, const float *phi, const float *eta, const float *s_bin,
                               const SpecTables &t, float *muT, float *w, float *Wg, float *Wsg,
-                              hipStream_t stream)
+                              hipStream_t stream, const InputCheck &chk)
 {
     hipLaunchKernelGGL(k_prep_tables, dim3(1), dim3(kBlock), 0, stream, mu, phi, eta, s_bin, t, muT, w,
-                       Wg, Wsg);
+                       Wg, Wsg, chk.psf, chk.n_psf, chk.bad);
     return hipGetLastError();
 }
 
@@ -505,12 +520,12 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
 }
 
 hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int8_t *bricks, int8_t *labels_bm,
-                               hipStream_t stream)
+                               hipStream_t stream, int n_mat, int *bad)
 {
     const int nbx = (nx + kBrickEdge - 1) / kBrickEdge, nby = (ny + kBrickEdge - 1) / kBrickEdge;
     const int nbz = (nz + kBrickEdge - 1) / kBrickEdge;
     hipLaunchKernelGGL(k_build_bricks, dim3(nbx * nby * nbz), dim3(kBuildThreads), 0, stream, labels, nx, ny, nz, nbx,
-                       nby, bricks, labels_bm);
+                       nby, bricks, labels_bm, n_mat, bad);
     return hipGetLastError();
 }
 

@@ -29,6 +29,26 @@ struct FdkGrid {
 __host__ __device__ inline int fdk_padded_cols(int nu) { return nu < 2 ? 2 : nu; }
 __host__ __device__ inline int64_t fdk_padded_plane(int nu, int nv) { return (int64_t)(nv + 3) * fdk_padded_cols(nu); }
 
+// Ramp filter: outputs per lane, and the dynamic LDS one workgroup needs
+// for rows of nu columns (the tap table, padded one word in eight, and the
+// even/odd halves of the rows it filters).  Both the host check of nu and
+// the launch use this one formula.
+constexpr int kRampOut = 8;
+constexpr size_t kFdkFilterMaxLds = 64 * 1024;
+__host__ __device__ inline int fdk_filter_rows_per_block(int nu)
+{
+    const int nq = (nu + 1) / 2;
+    const int ngrp = (nq + kRampOut - 1) / kRampOut;
+    const int rpb = 256 / (2 * ngrp);
+    return rpb < 1 ? 1 : rpb;
+}
+__host__ __device__ inline size_t fdk_filter_lds_bytes(int nu)
+{
+    const int nq = (nu + 1) / 2;
+    const int ntab = 2 * nq + kRampOut + 1;
+    return (size_t)(ntab + ntab / 8 + 1 + fdk_filter_rows_per_block(nu) * 2 * nq) * sizeof(float);
+}
+
 // Cosine-weighted, ramp-filtered rows of n_ang projections (proj
 // [n_ang][nv][nu]; filt dense [n_ang][nv][nu] or, if padded, n_ang padded
 // planes whose pads it leaves alone; filt may not alias proj).

@@ -172,9 +172,12 @@ def test_noise_dose_fdk_optics_reject_bad_args(fc):
     assert lib.fcat_fdk_filter(C.byref(geo), 0x1000, 3, 0x1010, None) == 1      # overlapping buffers
     assert lib.fcat_fdk_backproject(C.byref(geo), 0x1000, 1, 1, C.byref(grid), 0x2000, 0, W, 4096, None) == 1
     assert lib.fcat_fdk_backproject_workspace_bytes(360) == 3072 and lib.fcat_fdk_backproject_workspace_bytes(0) == 0  # 256-byte aligned
-    big = fc._CGeometry(1000.0, 1500.0, 9000, 4, 1.0, 1.0, 0.0, 0.0, 3, None)
-    assert lib.fcat_fdk_filter(C.byref(big), 0x1000, 3, 0x8000000, None) == 6   # unsupported width
-    tall = fc._CGeometry(1000.0, 1500.0, 8192, 40000, 1.0, 1.0, 0.0, 0.0, 3, None)
+    # the ramp filter holds a row and its taps in 64 KiB of LDS: nu <= 7704
+    for nu in (7705, 7706, 8192, 9000):
+        big = fc._CGeometry(1000.0, 1500.0, nu, 4, 1.0, 1.0, 0.0, 0.0, 3, None)
+        assert lib.fcat_fdk_filter(C.byref(big), 0x1000, 3, 0x8000000, None) == 6   # unsupported width
+        assert lib.fcat_fdk(C.byref(big), 0x1000, C.byref(grid), 0x2000, W, 1 << 26, None) == 6
+    tall = fc._CGeometry(1000.0, 1500.0, 7704, 40000, 1.0, 1.0, 0.0, 0.0, 3, None)
     assert lib.fcat_fdk(C.byref(tall), 0x1000, C.byref(grid), 0x2000, W, 1 << 26, None) == 6   # quad plane >= 4 GiB
     # workspace of fcat_fdk: (cos, sin) of the angles, then per angle of a
     # chunk the zero-padded rows and their 2 x 2 sample quads
