@@ -422,7 +422,10 @@ __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTable
 }
 
 // Reports a non-finite flood or scatter value read for this ray
-// (bad[1] |= 1).  Only the error case pays for the atomic.
+// (bad[1] |= 1).  Only the error case pays for the atomic.  Call it after
+// the last read of the spectral tables: the compiler cannot tell that the
+// flag word is not part of a table, and a store before those reads would
+// turn their wave-uniform scalar loads into per-lane vector loads.
 __device__ __forceinline__ void flag_nonfinite(int *bad, float i0, float sc)
 {
     if (bad && !(isfinite(i0) && isfinite(sc))) atomicOr(bad + 1, 1);

@@ -40,7 +40,6 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
     const int64_t pix = (int64_t)iv * G.nu + iu;
     const float i0 = flood ? flood[pix] : 1.0f;
     const float sc = scatter ? scatter[(int64_t)a * plane + pix] : 0.0f;
-    flag_nonfinite(G.bad, i0, sc);
     float total = 0.0f;
     for (int g = 0; g < T.G; ++g) {
         const float acc = any_hit ? group_sum<MP>(L, T, T.gstart[g], T.gstart[g + 1]) : T.Wg[g];
@@ -51,6 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
             total += y;
     }
     if (!Y) out[(int64_t)a * plane + pix] = total;
+    flag_nonfinite(G.bad, i0, sc);
 }
 
 template <int MP>

@@ -364,7 +364,6 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
     const int64_t al = r / io.plane, pix = r - al * io.plane;
     const float i0 = io.flood ? io.flood[pix] : 1.0f;
     const float sc = io.scatter ? io.scatter[r] : 0.0f;
-    flag_nonfinite(io.bad, i0, sc);
     float total = 0.0f;
     for (int g = 0; g < T.G; ++g) {
         float prim;
@@ -390,6 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
             total += y;
     }
     if (io.out) io.out[r] = total;
+    flag_nonfinite(io.bad, i0, sc);
 }
 
 struct TrainLds {

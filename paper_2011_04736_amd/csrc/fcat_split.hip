@@ -132,7 +132,6 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
     const int64_t pix = (int64_t)min(iv, G.nv - 1) * G.nu + min(iu, G.nu - 1);   // all lanes take part
     const float i0 = flood ? flood[pix] : 1.0f;
     const float sc = scatter ? scatter[(int64_t)a * plane + pix] : 0.0f;
-    flag_nonfinite(G.bad, i0, sc);
     float total = 0.0f;
     auto emit = [&](int g, float prim) {
         const float y = fmaf(i0, prim, T.Wsg[g] * sc);
@@ -148,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
         for (int g = 0; g < T.G; ++g) emit(g, T.Wg[g]);
     }
     if (!Y && valid) out[(int64_t)a * plane + pix] = total;
+    flag_nonfinite(G.bad, i0, sc);
 }
 
 template <int MP, int NKB>
