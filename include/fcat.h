@@ -248,6 +248,22 @@ fcat_status fcat_spectral(const float *L, int64_t n, const fcat_spectral_t *spec
                           float *Y, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * fcat_spectral without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as fcat_spectral;
+ * its tables (at most about 1.4 MiB: n_energy <= 4096, n_mat <= 32) go to a
+ * static 2 MiB device array of the library, which each GPU it runs on holds
+ * from the first call until the process ends.  The call allocates nothing.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams, threads) race and must not be made; calls
+ * on one stream are ordered and safe.  Tables larger than the array give
+ * FCAT_E_UNSUPPORTED (none within the limits above does).
+ */
+fcat_status fcat_spectral_static(const float *L, int64_t n, const fcat_spectral_t *spectral,
+                                 const float *i0, const float *S, const float *s_bin, fcat_mode mode,
+                                 float *Y, void *stream);
+
+/*
  * Optical spread and group sum (Sec. II.G): out[a][v][u] =
  * sum_g sum_{p,q} K[g][p][q] Y[a][g][v-p+c][u-q+c], zero outside, c = (k-1)/2.
  * Y DEVICE float [n_ang][n_groups][nv][nu], out DEVICE float [n_ang][nv][nu].

@@ -30,7 +30,7 @@ __all__ = [
     "FcatError", "MODES", "STAGES", "Geometry", "Phantom", "Spectral", "Scatter", "Psf", "Problem", "Noise",
     "Surrogate", "MlpTrain", "lib_path", "load", "upload", "project", "fcat_version", "fcat_status_string",
     "fcat_last_error", "fcat_project_workspace_bytes", "fcat_project", "fcat_project_status", "fcat_pathlengths_workspace_bytes",
-    "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_psf", "fcat_check_inputs",
+    "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_spectral_static", "fcat_psf", "fcat_check_inputs",
     "fcat_timing_enable", "fcat_timing_read", "fcat_count_scale", "fcat_poisson", "fcat_flood_workspace_bytes",
     "fcat_flood_profile", "fcat_log_projection", "fcat_projections_workspace_bytes", "fcat_projections",
     "fcat_dose_workspace_bytes", "fcat_dose", "fcat_fdk_filter", "fcat_fdk_backproject_workspace_bytes",
@@ -145,6 +145,8 @@ def load() -> C.CDLL:
     L.fcat_spectral_workspace_bytes.restype = sz
     L.fcat_spectral.argtypes = [vp, C.c_int64, sp, vp, vp, vp, st, vp, vp, sz, vp]
     L.fcat_spectral.restype = st
+    L.fcat_spectral_static.argtypes = [vp, C.c_int64, sp, vp, vp, vp, st, vp, vp]
+    L.fcat_spectral_static.restype = st
     L.fcat_psf.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, psp, vp, vp]
     L.fcat_psf.restype = st
     L.fcat_check_inputs.argtypes = [gp, pp, sp, scp, psp, vp, sz, vp]
@@ -681,6 +683,28 @@ def fcat_spectral(L, spectral: Spectral, i0=None, S=None, s_bin=None, mode: str 
         workspace = _workspace(fcat_spectral_workspace_bytes(spectral), L.device)
     wp, wn = _ws(workspace)
     _check(load().fcat_spectral(pL, n, C.byref(cs), pi0, pS, psb, md, _ptr(out), wp, wn, _stream(stream)))
+    return out
+
+
+@_entry
+def fcat_spectral_static(L, spectral: Spectral, i0=None, S=None, s_bin=None, mode: str = "plain", out=None,
+                         stream=None):
+    """fcat_spectral with its tables in the library's static scratch (no workspace)."""
+    f32 = _torch().float32
+    cs, _keep = spectral.c()
+    M, E = (int(x) for x in spectral.mu.shape)
+    pL = _arg(L, "L", f32, (None, M))
+    n = int(L.shape[0])
+    pi0 = _arg(i0, "i0", f32, (n,), optional=True)
+    pS = _arg(S, "S", f32, (n,), optional=True)
+    psb = _arg(s_bin, "s_bin", f32, (E,), optional=True)
+    if out is not None:
+        _arg(out, "out", f32, (spectral.n_groups, n))
+    md = _mode(mode)
+    torch = _require_gpu()
+    if out is None:
+        out = torch.empty((spectral.n_groups, n), dtype=torch.float32, device=L.device)
+    _check(load().fcat_spectral_static(pL, n, C.byref(cs), pi0, pS, psb, md, _ptr(out), _stream(stream)))
     return out
 
 

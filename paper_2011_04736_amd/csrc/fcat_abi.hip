@@ -13,6 +13,14 @@
 #include <string>
 #include <vector>
 
+// Static scratch of fcat_spectral_static, for callers that cannot allocate
+// device memory: its spectral tables live here instead of in a workspace.
+// Each GPU holds its own copy of the array (at its own address) from the
+// first call on it until the process ends.  In host code the array's name
+// is not a device address; the address comes from hipGetSymbolAddress, once
+// per device, and only that address is ever passed to a kernel.
+static __device__ __align__(256) unsigned char scratch[2u << 20];
+
 namespace fcat {
 namespace {
 
@@ -258,6 +266,32 @@ fcat_status check_workspace(void *ws, size_t have, size_t need)
     if (!ws) return fail(FCAT_E_WORKSPACE, "workspace is NULL (%zu bytes needed)", need);
     if ((uintptr_t)ws % kAlign) return fail(FCAT_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
     if (have < need) return fail(FCAT_E_WORKSPACE, "workspace has %zu bytes, %zu needed", have, need);
+    return FCAT_OK;
+}
+
+// ------------------------------------------------------------ static scratch
+
+constexpr size_t kStaticScratchBytes = sizeof(scratch);
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_at[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+fcat_status static_scratch(void **addr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FCAT_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (uintptr_t)p % kAlign) return fail(FCAT_E_DEVICE, "static scratch at an unusable address");
+        g_scratch_at[dev] = p;
+    }
+    *addr = g_scratch_at[dev];
     return FCAT_OK;
 }
 
@@ -1303,11 +1337,13 @@ size_t fcat_spectral_workspace_bytes(const fcat_spectral_t *spectral)
     return layout(t, nullptr, false, 0, &sp).fixed;   // enough for either mode
 }
 
-fcat_status fcat_spectral(const float *Lin, int64_t n, const fcat_spectral_t *spectral, const float *i0,
-                          const float *S, const float *s_bin, fcat_mode mode, float *Y, void *workspace,
-                          size_t workspace_bytes, void *stream_)
+// Eq. 3 on given path lengths, its tables in `workspace` (the caller's, or
+// this device's copy of the static scratch).  scratch_ws makes the workspace
+// the static scratch, looked up only once the arguments have been checked.
+static fcat_status spectral_impl(const float *Lin, int64_t n, const fcat_spectral_t *spectral, const float *i0,
+                                 const float *S, const float *s_bin, fcat_mode mode, float *Y, void *workspace,
+                                 size_t workspace_bytes, bool scratch_ws, void *stream_)
 {
-    g_last_error.clear();
     SpecTables t{};
     fcat_status s;
     if ((s = check_spectral(spectral, true, t))) return s;
@@ -1319,6 +1355,14 @@ fcat_status fcat_spectral(const float *Lin, int64_t n, const fcat_spectral_t *sp
     SplitTables sp{};
     split_host(t, sp);
     Layout L = layout(t, nullptr, false, 0, split ? &sp : nullptr);
+    if (scratch_ws) {
+        if (L.fixed > kStaticScratchBytes)
+            return fail(FCAT_E_UNSUPPORTED, "the tables need %zu bytes, the static scratch holds %zu", L.fixed,
+                        kStaticScratchBytes);
+        if (n == 0) return FCAT_OK;
+        if ((s = static_scratch(&workspace))) return s;
+        workspace_bytes = kStaticScratchBytes;
+    }
     if ((s = check_workspace(workspace, workspace_bytes, L.fixed))) return s;
     if (n == 0) return FCAT_OK;
     if ((s = check_pending())) return s;
@@ -1332,6 +1376,21 @@ fcat_status fcat_spectral(const float *Lin, int64_t n, const fcat_spectral_t *sp
     }
     if (e != hipSuccess) return device_fail(e, "spectral");
     return FCAT_OK;
+}
+
+fcat_status fcat_spectral(const float *Lin, int64_t n, const fcat_spectral_t *spectral, const float *i0,
+                          const float *S, const float *s_bin, fcat_mode mode, float *Y, void *workspace,
+                          size_t workspace_bytes, void *stream)
+{
+    g_last_error.clear();
+    return spectral_impl(Lin, n, spectral, i0, S, s_bin, mode, Y, workspace, workspace_bytes, false, stream);
+}
+
+fcat_status fcat_spectral_static(const float *Lin, int64_t n, const fcat_spectral_t *spectral, const float *i0,
+                                 const float *S, const float *s_bin, fcat_mode mode, float *Y, void *stream)
+{
+    g_last_error.clear();
+    return spectral_impl(Lin, n, spectral, i0, S, s_bin, mode, Y, nullptr, 0, true, stream);
 }
 
 fcat_status fcat_psf(const float *Y, int32_t n_ang, int32_t n_groups, int32_t nv, int32_t nu,
