@@ -1,19 +1,23 @@
 """Benchmark of the polyenergetic cone-beam projector on one MI355X.
 
-A step is one fcat_project call over the whole contrast-phantom workload:
-1024x1024x10 labelled voxels (0.15625 mm, 8 materials), 200 energy bins
-(0.01-6 MeV), 1024x64 detector at 0.392 mm, 360 angles, per-angle scatter
-maps and 8 energy-group 15x15 optical spread kernels.  Inputs are seeded
-synthetic stand-ins, resident in HBM before timing starts.
+A step is one fcat_project call over the whole head workload, the largest
+single-GPU configuration: 512x512x256 labelled voxels (0.5 mm, 10
+materials), a 120 kVp spectrum in 120 bins of 1 keV, a 1024x768 detector at
+0.4 mm, 720 angles, per-angle scatter maps and 8 energy-group 15x15 optical
+spread kernels.  Inputs are seeded synthetic stand-ins, resident in HBM
+before timing starts.
 
-Prints one JSON line: rays x energy-bins per second of the plain FP32 form,
-the roofline of the dominant kernel (timed live with HIP events on the
-library's stream), the two other forms of the projector (BF16 hi/lo split on
-the same workload; the learned surrogate on the head workload, trained here
-by the library's own kernels) with their error against the plain form, the
-noise and projection stage after the projector (Poisson counts of Eq. 5,
-log conversion through the flood) on the same workload, and the FP64 oracle
-timed on the host on a bounded sample of the workload.
+Prints one JSON line: rays x energy-bins per second of the plain FP32 form on
+that workload, the roofline of its dominant kernel (timed live with HIP
+events on the library's stream) priced by two work units (the Siddon voxel
+segments of the method and the steps the walk actually takes, both counted
+on the GPU by fcat_walk_stats), the FP64 oracle timed on the host on 16 of
+the 720 angles; then the contrast phantom and its thick-slab variant as
+secondary workloads, the other two forms of the projector (BF16 hi/lo split
+on the matrix cores; the learned surrogate trained here by the library's own
+kernels) with their errors against the plain form and their rooflines, the
+stages after the projector on the contrast workload, the device-ceiling
+microbenchmark, and the oracle's single-thread time on the tiny case.
 """
 import argparse
 import hashlib
@@ -28,15 +32,33 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 compute units x 4 SIMDs x 16 lanes at 2.4 GHz.
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9          # 3.93e13 vector lane-operations per second
-PEAK_FP32_VECTOR_TFLOPS = 157.3               # published FP32 vector peak (packed FMA)
-PEAK_BF16_MFMA_TFLOPS = 2500.0                # published dense BF16 matrix peak
+# MI355X published peaks.
+PEAK_FP32_VECTOR_TFLOPS = 157.3               # FP32 vector, counted with packed FMA (2 FP32 FMAs per lane per cycle)
+PEAK_BF16_MFMA_TFLOPS = 2500.0                # dense BF16 matrix
 PEAK_HBM_GBPS = 8000.0
+# Lane-operation peak for plain-ALU rows: the published FP32 rate in FMAs,
+# 157.3e12 FLOP/s / 2 FLOP per FMA = 78.65e12 lane-operations/s.  That rate
+# assumes packed FP32, which this library never emits; one unpacked vector
+# instruction per SIMD per cycle over 16 lanes gives 256 CUs x 4 SIMDs x 16 x
+# 2.4 GHz = 39.32e12, reported beside it.
+PEAK_LANE_OPS = PEAK_FP32_VECTOR_TFLOPS * 1e12 / 2
+SINGLE_ISSUE_LANE_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_NOTE = ("peak: published FP32 157.3 TFLOP/s / 2 FLOP per FMA = 78.65e12 lane-ops/s (packed issue); "
+             "peak_single_issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12")
 
 # Algorithmic work per unit (vector lane-operations).
-OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk
-EXP_SLOTS = 4                 # lane-operations counted for one exp (the hardware exp2 is half rate; expf adds its reduction)
+OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk (survey's count)
+EXP_SLOTS = 4                 # lane-operations counted for one exp (the hardware exp2 is half rate; the reduction adds more)
+
+WORKLOADS = {
+    "head": (3, "", "head phantom 512x512x256 @0.5 mm, 10 materials, 120 bins 1-120 keV, 1024x768 detector "
+                    "@0.4 mm, 720 angles, scatter + 8 groups 15x15 PSF"),
+    "contrast": (2, "", "contrast phantom 1024x1024x10 @0.15625 mm, 8 materials, 200 bins 0.01-6 MeV, "
+                        "1024x64 detector @0.392 mm, 360 angles, scatter + 8 groups 15x15 PSF"),
+    "contrast_dz": (2, "z", "contrast phantom 1024x1024x10 @0.15625 x 0.15625 x 1.5625 mm (thick-slab variant), "
+                            "8 materials, 200 bins 0.01-6 MeV, 1024x64 detector @0.392 mm, 360 angles, scatter + "
+                            "8 groups 15x15 PSF"),
+}
 
 
 def parse():
@@ -44,9 +66,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-angles", type=int, default=360,
-                    help="angles of the workload the FP64 oracle is timed on (0: skip)")
-    ap.add_argument("--variant", default="", help="'z' for the 1.5625 mm slab variant")
+    ap.add_argument("--workload", default="head", choices=sorted(WORKLOADS),
+                    help="the headline workload (default: the largest, head)")
+    ap.add_argument("--secondary", default="contrast,contrast_dz",
+                    help="comma list of further workloads timed in the plain form ('' for none)")
+    ap.add_argument("--secondary-steps", type=int, default=10)
+    ap.add_argument("--cpu-angles", type=int, default=16,
+                    help="angles of the headline workload the FP64 oracle is timed on (0: skip)")
+    ap.add_argument("--tiny-oracle", type=int, default=1, help="1: time the oracle single-threaded on the tiny case")
     ap.add_argument("--noise-counts", type=float, default=1.0e5,
                     help="H of Eq. 5 (flood counts per open pixel) for the noise stage; 0 skips it")
     ap.add_argument("--dose", type=int, default=1, help="1: time the dose estimate of Eqs. 6-7 (0 skips it)")
@@ -58,47 +85,12 @@ def parse():
                     help="1: run the device-ceiling microbenchmark and add fractions of the measured ceilings")
     ap.add_argument("--forms", default="split_bf16,surrogate",
                     help="comma list of extra forms to measure beside the plain one ('' for none)")
-    ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the head workload forms")
+    ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the extra forms and stages")
     ap.add_argument("--surrogate-samples", type=int, default=4_000_000)
     ap.add_argument("--surrogate-epochs", type=int, default=120)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale reference for HBM counters)")
     return ap.parse_args()
-
-
-# ----------------------------------------------------------------- counts
-
-def workload_counts(cfg, angles=None) -> dict:
-    """Rays, rays that cross the phantom and voxel segments of the exact walk
-    (per-axis voxel-plane crossings inside the box, plus one), for the given
-    angles; FP64 slab method in the conventions of the library."""
-    g, p = cfg.geometry, cfg.phantom
-    n = np.array([p.nx, p.ny, p.nz], np.float64)
-    h = np.array([p.dx, p.dy, p.dz], np.float64)
-    lo = np.array([p.cx, p.cy, p.cz], np.float64) - n * h / 2
-    hi = lo + n * h
-    th = g.angle_values()
-    if angles is None:
-        angles = np.arange(g.n_angles)
-    pu = ((np.arange(g.nu) - (g.nu - 1) / 2) * g.du + g.off_u)[None, :]
-    pv = ((np.arange(g.nv) - (g.nv - 1) / 2) * g.dv + g.off_v)[:, None]
-    segs = hits = 0
-    for a in angles:
-        c, s = np.cos(th[a]), np.sin(th[a])
-        src = np.array([g.sid * c, g.sid * s, 0.0])
-        cen = -(g.sdd - g.sid) * np.array([c, s, 0.0])
-        dst = np.stack(np.broadcast_arrays(cen[0] - pu * s, cen[1] + pu * c, pv + 0 * pu), -1)
-        d = dst - src
-        with np.errstate(divide="ignore", invalid="ignore"):
-            a0, a1 = (lo - src) / d, (hi - src) / d
-            amin = np.maximum(0.0, np.nanmax(np.minimum(a0, a1), -1))
-            amax = np.minimum(1.0, np.nanmin(np.maximum(a0, a1), -1))
-        hit = amax > amin
-        i0 = np.clip(np.floor((src + amin[..., None] * d - lo) / h), 0, n - 1)
-        i1 = np.clip(np.floor((src + amax[..., None] * d - lo) / h), 0, n - 1)
-        segs += int((1 + np.abs(i1 - i0).sum(-1))[hit].sum())
-        hits += int(hit.sum())
-    return {"rays": len(angles) * g.nu * g.nv, "hit_rays": hits, "segments": segs}
 
 
 # -------------------------------------------------------------- traffic
@@ -112,24 +104,67 @@ def source_digest(files) -> str:
 
 
 TRACE_SOURCES = ["fcat_kernels.hip", "fcat_device.h", "fcat_internal.h"]
+SPLIT_SOURCES = ["fcat_split.hip", "fcat_device.h", "fcat_internal.h"]
 NOISE_SOURCES = ["fcat_noise.hip", "fcat_internal.h"]
 DOSE_SOURCES = ["fcat_dose.hip", "fcat_internal.h"]
 FDK_SOURCES = ["fcat_fdk.hip", "fcat_recon.h"]
 BP_OPS_PER_VOXEL_ANGLE = 10   # axial position 1, floor and fraction 2, four-tap bilinear 6, weighted add 1
 
 
-def profiled_traffic(kernel: str, digest: str):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary,
-    or None when the summary is missing or was taken on other sources."""
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_contrast.txt")
+def profiled_traffic(kernel: str, digest: str, workload: str = "contrast"):
+    """HBM bytes per step (all launches of the kernel in one step) of ``kernel``
+    from the committed counter summary of the workload, or None when the
+    summary is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"^sources:\s*(\S+)", text, re.M)
-    t = re.search(r"^traffic_bytes_per_launch:\s*(\S+)", text, re.M)
+    t = re.search(r"^traffic_bytes_per_step:\s*(\S+)", text, re.M) or \
+        re.search(r"^traffic_bytes_per_launch:\s*(\S+)", text, re.M)
     if not m or not t or m.group(1) != digest:
         return None
     return float(t.group(1))
+
+
+def profiled_counters(kernel: str, digest: str, workload: str) -> dict:
+    """Derived counter figures (issue rate, MFMA busy, L2 hit ...) of ``kernel``
+    from the committed counter summary of the workload, if it was taken on
+    the current sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.txt")
+    if not os.path.exists(path):
+        return {}
+    text = open(path).read()
+    m = re.search(r"^sources:\s*(\S+)", text, re.M)
+    if not m or m.group(1) != digest:
+        return {}
+    for b in re.split(r"\n(?=\S)", text):
+        if b.startswith(kernel):
+            out = {}
+            for key, name in (("VALU issue rate", "valu_issue_vs_16_lane_rate"), ("MFMA busy", "mfma_busy"),
+                              ("L2 hit rate", "l2_hit"), ("LDS bank-conflict share", "lds_bank_conflict_share"),
+                              ("wait share of wave cycles", "wait_share"),
+                              ("ACTIVE_INST_VALU2 / VALU", "valu2_share"),
+                              ("VALU lane-slots per segment", "valu_lane_slots_per_segment")):
+                mm = re.search(rf"^\s+{re.escape(key)}\s+([0-9.eE+-]+)", b, re.M)
+                if mm:
+                    out[name] = float(mm.group(1))
+            return out
+    return {}
+
+
+def alu_roof(kernel: str, ops: float, ms: float, launches: float = 1, **extra) -> dict:
+    """Roofline entry of a plain-ALU kernel: ``ops`` algorithmic lane-operations
+    per step in ``ms`` per step over ``launches`` launches."""
+    ach = ops / (ms * 1e-3)
+    e = {"kernel": kernel, "bound": "alu", "achieved": round(ach / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
+         "unit": "Top/s", "frac": round(ach / PEAK_LANE_OPS, 4),
+         "peak_single_issue": round(SINGLE_ISSUE_LANE_OPS / 1e12, 2),
+         "frac_single_issue": round(ach / SINGLE_ISSUE_LANE_OPS, 4),
+         "stage_ms_per_step": round(ms, 4), "launches_per_step": launches,
+         "avg_launch_ms": round(ms / max(launches, 1), 4), "algorithmic_ops_per_step": ops}
+    e.update(extra)
+    return e
 
 
 # ----------------------------------------------------------------- forms
@@ -171,7 +206,7 @@ def optics_stage(pb, cfg, args, torch, fc):
 
 
 # v_exp_f32 issues at half the 16-lane rate (measured by the ceiling probe)
-EXP_RATE = 256 * 4 * 16 * 2.4e9 / 2
+EXP_RATE = SINGLE_ISSUE_LANE_OPS / 2
 
 
 def spectral_stage(pb, cfg, args, torch, fc):
@@ -201,7 +236,8 @@ def spectral_stage(pb, cfg, args, torch, fc):
         "exp_per_s": exps / (t * 1e-3),
         "exp_rate_frac": round(exps / (t * 1e-3) / EXP_RATE, 4),
         "roofline": {"kernel": "k_spectral", "bound": "alu", "achieved": round(ach / 1e12, 3),
-                     "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Top/s", "frac": round(ach / VALU_LANE_OPS, 4),
+                     "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Top/s", "frac": round(ach / PEAK_LANE_OPS, 4),
+                     "frac_single_issue": round(ach / SINGLE_ISSUE_LANE_OPS, 4),
                      "note": "per hit ray and bin M FMAs, the weight FMA, the scale and an exp counted as "
                              "EXP_SLOTS lane-operations; the exp unit itself is far from busy (exp_rate_frac)"},
     }
@@ -242,8 +278,9 @@ def fdk_stage(pb, cfg, args, torch, fc):
         "voxel_angle_updates_per_s": vox_ang / (bp_ms * 1e-3),
         "finite": finite,
         "roofline": {"kernel": "k_fdk_backproject", "bound": "alu", "achieved": round(bp_ach, 3),
-                     "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Top/s",
-                     "frac": round(bp_ach * 1e12 / VALU_LANE_OPS, 4), "stage_ms": round(bp_ms, 4),
+                     "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Top/s",
+                     "frac": round(bp_ach * 1e12 / PEAK_LANE_OPS, 4),
+                     "frac_single_issue": round(bp_ach * 1e12 / SINGLE_ISSUE_LANE_OPS, 4), "stage_ms": round(bp_ms, 4),
                      "algorithmic_ops_per_step": bp_ops,
                      "traffic": profiled_traffic("k_fdk_backproject", source_digest(FDK_SOURCES))},
         "filter": {"kernel": "k_fdk_filter", "bound": "alu", "achieved": round(fl_ach, 3),
@@ -291,8 +328,9 @@ def dose_stage(pb, cfg, args, torch, fc, hit_rays):
         "mass_kg": mass,
         "Dp_MeV_per_kg_per_particle": float(Dp.item()),
         "roofline": {"kernel": "k_dose_rays (+ k_dose_sum)", "bound": "alu", "achieved": round(ach, 3),
-                     "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Top/s",
-                     "frac": round(ach * 1e12 / VALU_LANE_OPS, 4), "stage_ms": round(per_step, 4),
+                     "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Top/s",
+                     "frac": round(ach * 1e12 / PEAK_LANE_OPS, 4),
+                     "frac_single_issue": round(ach * 1e12 / SINGLE_ISSUE_LANE_OPS, 4), "stage_ms": round(per_step, 4),
                      "algorithmic_ops_per_step": ops,
                      "traffic": profiled_traffic("k_dose_rays", source_digest(DOSE_SOURCES))},
     }
@@ -362,70 +400,167 @@ def rel_errors(x, ref, torch):
     return mx, (ss / n) ** 0.5
 
 
-def form_split(pb, cfg, plain_out, args, torch, fc):
+def walk_work(counts: dict, M: int, E: int) -> tuple[float, float]:
+    """(model, executed) lane-operations of the fused walk + spectral kernel:
+    OPS_PER_SEGMENT per Siddon voxel segment (the survey's unit of the
+    method's work) or per step the two-level walk takes (brick steps plus
+    voxel steps inside mixed bricks), plus the spectral sum of every hit ray
+    (M FMAs, the scale, the weight FMA and an exp of EXP_SLOTS per bin)."""
+    spectral = counts["hit_rays"] * E * (M + 2 + EXP_SLOTS)
+    model = OPS_PER_SEGMENT * counts["siddon_segments"] + spectral
+    executed = OPS_PER_SEGMENT * (counts["brick_steps"] + counts["voxel_steps"]) + spectral
+    return float(model), float(executed)
+
+
+def plain_workload(name, pb, cfg, warmup, steps, torch, fc):
+    """The plain form on one workload: throughput, stage times, walk counts and
+    the rooflines of its two kernels.  Returns (entry, out)."""
+    g, s = cfg.geometry, cfg.spectral
+    dev = pb.phantom.labels.device
+    out = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "plain"), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    elapsed, stages = timed_steps(lambda: fc.fcat_project(pb, mode="plain", out=out, workspace=ws, stream=stream),
+                                  warmup, steps, torch)
+    del ws
+    counts = fc.fcat_walk_stats(pb)
+    rays = g.n_angles * g.nu * g.nv
+    M, E, G, K = s.n_mat, s.n_energy, s.n_groups, cfg.psf.k
+    mp = 8 if M <= 8 else (12 if M <= 12 else (16 if M <= 16 else 32))
+    model, executed = walk_work(counts, M, E)
+    trace_ms, trace_n = (v / steps for v in stages["trace"])
+    psf_ms, psf_n = (v / steps for v in stages["psf"])
+    digest = source_digest(TRACE_SOURCES)
+    walk = alu_roof(f"k_project_rows<{mp}>", model, trace_ms, trace_n,
+                    traffic=profiled_traffic("k_project_rows", digest, name),
+                    work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment + {M + 2 + EXP_SLOTS} per hit "
+                              f"ray and bin",
+                    executed=alu_roof("same launches", executed, trace_ms, trace_n,
+                                      work_unit=f"{OPS_PER_SEGMENT} lane-ops per walk step taken (brick steps + voxel "
+                                                f"steps in mixed bricks) + the same spectral work"),
+                    counters=profiled_counters("k_project_rows", digest, name))
+    psf_flops = 2.0 * G * K * K * rays
+    psf_ach = psf_flops / (psf_ms * 1e-3) / 1e12
+    psf = {"kernel": "k_psf4<15, 8, 0>", "bound": "alu", "achieved": round(psf_ach, 3),
+           "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": round(psf_ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+           "stage_ms_per_step": round(psf_ms, 4), "launches_per_step": psf_n,
+           "avg_launch_ms": round(psf_ms / max(psf_n, 1), 4), "algorithmic_flops_per_step": psf_flops,
+           "traffic": profiled_traffic("k_psf", digest, name),
+           "counters": profiled_counters("k_psf4", digest, name)}
+    kernels = {"k_project_rows": walk, "k_psf": psf}
+    dom = kernels["k_project_rows"] if trace_ms >= psf_ms else kernels["k_psf"]
+    roof = {k: dom.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic")}
+    entry = {
+        "workload": WORKLOADS[name][2],
+        "value": rays * E * steps / elapsed, "unit": "ray*E/s",
+        "ms_per_step": 1e3 * elapsed / steps, "steps": steps,
+        "rays": rays, "energy_bins": E,
+        "walk": counts,
+        "stages_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]},
+        "roofline": roof, "kernels": kernels,
+    }
+    return entry, out
+
+
+def form_split(name, pb, cfg, plain_out, steps, torch, fc, counts):
+    """The BF16 hi/lo form on a workload: throughput, error against the plain
+    form, and the rooflines of its kernels (the walk as in the plain form;
+    the contraction and the spread on the matrix cores)."""
     g, s = cfg.geometry, cfg.spectral
     out = torch.empty_like(plain_out)
     ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "split_bf16"), dtype=torch.uint8, device=out.device)
     elapsed, stages = timed_steps(lambda: fc.fcat_project(pb, mode="split_bf16", out=out, workspace=ws),
-                                  1, args.steps, torch)
-    mx, rms = rel_errors(out, plain_out, torch)
-    ray_e = g.n_angles * g.nu * g.nv * s.n_energy
-    return {"workload": "contrast phantom (as the plain form)", "value": ray_e * args.steps / elapsed,
-            "unit": "ray*E/s", "ms_per_step": 1e3 * elapsed / args.steps,
-            "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
-            "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
-            "note": "the plain form is within 1e-5 of the FP64 oracle (parity tests)"}
-
-
-def form_surrogate(args, torch, fc):
-    import synth
-    from paper_2011_04736_amd import surrogate as sg
-    cfg = synth.make_config(5)
-    g, s = cfg.geometry, cfg.spectral
-    pb = fc.upload(cfg)
-    dev = pb.phantom.labels.device
-    ray_e = g.n_angles * g.nu * g.nv * s.n_energy
-    K = args.form_steps
-    plain = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
-    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "plain"), dtype=torch.uint8, device=dev)
-    t_plain, st_plain = timed_steps(lambda: fc.fcat_project(pb, mode="plain", out=plain, workspace=ws), 1, K, torch)
+                                  1, steps, torch)
     del ws
-    torch.cuda.empty_cache()
+    mx, rms = rel_errors(out, plain_out, torch)
+    del out
+    rays = g.n_angles * g.nu * g.nv
+    M, E, G, K = s.n_mat, s.n_energy, s.n_groups, cfg.psf.k
+    model, _ = walk_work(counts, M, E)
+    trace_ms, trace_n = (v / steps for v in stages["trace"])
+    psf_ms, psf_n = (v / steps for v in stages["psf"])
+    digest = source_digest(SPLIT_SOURCES)
+    # useful matrix-core work: the three BF16 products (hi.hi, lo.hi, hi.lo)
+    # of the contraction, M terms each per hit ray and bin; of the spread,
+    # K^2 taps per group and pixel
+    con_flops = 2.0 * 3 * M * E * counts["hit_rays"]
+    psf_flops = 2.0 * 3 * G * K * K * rays
+    mf = lambda f, ms: round(f / (ms * 1e-3) / 1e12, 3)
+    kernels = {
+        "k_project_rows_split": alu_roof("k_project_rows_split", model, trace_ms, trace_n,
+                                         counters=profiled_counters("k_project_rows_split", digest, name),
+                                         mfma={"bound": "mfma", "achieved": mf(con_flops, trace_ms),
+                                               "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                               "frac": round(mf(con_flops, trace_ms) / PEAK_BF16_MFMA_TFLOPS, 6),
+                                               "algorithmic_flops_per_step": con_flops}),
+        "k_psf_split": {"kernel": "k_psf_split", "bound": "mfma", "achieved": mf(psf_flops, psf_ms),
+                        "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(mf(psf_flops, psf_ms) / PEAK_BF16_MFMA_TFLOPS, 5),
+                        "stage_ms_per_step": round(psf_ms, 4), "launches_per_step": psf_n,
+                        "algorithmic_flops_per_step": psf_flops,
+                        "counters": profiled_counters("k_psf_split", digest, name)},
+    }
+    dom = kernels["k_project_rows_split"] if trace_ms >= psf_ms else kernels["k_psf_split"]
+    return {"workload": WORKLOADS[name][2], "value": rays * E * steps / elapsed, "unit": "ray*E/s",
+            "ms_per_step": 1e3 * elapsed / steps, "steps": steps,
+            "stages_ms_per_step": {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]},
+            "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
+            "roofline": {k: dom.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")},
+            "kernels": kernels,
+            "note": "the plain form is within 1e-5 and the split form within 1e-3 of the FP64 oracle (parity tests)"}
+
+
+def form_surrogate(pb, cfg, plain, args, torch, fc, counts):
+    """The learned form on the head workload: the network trained here on 4M
+    (L, signal) pairs by the library's kernels, then the projector with the
+    network and the exact fallback, against the plain form's step."""
+    from paper_2011_04736_amd import surrogate as sg
+    g, s = cfg.geometry, cfg.spectral
+    dev = pb.phantom.labels.device
+    rays = g.n_angles * g.nu * g.nv
+    ray_e = rays * s.n_energy
+    K = args.form_steps
     t0 = time.perf_counter()
     sur, rep = sg.build_surrogate(pb, n_samples=args.surrogate_samples, epochs=args.surrogate_epochs)
     t_build = time.perf_counter() - t0
-    out = torch.empty_like(plain)
+    out = torch.empty_like(plain["out"])
     ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "surrogate"), dtype=torch.uint8, device=dev)
     sur.counts = torch.zeros(2, dtype=torch.int32, device=dev)
     fc.fcat_project(pb, mode="surrogate", surrogate=sur, out=out, workspace=ws)
-    counts = sur.counts.cpu().numpy().astype(np.int64)
+    n_net, n_exact = (int(x) for x in sur.counts.cpu().numpy())
     sur.counts = None
-    t_sur, st_sur = timed_steps(lambda: fc.fcat_project(pb, mode="surrogate", surrogate=sur, out=out, workspace=ws),
-                                0, K, torch)
-    mx, rms = rel_errors(out, plain, torch)
-    mlp_ms = st_sur["mlp"][0] / K
-    # network MACs: n_in*64 + 64*64 + 64*n_out per ray that takes the network
+    t_sur, st = timed_steps(lambda: fc.fcat_project(pb, mode="surrogate", surrogate=sur, out=out, workspace=ws),
+                            0, K, torch)
+    del ws
+    mx, rms = rel_errors(out, plain["out"], torch)
+    del out
+    mlp_ms = st["mlp"][0] / K
+    trace_ms, trace_n = (v / K for v in st["trace"])
+    # network MACs per ray: n_in*64 + 64*64 + 64*n_out, each product as three BF16 MFMA terms
     macs = 64 * s.n_mat + 64 * 64 + 64 * s.n_groups
-    result = {
-        "workload": "head phantom 512x512x256 @0.5 mm, 10 materials, 120 bins 1-120 keV, 1024x768 detector "
-                    "@0.4 mm, 720 angles, scatter + 8 groups 15x15 PSF",
-        "plain": {"value": ray_e * K / t_plain, "unit": "ray*E/s", "ms_per_step": 1e3 * t_plain / K,
-                  "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st_plain.items() if v[1]}},
-        "surrogate": {"value": ray_e * K / t_sur, "unit": "ray*E/s", "ms_per_step": 1e3 * t_sur / K,
-                      "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st_sur.items() if v[1]},
-                      "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
-                      "rays_by_network": int(counts[0]), "rays_by_exact_sum": int(counts[1]),
-                      "mlp_stage_mfma_tflops": 2.0 * macs * counts[0] / (mlp_ms * 1e-3) / 1e12,
-                      "mlp_stage_mfma_frac": 2.0 * macs * counts[0] / (mlp_ms * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS},
-        "gain_vs_plain": t_plain / t_sur,
+    net_flops = 2.0 * 3 * macs * n_net
+    ach = net_flops / (mlp_ms * 1e-3) / 1e12
+    walk_ops = float(OPS_PER_SEGMENT * counts["siddon_segments"])
+    return {
+        "workload": WORKLOADS["head"][2],
+        "value": ray_e * K / t_sur, "unit": "ray*E/s", "ms_per_step": 1e3 * t_sur / K, "steps": K,
+        "plain_ms_per_step": plain["ms_per_step"],
+        "gain_vs_plain": plain["ms_per_step"] / (1e3 * t_sur / K),
+        "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st.items() if v[1]},
+        "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
+        "rays_by_network": n_net, "rays_by_exact_sum": n_exact,
+        "roofline": {"kernel": "k_mlp_spectral (network stage)", "bound": "mfma", "achieved": round(ach, 3),
+                     "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_BF16_MFMA_TFLOPS, 5),
+                     "stage_ms_per_step": round(mlp_ms, 4),
+                     "algorithmic_flops_per_step": net_flops,
+                     "work_unit": "2 x 3 BF16 products x (n_in*64 + 64*64 + 64*n_out) MACs per ray the network takes"},
+        "kernels": {"k_pathlengths": alu_roof("k_pathlengths", walk_ops, trace_ms, trace_n,
+                                              work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment")},
         "training": {"samples": rep.n_train, "holdout": rep.n_holdout, "epochs": rep.epochs,
                      "train_seconds": round(rep.seconds, 2), "setup_seconds": round(t_build, 2),
                      "final_loss": rep.epoch_loss[-1], "validated_cells": int(rep.cell_ok.sum()),
                      "holdout_share_in_validated_cells": rep.holdout_in_ok_cells},
     }
-    del pb, out, plain, ws
-    torch.cuda.empty_cache()
-    return result
 
 
 # ------------------------------------------------------------------ main
@@ -458,107 +593,88 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    cfg = synth.make_config(2, variant=args.variant)
+    forms = [f for f in args.forms.split(",") if f]
+    cfgn, variant, desc = WORKLOADS[args.workload]
+    cfg = synth.make_config(cfgn, variant=variant)
     g, s = cfg.geometry, cfg.spectral
     pb = fc.upload(cfg, device=dev)
-    out = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
-    ws = torch.empty(fc.fcat_project_workspace_bytes(pb, "plain"), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-
-    elapsed, stages = timed_steps(lambda: fc.fcat_project(pb, mode="plain", out=out, workspace=ws, stream=stream),
-                                  args.warmup, args.steps, torch)
-
-    rays = g.n_angles * g.nu * g.nv
-    ray_e = rays * s.n_energy
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = ray_e * args.steps / elapsed
-
-    # rooflines of the two kernels of the step; the dominant one is reported
-    cnt = workload_counts(cfg)
-    G, K, M, E = s.n_groups, cfg.psf.k, s.n_mat, s.n_energy
-    trace_ms, trace_n = stages["trace"]
-    psf_ms, psf_n = stages["psf"]
-    trace_ops = (OPS_PER_SEGMENT * cnt["segments"] + cnt["hit_rays"] * E * (M + 2 + EXP_SLOTS)) / max(trace_n
-                                                                                                    / args.steps, 1)
-    trace_avg = trace_ms / max(trace_n, 1)
-    trace_ach = trace_ops / (trace_avg * 1e-3) / 1e12
-    psf_flops = 2.0 * G * K * K * rays / max(psf_n / args.steps, 1)
-    psf_avg = psf_ms / max(psf_n, 1)
-    psf_ach = psf_flops / (psf_avg * 1e-3) / 1e12
-    kernels = {
-        "k_project_rows": {"bound": "alu", "achieved": round(trace_ach, 3), "peak": round(VALU_LANE_OPS / 1e12, 2),
-                           "unit": "Top/s", "frac": round(trace_ach * 1e12 / VALU_LANE_OPS, 4),
-                           "avg_launch_ms": round(trace_avg, 4), "launches_per_step": trace_n / args.steps,
-                           "algorithmic_ops_per_launch": trace_ops,
-                           "traffic": profiled_traffic("k_project_rows", source_digest(TRACE_SOURCES))},
-        "k_psf": {"bound": "alu", "achieved": round(psf_ach, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                  "unit": "TFLOP/s", "frac": round(psf_ach / PEAK_FP32_VECTOR_TFLOPS, 4),
-                  "avg_launch_ms": round(psf_avg, 4), "launches_per_step": psf_n / args.steps,
-                  "algorithmic_flops_per_launch": psf_flops,
-                  "traffic": profiled_traffic("k_psf", source_digest(TRACE_SOURCES))},
-    }
-    dominant = "k_project_rows" if trace_ms >= psf_ms else "k_psf"
-    roof = {k: kernels[dominant][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
-    roof["kernel"] = dominant
-
-    # compulsory HBM traffic per step: labels + scatter maps in, projections out
-    comp_bytes = cfg.phantom.labels.size + 2 * rays * 4
-    hbm = comp_bytes / (ms_per_step * 1e-3) / 1e9
+    head, out = plain_workload(args.workload, pb, cfg, args.warmup, args.steps, torch, fc)
+    counts = head["walk"]
 
     result = {
         "metric": "rays*energy_bins/s",
-        "value": value,
+        "value": head["value"],
         "unit": "ray*E/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded stand-in for the Catphan-like contrast phantom, MV spectrum, scatter and OSFs)",
+        "data": "synthetic (seeded stand-ins for the paper's phantoms, spectra, scatter and OSFs)",
         "config": {
-            "workload": "contrast phantom 1024x1024x10 @0.15625 mm, 8 materials, 200 bins 0.01-6 MeV, "
-                        "1024x64 detector @0.392 mm, 360 angles, scatter + 8 groups 15x15 PSF"
-                        + (" (dz=1.5625 variant)" if args.variant == "z" else ""),
+            "workload": desc,
             "mode": "plain",
-            "rays": rays,
-            "energy_bins": E,
-            "hit_rays": cnt["hit_rays"],
-            "voxel_segments": cnt["segments"],
+            "rays": head["rays"],
+            "energy_bins": s.n_energy,
+            "hit_rays": counts["hit_rays"],
+            "voxel_segments": counts["siddon_segments"],
+            "walk_steps": counts["brick_steps"] + counts["voxel_steps"],
         },
-        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
-        "hbm_compulsory_GBps": round(hbm, 2),
-        "roofline": roof,
-        "kernels": kernels,
+        "stages_ms_per_step": head["stages_ms_per_step"],
+        "roofline": head["roofline"],
+        "roofline_peak_note": PEAK_NOTE,
+        "kernels": head["kernels"],
+        "walk": counts,
     }
-
-    forms = [f for f in args.forms.split(",") if f]
     result["forms"] = {}
     if "split_bf16" in forms:
-        result["forms"]["split_bf16"] = form_split(pb, cfg, out, args, torch, fc)
-    del ws, out
+        result["forms"]["split_bf16"] = {args.workload: form_split(args.workload, pb, cfg, out, args.form_steps,
+                                                                   torch, fc, counts)}
+    if "surrogate" in forms and args.workload == "head":
+        result["forms"]["surrogate"] = form_surrogate(pb, cfg, {"out": out, "ms_per_step": head["ms_per_step"]},
+                                                      args, torch, fc, counts)
+    del pb, out
     torch.cuda.empty_cache()
-    result["stages"] = {"spectral": spectral_stage(pb, cfg, args, torch, fc)} if args.spectral else {}
+
+    # secondary workloads; the contrast one also carries the split form of
+    # its own configuration and the stages after the projector
+    result["workloads"] = {}
     result["next"] = {}
-    if args.noise_counts > 0:
-        result["next"]["noise_and_projections"] = noise_stage(pb, cfg, args, torch, fc)
-    if args.dose:
-        result["next"]["dose"] = dose_stage(pb, cfg, args, torch, fc, cnt["hit_rays"])
-    if args.fdk:
-        result["next"]["fdk"] = fdk_stage(pb, cfg, args, torch, fc)
-    if args.rl_iterations > 0:
-        result["next"]["optics"] = optics_stage(pb, cfg, args, torch, fc)
-    del pb
-    torch.cuda.empty_cache()
-    if "surrogate" in forms:
-        result["forms"]["surrogate"] = form_surrogate(args, torch, fc)
+    result["stages"] = {}
+    for name in [w for w in args.secondary.split(",") if w and w != args.workload]:
+        n2, var2, _ = WORKLOADS[name]
+        c2 = synth.make_config(n2, variant=var2)
+        p2 = fc.upload(c2, device=dev)
+        entry, o2 = plain_workload(name, p2, c2, 2, args.secondary_steps, torch, fc)
+        result["workloads"][name] = entry
+        if name == "contrast":
+            if "split_bf16" in forms:
+                result["forms"]["split_bf16"][name] = form_split(name, p2, c2, o2, args.secondary_steps, torch, fc,
+                                                                 entry["walk"])
+            del o2
+            torch.cuda.empty_cache()
+            if args.spectral:
+                result["stages"]["spectral"] = spectral_stage(p2, c2, args, torch, fc)
+            if args.noise_counts > 0:
+                result["next"]["noise_and_projections"] = noise_stage(p2, c2, args, torch, fc)
+            if args.dose:
+                result["next"]["dose"] = dose_stage(p2, c2, args, torch, fc, entry["walk"]["hit_rays"])
+            if args.fdk:
+                result["next"]["fdk"] = fdk_stage(p2, c2, args, torch, fc)
+            if args.rl_iterations > 0:
+                result["next"]["optics"] = optics_stage(p2, c2, args, torch, fc)
+        del p2
+        torch.cuda.empty_cache()
 
     if args.ceilings:
         add_measured_ceilings(result)
     if args.cpu_angles > 0:
-        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_angles, ray_e / g.n_angles)
+        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_angles, head["rays"] * s.n_energy / g.n_angles)
+    if args.tiny_oracle:
+        result["cpu_tiny_single_thread"] = tiny_oracle()
 
     print(json.dumps(result))
 
@@ -575,6 +691,18 @@ def measured_ceiling(entry: dict, ceil: dict):
     if bound == "mfma" and unit == "TFLOP/s":
         return ceil["mfma_bf16_TFLOPs"]
     return None
+
+
+def _roofline_entries(node):
+    """Every roofline-like dict (one with bound, unit and achieved) under node."""
+    if isinstance(node, dict):
+        if {"bound", "unit", "achieved"} <= node.keys():
+            yield node
+        for v in node.values():
+            yield from _roofline_entries(v)
+    elif isinstance(node, list):
+        for v in node:
+            yield from _roofline_entries(v)
 
 
 def add_measured_ceilings(result: dict) -> None:
@@ -594,13 +722,7 @@ def add_measured_ceilings(result: dict) -> None:
         result["ceilings"] = {"error": str(e)[-300:]}
         return
     result["ceilings"] = ceil
-    entries = [result["roofline"], *result["kernels"].values()]
-    for group in ("forms", "next", "stages"):
-        for v in result.get(group, {}).values():
-            for key in ("roofline", "filter"):
-                if isinstance(v, dict) and isinstance(v.get(key), dict):
-                    entries.append(v[key])
-    for e in entries:
+    for e in list(_roofline_entries(result)):
         m = measured_ceiling(e, ceil)
         if m:
             e["measured_peak"] = round(m, 2)
@@ -608,7 +730,9 @@ def add_measured_ceilings(result: dict) -> None:
 
 
 def cpu_baseline(cfg, n_angles: int, ray_e_per_angle: float) -> dict:
-    """The FP64 oracle on an evenly spaced sample of the workload's angles."""
+    """The FP64 oracle on an evenly spaced sample of the workload's angles,
+    every thread of the host; its rate extrapolates linearly to all angles
+    (angles are independent and alike in cost)."""
     import oracle
     A = cfg.geometry.n_angles
     angles = np.unique(np.linspace(0, A - 1, n_angles).round().astype(int))
@@ -616,10 +740,30 @@ def cpu_baseline(cfg, n_angles: int, ray_e_per_angle: float) -> dict:
     t0 = time.perf_counter()
     oracle.project(cfg, angles, scatter_maps=S)
     dt = time.perf_counter() - t0
+    g = cfg.geometry
     return {"value": len(angles) * ray_e_per_angle / dt, "unit": "ray*E/s", "cores": oracle.max_threads(),
             "kind": "oracle", "seconds": round(dt, 2),
-            "sample": (f"{len(angles)} of {A} angles (evenly spaced), " if len(angles) < A else "all angles, ")
-                      + "full detector, all bins, scatter and PSF"}
+            "sample": (f"{len(angles)} of {A} angles (evenly spaced; linear extrapolation to all {A}: "
+                       f"{dt * A / len(angles):.0f} s)" if len(angles) < A else "all angles")
+                      + f", full {g.nu}x{g.nv} detector, all {cfg.spectral.n_energy} bins, scatter and PSF"}
+
+
+def tiny_oracle() -> dict:
+    """The FP64 oracle on the whole tiny case (45 angles of 128x16 rays, 32
+    bins) on one thread and on every thread."""
+    import oracle
+    import synth
+    cfg = synth.make_config(1)
+    ray_e = cfg.ray_energy
+    out = {"workload": "tiny phantom 64x64x16 @1 mm, 6 materials, 32 bins 20-120 keV, 128x16 detector, 45 angles",
+           "kind": "oracle", "unit": "ray*E/s"}
+    n_all = oracle.max_threads()
+    for key, nt in (("single_thread", 1), ("all_threads", n_all)):
+        t0 = time.perf_counter()
+        oracle.project(cfg, list(range(cfg.geometry.n_angles)), n_threads=nt)
+        dt = time.perf_counter() - t0
+        out[key] = {"seconds": round(dt, 4), "value": ray_e / dt, "cores": nt}
+    return out
 
 
 if __name__ == "__main__":

@@ -234,6 +234,27 @@ fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom
                              int32_t n_mat, int32_t a_begin, int32_t a_end, float *L, void *workspace,
                              size_t workspace_bytes, void *stream);
 
+/*
+ * Work the exact walk does for the rays of angles a_begin <= a < a_end, for
+ * cost models and roofline accounting (the projector's own walk, counting
+ * instead of charging lengths).  counts (DEVICE int64 [6], overwritten):
+ *   [0] rays that meet the grid,
+ *   [1] brick steps (uniform bricks cross in one step each),
+ *   [2] mixed bricks entered,
+ *   [3] voxel steps inside mixed bricks,
+ *   [4] lane slots of the voxel loop: its wavefront iterations times 64
+ *       (one lane follows one ray; a wavefront iterates until its slowest
+ *       lane is done, so [4] / [3] measures the divergence),
+ *   [5] voxel segments of Siddon's method: per ray that meets the grid,
+ *       1 + sum over axes of |i_exit - i_entry| (entry and exit voxels by
+ *       floor of the FP64 entry and exit points).
+ * Siddon's method (Sec. II.F's line integral through the labelled phantom)
+ * steps once per voxel segment, [5]; [1] + [3] is what this walk takes.
+ * Workspace: fcat_pathlengths_workspace_bytes(phantom) bytes.
+ */
+fcat_status fcat_walk_stats(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom, int32_t a_begin,
+                            int32_t a_end, int64_t *counts, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Workspace needed by fcat_spectral. */
 size_t fcat_spectral_workspace_bytes(const fcat_spectral_t *spectral);
 

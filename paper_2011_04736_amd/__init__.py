@@ -30,7 +30,7 @@ __all__ = [
     "FcatError", "MODES", "STAGES", "Geometry", "Phantom", "Spectral", "Scatter", "Psf", "Problem", "Noise",
     "Surrogate", "MlpTrain", "lib_path", "load", "upload", "project", "fcat_version", "fcat_status_string",
     "fcat_last_error", "fcat_project_workspace_bytes", "fcat_project", "fcat_project_status", "fcat_pathlengths_workspace_bytes",
-    "fcat_pathlengths", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_spectral_static", "fcat_psf", "fcat_check_inputs",
+    "fcat_pathlengths", "fcat_walk_stats", "WALK_COUNTS", "fcat_spectral_workspace_bytes", "fcat_spectral", "fcat_spectral_static", "fcat_psf", "fcat_check_inputs",
     "fcat_timing_enable", "fcat_timing_read", "fcat_count_scale", "fcat_poisson", "fcat_flood_workspace_bytes",
     "fcat_flood_profile", "fcat_log_projection", "fcat_projections_workspace_bytes", "fcat_projections",
     "fcat_dose_workspace_bytes", "fcat_dose", "fcat_fdk_filter", "fcat_fdk_backproject_workspace_bytes",
@@ -141,6 +141,8 @@ def load() -> C.CDLL:
     L.fcat_pathlengths_workspace_bytes.restype = sz
     L.fcat_pathlengths.argtypes = [gp, pp, C.c_int32, C.c_int32, C.c_int32, vp, vp, sz, vp]
     L.fcat_pathlengths.restype = st
+    L.fcat_walk_stats.argtypes = [gp, pp, C.c_int32, C.c_int32, vp, vp, sz, vp]
+    L.fcat_walk_stats.restype = st
     L.fcat_spectral_workspace_bytes.argtypes = [sp]
     L.fcat_spectral_workspace_bytes.restype = sz
     L.fcat_spectral.argtypes = [vp, C.c_int64, sp, vp, vp, vp, st, vp, vp, sz, vp]
@@ -652,6 +654,28 @@ def fcat_pathlengths(pb: Problem, n_mat: int, a_begin: int = 0, a_end: Optional[
     _check(load().fcat_pathlengths(C.byref(cg), C.byref(cp), int(n_mat), int(a_begin), int(a_end),
                                    _ptr(out), wp, wn, _stream(stream)))
     return out
+
+
+WALK_COUNTS = ("hit_rays", "brick_steps", "mixed_bricks", "voxel_steps", "voxel_lane_slots", "siddon_segments")
+
+
+@_entry
+def fcat_walk_stats(pb: Problem, a_begin: int = 0, a_end: Optional[int] = None, workspace=None,
+                    stream=None) -> dict:
+    """Step counts of the exact walk over angles a_begin <= a < a_end (synchronises)."""
+    g = pb.geometry
+    a_end = g.n_angles if a_end is None else a_end
+    cg, cp = g.c(), pb.phantom.c()
+    _ws(workspace)
+    torch = _require_gpu()
+    dev = pb.phantom.labels.device
+    counts = torch.empty(len(WALK_COUNTS), dtype=torch.int64, device=dev)
+    if workspace is None:
+        workspace = _workspace(fcat_pathlengths_workspace_bytes(pb.phantom), dev)
+    wp, wn = _ws(workspace)
+    _check(load().fcat_walk_stats(C.byref(cg), C.byref(cp), int(a_begin), int(a_end), _ptr(counts), wp, wn,
+                                  _stream(stream)))
+    return dict(zip(WALK_COUNTS, (int(x) for x in counts.cpu().tolist())))
 
 
 @_entry

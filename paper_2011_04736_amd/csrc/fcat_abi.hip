@@ -1328,6 +1328,32 @@ fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom
     return FCAT_OK;
 }
 
+fcat_status fcat_walk_stats(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom, int32_t a_begin,
+                            int32_t a_end, int64_t *counts, void *workspace, size_t workspace_bytes, void *stream_)
+{
+    g_last_error.clear();
+    fcat_status s;
+    if ((s = check_geometry(geometry)) || (s = check_phantom(phantom))) return s;
+    if (a_begin < 0 || a_end > geometry->n_angles || a_begin >= a_end)
+        return fail(FCAT_E_INVALID_ARG, "need 0 <= a_begin < a_end <= n_angles");
+    if (!counts) return fail(FCAT_E_INVALID_ARG, "counts is NULL");
+    if ((s = check_workspace(workspace, workspace_bytes, align_up(brick_bytes(phantom))))) return s;
+    if ((s = check_pending())) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    TraceGeom G = make_geom(geometry, phantom);
+    int8_t *bricks = static_cast<int8_t *>(workspace);
+    G.bricks = bricks;
+    G.labels_bm = bricks + align_up(brick_count(phantom));
+    hipError_t e = launch_zero_ints(reinterpret_cast<int *>(counts), 2 * kWalkCounts, stream);
+    if (e == hipSuccess)
+        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks,
+                                const_cast<int8_t *>(G.labels_bm), stream);
+    if (e == hipSuccess)
+        e = launch_walk_stats(G, a_begin, a_end - a_begin, reinterpret_cast<unsigned long long *>(counts), stream);
+    if (e != hipSuccess) return device_fail(e, "walk_stats");
+    return FCAT_OK;
+}
+
 size_t fcat_spectral_workspace_bytes(const fcat_spectral_t *spectral)
 {
     SpecTables t{};

@@ -249,6 +249,30 @@ __device__ __forceinline__ float crossings_before(float T, float t0, float dt, f
     return k;
 }
 
+// Step counters of the walk.  The projector uses NoCount (every call
+// compiles away); fcat_walk_stats uses StepCount to measure the work the walk
+// actually does: per lane, brick steps, mixed bricks entered and voxel steps
+// inside them, and per wavefront the iterations of the voxel loop (each one
+// issues for all 64 lanes, so their count times 64 is the lane slots the
+// voxel loop occupies).
+struct NoCount {
+    __device__ __forceinline__ void brick() {}
+    __device__ __forceinline__ void mixed() {}
+    __device__ __forceinline__ void voxel() {}
+};
+struct StepCount {
+    uint32_t bricks = 0, mixed_bricks = 0, voxels = 0, wave_voxel_iters = 0;
+    __device__ __forceinline__ void brick() { ++bricks; }
+    __device__ __forceinline__ void mixed() { ++mixed_bricks; }
+    __device__ __forceinline__ void voxel()
+    {
+        ++voxels;
+        // the lowest active lane counts the wavefront's iteration
+        const uint64_t active = __ballot(1);
+        if ((threadIdx.x & (kWave - 1)) == (unsigned)(__ffsll((unsigned long long)active) - 1)) ++wave_voxel_iters;
+    }
+};
+
 // Two-level exact walk (Siddon's path lengths, found hierarchically).
 //
 // The grid is tiled into B x B x B bricks; bricks[] holds the label of a
@@ -260,10 +284,11 @@ __device__ __forceinline__ float crossings_before(float T, float t0, float dt, f
 // a material only when the label changes, with compensated summation.
 //
 // acc_wave is this wavefront's MatAcc block in LDS; L receives the sums.
-template <int MP>
+template <int MP, typename Count = NoCount>
 __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const TraceGeom &G,
                                              const int8_t *__restrict__ labels_bm,
-                                             const int8_t *__restrict__ bricks, float *acc_wave, float (&L)[MP])
+                                             const int8_t *__restrict__ bricks, float *acc_wave, float (&L)[MP],
+                                             Count &&count = Count())
 {
     MatAcc<MP> acc(acc_wave, threadIdx.x & (kWave - 1));
     acc.clear();
@@ -291,6 +316,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
     int budget = G.nb[0] + G.nb[1] + G.nb[2] + 4;
     bool active = true;
     while (active) {
+        count.brick();
         const float tco = fminf(tc[0], fminf(tc[1], tc[2]));
         const bool last = !(tco < t_end) || --budget < 0;
         const float T_out = last ? t_end : tco;
@@ -301,6 +327,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                 run = T_in;
             }
         } else {
+            count.mixed();
             // fine walk over [T_in, T_out) inside brick `blin`, whose
             // kBrickVox labels are contiguous in the brick-major copy: resume the
             // voxel counters at T_in, then step plane by plane
@@ -348,6 +375,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             }
             for (int f = 0; f < 3 * kBrickEdge + 3; ++f) {
                 if (!(tn < T_out)) break;
+                count.voxel();
                 float tn2;
                 unsigned lab2;
                 advance(tn2, lab2);

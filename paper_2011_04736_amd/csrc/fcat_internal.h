@@ -174,6 +174,9 @@ hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int
 
 hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0,
                               int n_ang, float *L, hipStream_t stream);
+// Step counts of the walk (see fcat_walk_stats); counts must be zero first.
+constexpr int kWalkCounts = 6;
+hipError_t launch_walk_stats(const TraceGeom &g, int a0, int n_ang, unsigned long long *counts, hipStream_t stream);
 
 hipError_t launch_spectral(const float *L, int64_t n, const SpecTables &t, const float *i0,
                            const float *S, float *Y, hipStream_t stream);

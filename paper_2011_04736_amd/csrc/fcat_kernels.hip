@@ -80,6 +80,73 @@ __global__ __launch_bounds__(kBlock) void k_pathlengths(TraceGeom G, const int8_
         if (m < n_mat) dst[m] = L[m];
 }
 
+// Voxel segments of Siddon's method on the ray to pixel (iv, iu): one per
+// voxel between entry and exit, 1 + sum over axes of |i_exit - i_entry|, the
+// two voxels taken by floor of the FP64 entry and exit points (clamped to
+// the grid); 0 for a ray that misses.  The unit of work the walk is priced
+// against, counted here so that no host pass over every ray is needed.
+__device__ uint32_t siddon_segments(const TraceGeom &G, double ct, double st, int iv, int iu)
+{
+    const double pu = ((double)iu - G.cu) * G.du + G.off_u;
+    const double pv = ((double)iv - G.cv) * G.dv + G.off_v;
+    const double s[3] = {G.sid * ct, G.sid * st, 0.0};
+    const double p[3] = {-G.back * ct - pu * st, -G.back * st + pu * ct, pv};
+    double d[3], amin = 0.0, amax = 1.0;
+    bool inside = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        d[ax] = p[ax] - s[ax];
+        const double lo = G.lo[ax], hi = G.lo[ax] + G.n[ax] * G.h[ax];
+        if (d[ax] == 0.0) {
+            inside = inside && s[ax] >= lo && s[ax] < hi;
+        } else {
+            const double a0 = (lo - s[ax]) / d[ax], a1 = (hi - s[ax]) / d[ax];
+            amin = fmax(amin, fmin(a0, a1));
+            amax = fmin(amax, fmax(a0, a1));
+        }
+    }
+    if (!inside || !(amax > amin)) return 0;
+    uint32_t n = 1;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int i0 = min(max((int)floor((s[ax] + amin * d[ax] - G.lo[ax]) * G.inv_h[ax]), 0), G.n[ax] - 1);
+        const int i1 = min(max((int)floor((s[ax] + amax * d[ax] - G.lo[ax]) * G.inv_h[ax]), 0), G.n[ax] - 1);
+        n += (uint32_t)abs(i1 - i0);
+    }
+    return n;
+}
+
+// Step counts of the walk over angles [a0, a0 + n_ang): counts[0] rays that
+// meet the grid, [1] brick steps, [2] mixed bricks entered, [3] voxel steps,
+// [4] wavefront iterations of the voxel loop times 64 (lane slots), [5]
+// Siddon voxel segments.  Per-lane counts are summed over the wavefront with
+// shuffles, then one 64-bit atomic per wavefront and counter.
+template <int MP>
+__global__ __launch_bounds__(kBlock) void k_walk_stats(TraceGeom G, int a0, int n_ang, int nblk_pad,
+                                                       unsigned long long *__restrict__ counts)
+{
+    __shared__ float acc_all[(kBlock / kWave) * mat_acc_floats<MP>()];
+    const int blk = xcd_block(nblk_pad);
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gw = blk * (kBlock / kWave) + wave;
+    if (gw >= n_ang * tiles_per_angle(G)) return;
+    const PixelOf px = pixel_of(G, gw, lane);
+    double st, ct;
+    sincos(angle_of(G, a0 + px.al), &st, &ct);
+    float L[MP];
+    Ray r{};
+    const bool hit = px.valid && setup_ray(G, ct, st, px.iv, px.iu, r);
+    StepCount c;
+    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, acc_all + wave * mat_acc_floats<MP>(), L, c);
+    const uint32_t segs = px.valid ? siddon_segments(G, ct, st, px.iv, px.iu) : 0u;
+    unsigned long long v[kWalkCounts] = {hit ? 1ull : 0ull, hit ? (unsigned long long)c.bricks : 0ull,
+                                         c.mixed_bricks, c.voxels, 64ull * c.wave_voxel_iters, segs};
+#pragma unroll
+    for (int k = 0; k < kWalkCounts; ++k) {
+        for (int off = kWave / 2; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+        if (lane == 0 && v[k]) atomicAdd(counts + k, v[k]);
+    }
+}
+
 template <int MP>
 __global__ __launch_bounds__(kBlock) void k_spectral(const float *__restrict__ Lin, int64_t n, SpecTables T,
                                                      const float *__restrict__ i0,
@@ -546,6 +613,14 @@ hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_ma
     else
         hipLaunchKernelGGL(k_pathlengths<32>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
                            n_ang, nblk, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_stats(const TraceGeom &g, int a0, int n_ang, unsigned long long *counts, hipStream_t stream)
+{
+    const int64_t waves = (int64_t)n_ang * tiles_per_angle_host(g);
+    const int nblk = padded_blocks(waves);
+    hipLaunchKernelGGL(k_walk_stats<8>, dim3(nblk), dim3(kBlock), 0, stream, g, a0, n_ang, nblk, counts);
     return hipGetLastError();
 }
 
