@@ -70,6 +70,10 @@ fcat_status check_phantom(const fcat_phantom_t *p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FCAT_E_INVALID_ARG, "nx, ny, nz must be >= 1");
     if ((int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
         return fail(FCAT_E_INVALID_ARG, "phantom larger than 2^31 - 1 voxels");
+    const int64_t bricked = (int64_t)((p->nx + kBrickEdge - 1) / kBrickEdge) * ((p->ny + kBrickEdge - 1) / kBrickEdge) *
+                            ((p->nz + kBrickEdge - 1) / kBrickEdge) * kBrickVox;
+    if (bricked + 2 * (int64_t)kLabelPad >= ((int64_t)1 << 31))
+        return fail(FCAT_E_INVALID_ARG, "phantom rounded up to 16^3 bricks must hold fewer than 2^31 voxels");
     if (!finite_pos(p->dx_mm) || !finite_pos(p->dy_mm) || !finite_pos(p->dz_mm))
         return fail(FCAT_E_INVALID_ARG, "voxel sizes must be finite and > 0");
     if (!std::isfinite(p->cx_mm) || !std::isfinite(p->cy_mm) || !std::isfinite(p->cz_mm))
@@ -132,8 +136,13 @@ size_t brick_count(const fcat_phantom_t *p)
            ((p->nz + kBrickEdge - 1) / kBrickEdge);
 }
 
-// brick map + brick-major label copy
-size_t brick_bytes(const fcat_phantom_t *p) { return align_up(brick_count(p)) + brick_count(p) * kBrickVox; }
+// brick map + brick-major label copy with its padding
+size_t brick_bytes(const fcat_phantom_t *p)
+{
+    return align_up(brick_count(p)) + brick_count(p) * kBrickVox + 2 * (size_t)kLabelPad;
+}
+// brick 0 of the brick-major labels, in a workspace whose brick map starts at `bricks`
+int8_t *labels_bm_at(int8_t *bricks, const fcat_phantom_t *p) { return bricks + align_up(brick_count(p)) + kLabelPad; }
 
 }  // namespace
 
@@ -589,7 +598,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     if (sur && (s = prep_mlp(surrogate, surrogate->params, t, L, workspace, stream, mt))) return s;
     TraceGeom G = make_geom(geometry, phantom);
     G.bricks = at<int8_t>(workspace, L.bricks);
-    G.labels_bm = G.bricks + align_up(brick_count(phantom));
+    G.labels_bm = labels_bm_at(const_cast<int8_t *>(G.bricks), phantom);
     G.bad = bad;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
@@ -776,7 +785,7 @@ fcat_status fcat_dose(const fcat_geometry_t *geometry, const fcat_phantom_t *pha
     if ((s = prep_tables(spectral, nullptr, t, d.base, workspace, stream))) return s;
     TraceGeom G = make_geom(geometry, phantom);
     G.bricks = at<int8_t>(workspace, d.base.bricks);
-    G.labels_bm = G.bricks + align_up(brick_count(phantom));
+    G.labels_bm = labels_bm_at(const_cast<int8_t *>(G.bricks), phantom);
     double *S = at<double>(workspace, d.S);
     double *partial = at<double>(workspace, d.partial);
     float *L = at<float>(workspace, d.L);
@@ -1311,7 +1320,7 @@ fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     TraceGeom G = make_geom(geometry, phantom);
     int8_t *bricks = static_cast<int8_t *>(workspace);
-    int8_t *labels_bm = bricks + align_up(brick_count(phantom));
+    int8_t *labels_bm = labels_bm_at(bricks, phantom);
     G.bricks = bricks;
     G.labels_bm = labels_bm;
     hipError_t e;
@@ -1343,7 +1352,7 @@ fcat_status fcat_walk_stats(const fcat_geometry_t *geometry, const fcat_phantom_
     TraceGeom G = make_geom(geometry, phantom);
     int8_t *bricks = static_cast<int8_t *>(workspace);
     G.bricks = bricks;
-    G.labels_bm = bricks + align_up(brick_count(phantom));
+    G.labels_bm = labels_bm_at(bricks, phantom);
     hipError_t e = launch_zero_ints(reinterpret_cast<int *>(counts), 2 * kWalkCounts, stream);
     if (e == hipSuccess)
         e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks,

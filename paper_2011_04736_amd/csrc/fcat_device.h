@@ -273,6 +273,37 @@ struct StepCount {
     }
 };
 
+// Voxel-level stepping inside one mixed brick: the next crossing time and
+// the crossings taken per axis, and the voxel's offset in the brick.  Each
+// step moves to the nearest crossing (x if t0 is the nearest, else y if t1
+// is, else z), updates that axis's counter and recomputes all three
+// crossings as t0 + k dt with one rounding each.  It is written with scalar
+// members and selects of values only: an array indexed by a select, or a
+// select between captured variables, is turned by the compiler into a
+// select of addresses and a load from scratch memory.
+struct VoxelStepper {
+    float t0, t1, t2;
+    float k0, k1, k2;
+    int loc;
+    __device__ __forceinline__ float step(const Ray &r, int dl0, int dl1, int dl2)
+    {
+        const float tn = fminf(t0, fminf(t1, t2));
+        const bool cx = (t0 == tn);
+        const bool cy = (t1 == tn);
+        const bool ey = cy && !cx;            // exclusive: the axis that steps
+        const bool ez = !cx && !cy;
+        const int dyz = cy ? dl1 : dl2;
+        loc += cx ? dl0 : dyz;
+        k0 += cx ? 1.0f : 0.0f;
+        k1 += ey ? 1.0f : 0.0f;
+        k2 += ez ? 1.0f : 0.0f;
+        t0 = fmaf(k0, r.dt[0], r.t0[0]);      // parallel axis: 0 * 0 + inf
+        t1 = fmaf(k1, r.dt[1], r.t0[1]);
+        t2 = fmaf(k2, r.dt[2], r.t0[2]);
+        return tn;
+    }
+};
+
 // Two-level exact walk (Siddon's path lengths, found hierarchically).
 //
 // The grid is tiled into B x B x B bricks; bricks[] holds the label of a
@@ -298,6 +329,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
         return;
     }
     const float t_end = r.t_end;
+    const uint8_t *lbase = reinterpret_cast<const uint8_t *>(labels_bm) - kLabelPad;
     const int nbx = G.nb[0], nby = G.nb[1];
     const int last_brick = G.nb[0] * G.nb[1] * G.nb[2] - 1;
     const int lstride[3] = {1, kBrickEdge, kBrickEdge * kBrickEdge};
@@ -305,8 +337,10 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
 
     float kc[3] = {0.0f, 0.0f, 0.0f};
     float tc[3] = {r.tc0[0], r.tc0[1], r.tc0[2]};
-    const int db[3] = {r.sgn[0] * bstride[0], r.sgn[1] * bstride[1], r.sgn[2] * bstride[2]};
-    const int dl[3] = {r.sgn[0] * lstride[0], r.sgn[1] * lstride[1], r.sgn[2] * lstride[2]};
+    const int db0 = r.sgn[0] * bstride[0], db1 = r.sgn[1] * bstride[1], db2 = r.sgn[2] * bstride[2];
+    // voxel-index steps per axis, as separate values: an array indexed by a
+    // select would be kept in scratch memory
+    const int dl0 = r.sgn[0] * lstride[0], dl1 = r.sgn[1] * lstride[1], dl2 = r.sgn[2] * lstride[2];
     int bc[3] = {r.i0[0] / kBrickEdge, r.i0[1] / kBrickEdge, r.i0[2] / kBrickEdge};
     int blin = (bc[2] * nby + bc[1]) * nbx + bc[0];
     int bl = bricks[blin];
@@ -345,29 +379,15 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
                 t[a] = fmaf(k[a], r.dt[a], r.t0[a]);
                 loc += (ia - b0) * lstride[a];
             }
-            const uint8_t *brick =
-                reinterpret_cast<const uint8_t *>(labels_bm) + (int64_t)min(max(blin, 0), last_brick) * kBrickVox;
-            unsigned lab = brick[loc];
+            // offsets from the start of the padding: unsigned 32-bit, so each
+            // label load takes the wave-uniform base plus one vector offset
+            const uint32_t boff = kLabelPad + (uint32_t)min(max(blin, 0), last_brick) * kBrickVox;
+            VoxelStepper w{t[0], t[1], t[2], k[0], k[1], k[2], (int)(boff + loc)};
+            unsigned lab = lbase[boff + loc];
             // the walk runs one crossing ahead of the label comparison, so
             // each label load has a step's worth of work to arrive
-            auto advance = [&](float &tn, unsigned &labn) {
-                tn = fminf(t[0], fminf(t[1], t[2]));
-                const bool bx = (t[0] == tn);
-                const bool ty = (t[1] == tn);
-                const bool by = !bx && ty;
-                const bool bz = !bx && !ty;
-                loc += bx ? dl[0] : (ty ? dl[1] : dl[2]);
-                k[0] += bx ? 1.0f : 0.0f;
-                k[1] += by ? 1.0f : 0.0f;
-                k[2] += bz ? 1.0f : 0.0f;
-                t[0] = fmaf(k[0], r.dt[0], r.t0[0]);      // parallel axis: 0 * 0 + inf
-                t[1] = fmaf(k[1], r.dt[1], r.t0[1]);
-                t[2] = fmaf(k[2], r.dt[2], r.t0[2]);
-                labn = brick[min(max(loc, 0), kBrickVox - 1)];
-            };
-            float tn;
-            unsigned labn;
-            advance(tn, labn);
+            float tn = w.step(r, dl0, dl1, dl2);
+            unsigned labn = lbase[(uint32_t)w.loc];
             if (lab != cur) {
                 acc.add(cur, T_in - run);
                 cur = lab;
@@ -376,9 +396,8 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             for (int f = 0; f < 3 * kBrickEdge + 3; ++f) {
                 if (!(tn < T_out)) break;
                 count.voxel();
-                float tn2;
-                unsigned lab2;
-                advance(tn2, lab2);
+                const float tn2 = w.step(r, dl0, dl1, dl2);
+                const unsigned lab2 = lbase[(uint32_t)w.loc];
                 if (labn != cur) {
                     acc.add(cur, tn - run);
                     cur = labn;
@@ -395,7 +414,8 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             const bool ty = (tc[1] == tco);
             const bool by = !bx && ty;
             const bool bz = !bx && !ty;
-            blin += bx ? db[0] : (ty ? db[1] : db[2]);
+            const int dbyz = ty ? db1 : db2;
+            blin += bx ? db0 : dbyz;
             bc[0] += bx ? r.sgn[0] : 0;
             bc[1] += by ? r.sgn[1] : 0;
             bc[2] += bz ? r.sgn[2] : 0;

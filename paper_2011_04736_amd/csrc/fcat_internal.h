@@ -15,6 +15,14 @@ constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kXcds = 8;           // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kBrickEdge = 16;     // edge of the cubic label bricks of the two-level walk (8 and 32 measured slower)
 constexpr int kBrickVox = kBrickEdge * kBrickEdge * kBrickEdge;
+// Padding before and after the brick-major labels, filled with 0xFF (a label
+// that only ever reaches the spare accumulator slot).  Inside a brick the
+// voxel walk takes at most 3 kBrickEdge + 4 steps of at most kBrickEdge^2
+// bytes each, so a walk that rounding carries past the brick face reads
+// padding or a neighbouring brick, never outside the buffer: no clamp of
+// the offset is needed per step.
+constexpr uint32_t kLabelPad = 16384;
+static_assert(kLabelPad >= (3 * kBrickEdge + 4) * kBrickEdge * kBrickEdge, "label padding covers the walk");
 
 // Ray geometry of one launch, everything a lane needs to build its ray in
 // FP64.  lo/h/n describe the voxel grid; cu/cv are the detector centre
@@ -29,7 +37,8 @@ struct TraceGeom {
     const double *angles;          // device, or null for 2 pi a / A
     // Brick map of the labels: kBrickEdge^3 bricks, nb[] per axis; bricks[]
     // ([nb2][nb1][nb0]) holds the common label of a uniform brick or -1, and
-    // labels_bm[brick][z][y][x] is the brick-major copy of the labels.
+    // labels_bm[brick][z][y][x] is the brick-major copy of the labels, with
+    // kLabelPad bytes of padding before brick 0 and after the last brick.
     int nb[3];
     const int8_t *bricks;
     const int8_t *labels_bm;

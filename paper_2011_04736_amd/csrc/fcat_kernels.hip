@@ -536,6 +536,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__
     const bool mixed = __syncthreads_or(diff);
     if (bad && __syncthreads_or(out_of_range) && threadIdx.x == 0) atomicOr(bad, 1);
     if (threadIdx.x == 0) bricks[b] = mixed ? (int8_t)-1 : (int8_t)f;
+    // the first and the last workgroup fill the padding before and after the copy
+    if (b == 0)
+        for (uint32_t i = threadIdx.x; i < kLabelPad; i += kBuildThreads) labels_bm[(int64_t)i - kLabelPad] = (int8_t)-1;
+    if (b == (int)gridDim.x - 1)
+        for (uint32_t i = threadIdx.x; i < kLabelPad; i += kBuildThreads)
+            labels_bm[(int64_t)gridDim.x * kBrickVox + i] = (int8_t)-1;
 }
 
 int padded_blocks(int64_t waves)
