@@ -81,7 +81,9 @@ fcat_status check_phantom(const fcat_phantom_t *p)
     return FCAT_OK;
 }
 
-int padded_materials(int m) { return m <= 8 ? 8 : (m <= 12 ? 12 : (m <= 16 ? 16 : 32)); }
+// Material slots the kernels are compiled for: each spectral bin costs one
+// FMA per slot, so the common counts get a close fit (10: the head phantom).
+int padded_materials(int m) { return m <= 8 ? 8 : (m <= 10 ? 10 : (m <= 12 ? 12 : (m <= 16 ? 16 : 32))); }
 
 // Validates the spectral descriptor and fills the host part of the tables.
 fcat_status check_spectral(const fcat_spectral_t *s, bool need_tables, SpecTables &t)

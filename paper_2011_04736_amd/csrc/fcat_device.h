@@ -433,25 +433,27 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
     acc.read(L);
 }
 
-// exp(-P) for the spectral sum, by Cody and Waite's argument reduction
-// (W. J. Cody, W. Waite, Software Manual for the Elementary Functions, 1980):
-// n = rint(P log2 e), r = P - n ln 2 with ln 2 split in a 16-bit head (n times
-// the head is exact for n < 2^8, all n whose result is above the FP32
-// subnormals) and the FP32 rounding of the rest, then 2^-n exp(-r) with the
-// hardware base-2 exponential of -r log2 e (|r log2 e| <= 1/2 up to rounding)
-// and an exact scaling by 2^-n.  P is a non-negative optical depth; only n
-// is clamped (at 2^21, far beyond underflow): a larger P leaves a large r
-// whose exponential is 0 itself, and a NaN or +inf passes through r
-// unchanged (+inf gives 0).
+// exp(-P) for the spectral sum, as 2^-x with x = P log2(e) split into two
+// FP32 parts: x = fl(P log2e) and the rest c = P log2(e) - x, found exactly
+// by an FMA (the product's own rounding error) plus P times the tail of
+// log2(e) beyond FP32.  Then exp(-P) = 2^-x 2^-c = 2^-x (1 - c ln 2 + ...),
+// with |c ln 2| below 2^-25 |x|, so the dropped terms are below 1e-11
+// relative.  2^-x is the hardware base-2 exponential (v_exp_f32, accurate to
+// about one ulp over its whole range).  Six vector instructions.  P is a
+// non-negative optical depth; a result below the smallest normal FP32 number
+// (P > 87.3) may come out as 0, a NaN P gives NaN, and non-finite or
+// negative P below -88 (only from non-finite or negative inputs) is not
+// defined.
 __device__ __forceinline__ float exp_neg(float P)
 {
-    constexpr float kLog2e = 1.44269504088896341f;
-    constexpr float kLn2Hi = 0.693145751953125f;        // ln 2 rounded to 16 significant bits
-    constexpr float kLn2Lo = 1.428606765330187e-06f;    // ln 2 - kLn2Hi, rounded
-    const float n = rintf(fminf(P * kLog2e, 2097152.0f));
-    float r = fmaf(-n, kLn2Hi, P);
-    r = fmaf(-n, kLn2Lo, r);
-    return ldexpf(__builtin_amdgcn_exp2f(-r * kLog2e), (int)(-n));
+    constexpr float kLog2e = 1.44269502162933349609375f;   // log2(e) rounded to FP32
+    constexpr float kLog2eLo = 1.925963033500011e-08f;      // log2(e) - kLog2e, rounded
+    constexpr float kLn2 = 0.693147182464599609375f;
+    const float x = P * kLog2e;
+    float c = fmaf(P, kLog2e, -x);
+    c = fmaf(P, kLog2eLo, c);
+    const float y = __builtin_amdgcn_exp2f(-x);
+    return fmaf(-y * kLn2, c, y);
 }
 
 // sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3)
@@ -459,6 +461,9 @@ template <int MP>
 __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTables &T, int e0, int e1)
 {
     float acc = 0.0f;
+    // two bins per iteration: their table loads issue together and their
+    // chains of FMAs interleave
+#pragma unroll 2
     for (int e = e0; e < e1; ++e) {
         const float *mrow = T.muT + e * MP;
         float P = 0.0f;

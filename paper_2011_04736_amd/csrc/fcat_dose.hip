@@ -163,6 +163,10 @@ hipError_t launch_dose_rays(const float *L, int64_t n_rays, int M, const SpecTab
         hipLaunchKernelGGL(k_dose_rays<8>, dim3(nblk), dim3(kBlock), 0, stream, L, n_rays, M, t.muT, t.E, n_tiles,
                            partial);
         break;
+    case 10:
+        hipLaunchKernelGGL(k_dose_rays<10>, dim3(nblk), dim3(kBlock), 0, stream, L, n_rays, M, t.muT, t.E, n_tiles,
+                           partial);
+        break;
     case 12:
         hipLaunchKernelGGL(k_dose_rays<12>, dim3(nblk), dim3(kBlock), 0, stream, L, n_rays, M, t.muT, t.E, n_tiles,
                            partial);

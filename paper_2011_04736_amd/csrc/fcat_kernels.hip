@@ -574,6 +574,10 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
         hipLaunchKernelGGL(k_project_rows<8>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, t, flood,
                            scatter, a0, n_ang, nblk, Y, out);
         break;
+    case 10:
+        hipLaunchKernelGGL(k_project_rows<10>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, t, flood,
+                           scatter, a0, n_ang, nblk, Y, out);
+        break;
     case 12:
         hipLaunchKernelGGL(k_project_rows<12>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, t, flood,
                            scatter, a0, n_ang, nblk, Y, out);
@@ -610,6 +614,9 @@ hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_ma
     if (n_mat <= 8)
         hipLaunchKernelGGL(k_pathlengths<8>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
                            n_ang, nblk, L);
+    else if (n_mat <= 10)
+        hipLaunchKernelGGL(k_pathlengths<10>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
+                           n_ang, nblk, L);
     else if (n_mat <= 12)
         hipLaunchKernelGGL(k_pathlengths<12>, dim3(nblk), dim3(kBlock), 0, stream, g, labels, n_mat, a0,
                            n_ang, nblk, L);
@@ -637,6 +644,9 @@ hipError_t launch_spectral(const float *L, int64_t n, const SpecTables &t, const
     switch (t.mp) {
     case 8:
         hipLaunchKernelGGL(k_spectral<8>, dim3(nblk), dim3(kBlock), 0, stream, L, n, t, i0, S, Y);
+        break;
+    case 10:
+        hipLaunchKernelGGL(k_spectral<10>, dim3(nblk), dim3(kBlock), 0, stream, L, n, t, i0, S, Y);
         break;
     case 12:
         hipLaunchKernelGGL(k_spectral<12>, dim3(nblk), dim3(kBlock), 0, stream, L, n, t, i0, S, Y);

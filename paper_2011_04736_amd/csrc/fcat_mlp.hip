@@ -961,6 +961,8 @@ hipError_t launch_mlp_spectral(const SpecTables &t, const MlpTables &m, const Su
     const unsigned nblk = (unsigned)((io.n + kBlock - 1) / kBlock);
     if (t.mp == 8)
         hipLaunchKernelGGL(k_mlp_spectral<8>, dim3(nblk), dim3(kBlock), 0, stream, t, m, io);
+    else if (t.mp == 10)
+        hipLaunchKernelGGL(k_mlp_spectral<10>, dim3(nblk), dim3(kBlock), 0, stream, t, m, io);
     else if (t.mp == 12)
         hipLaunchKernelGGL(k_mlp_spectral<12>, dim3(nblk), dim3(kBlock), 0, stream, t, m, io);
     else if (t.mp == 16)

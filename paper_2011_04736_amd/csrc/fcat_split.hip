@@ -342,6 +342,7 @@ hipError_t launch_prep_split(const float *mu, const SpecTables &t, const SplitTa
 
 #define FCAT_SPLIT_DISPATCH(MACRO) \
     if (t.mp == 8 && sp.nkb == 1) MACRO(8, 1) \
+    else if (t.mp == 10 && sp.nkb == 1) MACRO(10, 1) \
     else if (t.mp == 12 && sp.nkb == 1) MACRO(12, 1) \
     else if (t.mp == 12 && sp.nkb == 2) MACRO(12, 2) \
     else if (t.mp == 16 && sp.nkb == 1) MACRO(16, 1) \
