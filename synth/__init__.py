@@ -20,6 +20,9 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
+import json
+import os
+
 import numpy as np
 
 __all__ = [
@@ -403,32 +406,53 @@ def random_phantom(rng: np.random.Generator, nx: int, ny: int, nz: int, n_mat: i
 
 
 # ------------------------------------------------------------- configurations
+#
+# Each configuration is described by a JSON file in synth/configs/ (geometry,
+# grid, seed, materials, energy bins, groups, optical-spread size, mode); the
+# recipe named in the file builds the phantom's structure and the seeded
+# tables.  make_config(n) loads the file of configuration n.
 
-def _config1(rng: np.random.Generator) -> Config:
-    names = ["air", "water", "compact_bone", "lung", "adipose", "brain"]
-    energies = 20.0 + np.arange(32) * (100.0 / 31.0)          # keV, bin centres
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+CONFIG_FILES = {(1, ""): "tiny.json", (2, ""): "contrast.json", (2, "z"): "contrast_dz.json",
+                (3, ""): "head.json", (4, ""): "contrast_split.json", (4, "z"): "contrast_dz.json",
+                (5, ""): "head_surrogate.json"}
+
+
+def _energies(p: dict) -> np.ndarray:
+    e = p["energy"]
+    return e["first"] + np.arange(e["bins"]) * (e["span"] / (e["bins"] - 1))
+
+
+def _geometry(p: dict) -> Geometry:
+    g = p["geometry"]
+    return Geometry(sid=g["sid_mm"], sdd=g["sdd_mm"], nu=g["nu"], nv=g["nv"], du=g["du_mm"], dv=g["dv_mm"],
+                    n_angles=g["n_angles"])
+
+
+def _config1(rng: np.random.Generator, p: dict) -> Config:
+    names, grid = p["materials"], p["grid"]
+    energies = _energies(p)                                    # keV, bin centres
     phi = kramers_spectrum(rng, energies, 120.0, 30.0, (0.3, 0.6))
     eta = detector_response(rng, energies, 30.0)
     # water cylinder of 50 mm diameter (25 mm radius) so that air surrounds it
     ring = 12.0
     inserts = [(ring, 0.0, 2.0, 2), (0.0, ring, 3.0, 3), (-ring, 0.0, 4.0, 4), (0.0, -ring, 5.0, 5)]
-    labels = cylinder_phantom(64, 64, 16, 1.0, 1.0, 25.0, inserts)
+    labels = cylinder_phantom(grid["nx"], grid["ny"], grid["nz"], grid["dx_mm"], grid["dz_mm"], 25.0, inserts)
     mu = material_tables(rng, names, energies, 30.0, (0.015, 0.015, 0.0075),
                          phi.astype(np.float64) * eta, 50.0, 3.0)
-    spec = Spectral(energies=energies, mu=mu, phi=phi, eta=eta, n_groups=1,
-                    group_of_bin=contiguous_groups(32, 1), energy_unit="keV",
+    spec = Spectral(energies=energies, mu=mu, phi=phi, eta=eta, n_groups=p["groups"],
+                    group_of_bin=contiguous_groups(len(energies), p["groups"]), energy_unit=p["energy"]["unit"],
                     material_names=names)
-    geom = Geometry(sid=1000.0, sdd=1500.0, nu=128, nv=16, du=1.0, dv=1.0, n_angles=45)
-    ph = Phantom(dx=1.0, dy=1.0, dz=1.0, labels=labels)
-    return Config("tiny", geom, ph, spec, None, None)
+    ph = Phantom(dx=grid["dx_mm"], dy=grid["dy_mm"], dz=grid["dz_mm"], labels=labels)
+    return Config(p["name"], _geometry(p), ph, spec, None, None)
 
 
-def _config2(rng: np.random.Generator, dz: float = 0.15625) -> Config:
-    names = ["air", "water", "lung", "compact_bone", "cortical_bone", "adipose", "brain", "b100"]
-    energies = 0.01 + np.arange(200) * (5.99 / 199.0)          # MeV, bin centres
+def _config2(rng: np.random.Generator, p: dict) -> Config:
+    names, grid, g = p["materials"], p["grid"], p["geometry"]
+    energies = _energies(p)                                    # MeV, bin centres
     phi = kramers_spectrum(rng, energies, 6.0, 1.0, (0.01, 0.03))
     eta = detector_response(rng, energies, 1.0)
-    h = 0.15625
+    h = grid["dx_mm"]
     inserts = []
     diam = [1.0, 2.0, 3.0, 4.0, 5.0]
     radii = [30.0, 37.5, 45.0, 52.5, 60.0]
@@ -437,23 +461,21 @@ def _config2(rng: np.random.Generator, dz: float = 0.15625) -> Config:
             ang = np.deg2rad(60.0 * t + 12.0 * k + 6.0 + rng.uniform(-3.0, 3.0))
             r = radii[k] + rng.uniform(-2.0, 2.0)
             inserts.append((r * np.cos(ang), r * np.sin(ang), diam[k] / 2.0, 2 + t))
-    labels = cylinder_phantom(1024, 1024, 10, h, dz, 80.0, inserts)
+    labels = cylinder_phantom(grid["nx"], grid["ny"], grid["nz"], h, grid["dz_mm"], 80.0, inserts)
     mu = material_tables(rng, names, energies, 1.0, (5.0e-6, 0.05, 0.02),
                          phi.astype(np.float64) * eta, 160.0, 1.0)
-    spec = Spectral(energies=energies, mu=mu, phi=phi, eta=eta, n_groups=8,
-                    group_of_bin=contiguous_groups(200, 8), energy_unit="MeV",
+    spec = Spectral(energies=energies, mu=mu, phi=phi, eta=eta, n_groups=p["groups"],
+                    group_of_bin=contiguous_groups(len(energies), p["groups"]), energy_unit=p["energy"]["unit"],
                     material_names=names)
-    geom = Geometry(sid=1000.0, sdd=1520.0, nu=1024, nv=64, du=0.392, dv=0.392, n_angles=360)
-    ph = Phantom(dx=h, dy=h, dz=dz, labels=labels)
-    sc = scatter_blobs(rng, 360, 1024, 64, (200.0, 300.0), (30.0, 60.0))
-    psf = Psf(gaussian_psfs(rng, 8, 15))
-    return Config("contrast" if dz == 0.15625 else "contrast_z", geom, ph, spec, sc, psf)
+    ph = Phantom(dx=h, dy=grid["dy_mm"], dz=grid["dz_mm"], labels=labels)
+    sc = scatter_blobs(rng, g["n_angles"], g["nu"], g["nv"], (200.0, 300.0), (30.0, 60.0)) if p["scatter"] else None
+    psf = Psf(gaussian_psfs(rng, p["groups"], p["psf_k"])) if p["psf_k"] else None
+    return Config(p["name"], _geometry(p), ph, spec, sc, psf)
 
 
-def _config3(rng: np.random.Generator) -> Config:
-    names = ["air", "skin", "adipose", "muscle", "cortical_bone", "cancellous_bone",
-             "grey_matter", "white_matter", "csf", "blood"]
-    energies = np.arange(1, 121, dtype=np.float64)              # keV, 1-keV bins
+def _config3(rng: np.random.Generator, p: dict) -> Config:
+    names, grid, g = p["materials"], p["grid"], p["geometry"]
+    energies = _energies(p)                                    # keV, 1-keV bins
     phi = kramers_spectrum(rng, energies, 120.0, 30.0, (0.3, 0.6))
     eta = detector_response(rng, energies, 30.0)
     j = lambda s: 1.0 + s * rng.uniform(-1.0, 1.0)
@@ -477,17 +499,32 @@ def _config3(rng: np.random.Generator) -> Config:
     bodies.append(((0.0, 0.0, cz0 + 48.0), (3.0, 70.0, 3.0), 9))        # sagittal-sinus-like tube
     for sgn in (-1.0, 1.0):     # air sinuses
         bodies.append(((sgn * 14.0, 78.0 * j(0.03), cz0 - 22.0), (9.0, 7.0, 8.0), 0))
-    labels = ellipsoid_phantom(512, 512, 256, 0.5, bodies)
+    labels = ellipsoid_phantom(grid["nx"], grid["ny"], grid["nz"], grid["dx_mm"], bodies)
     mu = material_tables(rng, names, energies, 30.0, (0.015, 0.015, 0.0075),
                          phi.astype(np.float64) * eta, 2.0 * a, 3.0)
-    spec = Spectral(energies=energies, mu=mu, phi=phi, eta=eta, n_groups=8,
-                    group_of_bin=contiguous_groups(120, 8), energy_unit="keV",
+    spec = Spectral(energies=energies, mu=mu, phi=phi, eta=eta, n_groups=p["groups"],
+                    group_of_bin=contiguous_groups(len(energies), p["groups"]), energy_unit=p["energy"]["unit"],
                     material_names=names)
-    geom = Geometry(sid=1000.0, sdd=1520.0, nu=1024, nv=768, du=0.4, dv=0.4, n_angles=720)
-    ph = Phantom(dx=0.5, dy=0.5, dz=0.5, labels=labels)
-    sc = scatter_blobs(rng, 720, 1024, 768, (200.0, 300.0), (360.0, 720.0))
-    psf = Psf(gaussian_psfs(rng, 8, 15))
-    return Config("head", geom, ph, spec, sc, psf)
+    ph = Phantom(dx=grid["dx_mm"], dy=grid["dy_mm"], dz=grid["dz_mm"], labels=labels)
+    sc = scatter_blobs(rng, g["n_angles"], g["nu"], g["nv"], (200.0, 300.0), (360.0, 720.0)) if p["scatter"] else None
+    psf = Psf(gaussian_psfs(rng, p["groups"], p["psf_k"])) if p["psf_k"] else None
+    return Config(p["name"], _geometry(p), ph, spec, sc, psf)
+
+
+RECIPES = {"tiny": _config1, "contrast": _config2, "head": _config3}
+
+
+def load_config(source) -> Config:
+    """A configuration from a JSON file (path) or its parsed dict: the recipe
+    builds the phantom and the seeded tables with the file's geometry, grid,
+    seed, materials, energy bins, groups and optical-spread size; ``mode``
+    names the projector form it is meant for."""
+    p = source if isinstance(source, dict) else json.load(open(source))
+    if p.get("recipe") not in RECIPES:
+        raise ValueError(f"unknown recipe {p.get('recipe')!r}; known: {sorted(RECIPES)}")
+    cfg = RECIPES[p["recipe"]](np.random.default_rng(int(p["seed"])), p)
+    cfg.mode = p.get("mode", "plain")
+    return cfg
 
 
 def make_config(n: int, variant: str = "") -> Config:
@@ -496,20 +533,10 @@ def make_config(n: int, variant: str = "") -> Config:
     ``variant="z"`` with n in (2, 4) gives the thick-slab contrast phantom
     (dz = 1.5625 mm, the ten slices fill the 64-row cone).
     """
-    base = {4: 2, 5: 3}.get(n, n)
-    rng = np.random.default_rng(config_seed(base))
-    if base == 1:
-        cfg = _config1(rng)
-    elif base == 2:
-        cfg = _config2(rng, dz=1.5625 if variant == "z" else 0.15625)
-    elif base == 3:
-        cfg = _config3(rng)
-    else:
-        raise ValueError(f"no configuration {n}")
-    if n == 4:
+    key = (int(n), variant)
+    if key not in CONFIG_FILES:
+        raise ValueError(f"no configuration {n}{' variant ' + variant if variant else ''}")
+    cfg = load_config(os.path.join(CONFIG_DIR, CONFIG_FILES[key]))
+    if key == (4, "z"):
         cfg.mode = "split_bf16"
-        cfg.name += "_split"
-    elif n == 5:
-        cfg.mode = "surrogate"
-        cfg.name += "_surrogate"
     return cfg

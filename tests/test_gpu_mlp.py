@@ -181,6 +181,31 @@ def test_training_and_surrogate_projector(fc):
     assert counts[0] > 0 and err.max() <= 1e-3
 
 
+def test_benchmarked_network_against_the_oracle(fc):
+    """The network the benchmark reports (head workload, 4M pairs with 10%
+    held out, 120 epochs, the build_surrogate defaults) projects within 1e-3
+    of the FP64 oracle on sampled angles, with the network taking most of the
+    hit rays."""
+    import torch
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(5)
+    pb = fc.upload(cfg)
+    sur, rep = sg.build_surrogate(pb, n_samples=4_000_000, epochs=120)
+    assert rep.n_train + rep.n_holdout == 4_000_000 and rep.epochs == 120
+    sur.counts = torch.zeros(2, dtype=torch.int32, device="cuda")
+    out = fc.fcat_project(pb, mode="surrogate", surrogate=sur)
+    sample = [0, 251, 611]
+    o = out[sample].cpu().numpy()
+    counts = sur.counts.cpu().numpy()
+    del out, pb
+    torch.cuda.empty_cache()
+    err = rel_err(o, oracle.project(cfg, sample))
+    share = counts[0] / max(counts[0] + counts[1], 1)
+    print(f"benchmarked network: max rel err {err.max():.2e}, rms {np.sqrt((err ** 2).mean()):.2e}; "
+          f"network share of hit rays {share:.3f}")
+    assert err.max() <= 1e-3 and share > 0.5
+
+
 def test_training_resumes_from_a_checkpoint(fc, tmp_path):
     """Two epochs, a checkpoint, then a resumed call for the other two give
     the same weights, Adam state and loss history as four epochs in one go."""
