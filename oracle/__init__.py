@@ -19,6 +19,10 @@ Functions and the passages they follow:
 * ``psf`` -- Sec. II.G: convolution of each group's profile with its optical
   spread kernel (Eq. 1 normalisation), then the sum over groups.
 * ``project`` -- all of the above for a list of angles.
+* ``forward_image`` / ``backproject_image`` -- the projector of a real-valued
+  voxel image (the Sec. II.F line integral over an image, as an iterative
+  reconstruction of Sec. II.G needs it) and its transpose, from the same
+  Siddon segments: (A f)_r = sum_k l_rk f_k and (A^T y)_k = sum_r l_rk y_r.
 """
 from __future__ import annotations
 
@@ -53,6 +57,12 @@ class _Volume(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double),
                 ("labels", C.POINTER(C.c_int8))]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("cz", C.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -94,6 +104,9 @@ def lib() -> C.CDLL:
             L.orc_project.argtypes = [gp, vp, C.c_int, C.c_int, C.c_int, dp, dp, dp, i32p,
                                       dp, dp, dp, dp, C.c_int, i32p, C.c_int, dp, dp, C.c_int]
             L.orc_max_threads.argtypes = []
+            grp = C.POINTER(_Grid)
+            L.orc_forward_image.argtypes = [gp, grp, dp, i32p, C.c_int, dp, C.c_int]
+            L.orc_backproject_image.argtypes = [gp, grp, dp, i32p, C.c_int, dp, C.c_int]
             _lib = L
     return _lib
 
@@ -273,3 +286,36 @@ def project(cfg, angle_idx: Sequence[int], with_groups: bool = False, scatter: b
                            ai.ctypes.data_as(C.POINTER(C.c_int32)), n_ang, _dptr(out), _dptr(Y), n_threads)
     _check(rc, "project")
     return (out, Y) if with_groups else out
+
+
+# ------------------------------------------------------- image projector pair
+
+def _cgrid(grid) -> _Grid:
+    return _Grid(int(grid.nx), int(grid.ny), int(grid.nz), float(grid.dx), float(grid.dy), float(grid.dz),
+                 float(getattr(grid, "cx", 0.0)), float(getattr(grid, "cy", 0.0)), float(getattr(grid, "cz", 0.0)))
+
+
+def forward_image(geometry, grid, image, angle_idx: Sequence[int], n_threads: int = 0) -> np.ndarray:
+    """(A f)[n_ang][nv][nu]: line integrals of image [nz][ny][nx] over the grid."""
+    keep = _Keep()
+    g, gr = _geom(geometry, keep), _cgrid(grid)
+    f = _f64(image)
+    assert f.shape == (grid.nz, grid.ny, grid.nx)
+    ai = np.ascontiguousarray(np.asarray(angle_idx, dtype=np.int32).reshape(-1))
+    out = np.zeros((ai.size, geometry.nv, geometry.nu), np.float64)
+    _check(lib().orc_forward_image(C.byref(g), C.byref(gr), _dptr(f), ai.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   ai.size, _dptr(out), n_threads), "forward_image")
+    return out
+
+
+def backproject_image(geometry, grid, proj, angle_idx: Sequence[int], n_threads: int = 0) -> np.ndarray:
+    """(A^T y)[nz][ny][nx] for y = proj [n_ang][nv][nu] of the listed angles."""
+    keep = _Keep()
+    g, gr = _geom(geometry, keep), _cgrid(grid)
+    y = _f64(proj)
+    ai = np.ascontiguousarray(np.asarray(angle_idx, dtype=np.int32).reshape(-1))
+    assert y.shape == (ai.size, geometry.nv, geometry.nu)
+    img = np.zeros((grid.nz, grid.ny, grid.nx), np.float64)
+    _check(lib().orc_backproject_image(C.byref(g), C.byref(gr), _dptr(y), ai.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       ai.size, _dptr(img), n_threads), "backproject_image")
+    return img

@@ -426,3 +426,158 @@ int orc_project(const orc_geometry *g, const orc_volume *v, int n_mat, int n_ene
     if (!Y_out) free(Y);
     return rc;
 }
+
+/* ------------------------------------------ projector of a voxel image, Aᵀ */
+/*
+ * The projector of a real-valued voxel image f (the line integral of Sec.
+ * II.F over an image instead of a labelled phantom, as an iterative
+ * reconstruction uses it, Sec. II.G) and its transpose:
+ *   (A f)_r     = sum over the voxels k the ray r crosses of l_{r,k} f_k,
+ *   (A^T y)_k   = sum over the rays r of l_{r,k} y_r,
+ * with l_{r,k} the length of ray r inside voxel k from Siddon's merged
+ * parametric plane crossings (as siddon_work above).  The grid follows the
+ * phantom's conventions; f and the result of A^T are [nz][ny][nx].
+ */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+    double cx, cy, cz;
+} orc_grid;
+
+typedef void (*orc_visit_fn)(void *ctx, int64_t voxel, double length);
+
+/* Calls visit(ctx, voxel, length) for each voxel segment of src->dst, in order. */
+static void siddon_visit(const double src[3], const double dst[3], const orc_grid *gr, double *work,
+                         orc_visit_fn visit, void *ctx)
+{
+    box_t b;
+    b.n[0] = gr->nx; b.n[1] = gr->ny; b.n[2] = gr->nz;
+    b.h[0] = gr->dx; b.h[1] = gr->dy; b.h[2] = gr->dz;
+    b.lo[0] = gr->cx - 0.5 * gr->nx * gr->dx;
+    b.lo[1] = gr->cy - 0.5 * gr->ny * gr->dy;
+    b.lo[2] = gr->cz - 0.5 * gr->nz * gr->dz;
+    double d[3] = {dst[0] - src[0], dst[1] - src[1], dst[2] - src[2]};
+    double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double amin = 0.0, amax = 1.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        double lo = b.lo[ax], hi = b.lo[ax] + b.n[ax] * b.h[ax];
+        if (d[ax] == 0.0) {
+            if (!(src[ax] >= lo && src[ax] < hi)) return;
+            continue;
+        }
+        double a0 = (lo - src[ax]) / d[ax], a1 = (hi - src[ax]) / d[ax];
+        double amn = a0 < a1 ? a0 : a1, amx = a0 < a1 ? a1 : a0;
+        if (amn > amin) amin = amn;
+        if (amx < amax) amax = amx;
+    }
+    if (!(amax > amin)) return;
+    int cap = b.n[0] + b.n[1] + b.n[2] + 5;
+    double *lists = work, *merged = work + cap;
+    int cnt[3], off[3], o = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        off[ax] = o;
+        cnt[ax] = axis_alphas(&b, ax, src, d, amin, amax, lists + o);
+        o += cnt[ax];
+    }
+    int k = 0, p[3] = {0, 0, 0};
+    merged[k++] = amin;
+    for (;;) {
+        int best = -1;
+        double bv = 0.0;
+        for (int ax = 0; ax < 3; ++ax)
+            if (p[ax] < cnt[ax]) {
+                double a = lists[off[ax] + p[ax]];
+                if (best < 0 || a < bv) { best = ax; bv = a; }
+            }
+        if (best < 0) break;
+        merged[k++] = bv;
+        p[best]++;
+    }
+    merged[k++] = amax;
+    for (int i = 0; i + 1 < k; ++i) {
+        double a0 = merged[i], a1 = merged[i + 1];
+        if (!(a1 > a0)) continue;
+        double am = 0.5 * (a0 + a1);
+        int ix = clampi((int)floor((src[0] + am * d[0] - b.lo[0]) / b.h[0]), b.n[0]);
+        int iy = clampi((int)floor((src[1] + am * d[1] - b.lo[1]) / b.h[1]), b.n[1]);
+        int iz = clampi((int)floor((src[2] + am * d[2] - b.lo[2]) / b.h[2]), b.n[2]);
+        visit(ctx, ((int64_t)iz * b.n[1] + iy) * b.n[0] + ix, (a1 - a0) * len);
+    }
+}
+
+typedef struct { const double *f; double sum; } fwd_ctx;
+static void fwd_visit(void *c, int64_t voxel, double length)
+{
+    fwd_ctx *x = (fwd_ctx *)c;
+    x->sum += length * x->f[voxel];
+}
+
+typedef struct { double *img; double y; } bp_ctx;
+static void bp_visit(void *c, int64_t voxel, double length)
+{
+    bp_ctx *x = (bp_ctx *)c;
+    double v = x->y * length;
+#pragma omp atomic
+    x->img[voxel] += v;
+}
+
+/* proj[n_ang][nv][nu] = (A f) over every pixel of the listed angles. */
+int orc_forward_image(const orc_geometry *g, const orc_grid *gr, const double *f, const int32_t *angle_idx,
+                      int n_ang, double *proj, int n_threads)
+{
+    set_threads(n_threads);
+    int rc = ORC_OK;
+    size_t cap = (size_t)(gr->nx + gr->ny + gr->nz + 5);
+    int64_t plane = (int64_t)g->nu * g->nv, n = (int64_t)n_ang * plane;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(2 * cap * sizeof(double));
+        if (!work) {
+#pragma omp critical
+            rc = ORC_NOMEM;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n; ++r) {
+            if (!work) continue;
+            int a = angle_idx[r / plane];
+            int iv = (int)((r % plane) / g->nu), iu = (int)(r % g->nu);
+            double s[3], p[3];
+            orc_ray_endpoints(g, a, iv, iu, s, p);
+            fwd_ctx c = {f, 0.0};
+            siddon_visit(s, p, gr, work, fwd_visit, &c);
+            proj[r] = c.sum;
+        }
+        free(work);
+    }
+    return rc;
+}
+
+/* img[nz][ny][nx] += (A^T y) over every pixel of the listed angles (y [n_ang][nv][nu]). */
+int orc_backproject_image(const orc_geometry *g, const orc_grid *gr, const double *y, const int32_t *angle_idx,
+                          int n_ang, double *img, int n_threads)
+{
+    set_threads(n_threads);
+    int rc = ORC_OK;
+    size_t cap = (size_t)(gr->nx + gr->ny + gr->nz + 5);
+    int64_t plane = (int64_t)g->nu * g->nv, n = (int64_t)n_ang * plane;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(2 * cap * sizeof(double));
+        if (!work) {
+#pragma omp critical
+            rc = ORC_NOMEM;
+        }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n; ++r) {
+            if (!work || y[r] == 0.0) continue;
+            int a = angle_idx[r / plane];
+            int iv = (int)((r % plane) / g->nu), iu = (int)(r % g->nu);
+            double s[3], p[3];
+            orc_ray_endpoints(g, a, iv, iu, s, p);
+            bp_ctx c = {img, y[r]};
+            siddon_visit(s, p, gr, work, bp_visit, &c);
+        }
+        free(work);
+    }
+    return rc;
+}
