@@ -480,6 +480,28 @@ size_t fcat_fdk_workspace_bytes(const fcat_geometry_t *geometry, int32_t angles_
 fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const fcat_grid_t *grid, float *volume,
                      void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * The projector of a real-valued voxel image and its transpose, the pair an
+ * iterative reconstruction alternates (Sec. II.F: a projection is the line
+ * integral along the source-to-pixel ray; Sec. II.G: the projections are
+ * reconstructed).  For the rays r of angles a_begin <= a < a_end (pixel
+ * centres and angles as above) and the voxels k of grid (the phantom's
+ * conventions: half-open boxes, image [nz][ny][nx], x fastest):
+ *   fcat_image_project:     proj[r] = sum_k l_rk image[k]       (A f)
+ *   fcat_image_backproject: image[k] = (accumulate ? image[k] : 0)
+ *                                      + sum_r l_rk proj[r]     (A^T y)
+ * with l_rk the exact length of ray r inside voxel k (Siddon's method, FP64
+ * ray set-up, FP32 plane stepping as in fcat_project), so the two are each
+ * other's transpose up to FP32 rounding.  proj is DEVICE float [a_end -
+ * a_begin][nv][nu], image DEVICE float [nz][ny][nx].  The back-projection
+ * adds with floating-point atomics: its sums are not in a fixed order
+ * (results may differ in the last bits between calls).  No workspace.
+ */
+fcat_status fcat_image_project(const fcat_geometry_t *geometry, const fcat_grid_t *grid, const float *image,
+                               int32_t a_begin, int32_t a_end, float *proj, void *stream);
+fcat_status fcat_image_backproject(const fcat_geometry_t *geometry, const fcat_grid_t *grid, const float *proj,
+                                   int32_t a_begin, int32_t a_end, float *image, int32_t accumulate, void *stream);
+
 /* ---------------------------------------------------------- detector optics */
 /*
  * Sec. II.B: the energy-dependent optical spread kernels, weighted by the

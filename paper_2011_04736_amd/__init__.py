@@ -34,7 +34,7 @@ __all__ = [
     "fcat_timing_enable", "fcat_timing_read", "fcat_count_scale", "fcat_poisson", "fcat_flood_workspace_bytes",
     "fcat_flood_profile", "fcat_log_projection", "fcat_projections_workspace_bytes", "fcat_projections",
     "fcat_dose_workspace_bytes", "fcat_dose", "fcat_fdk_filter", "fcat_fdk_backproject_workspace_bytes",
-    "fcat_fdk_backproject", "fcat_fdk_workspace_bytes", "fcat_fdk", "fcat_effective_psf",
+    "fcat_fdk_backproject", "fcat_fdk_workspace_bytes", "fcat_fdk", "fcat_image_project", "fcat_image_backproject", "fcat_effective_psf",
     "fcat_slit_lsf_range", "fcat_slit_mtf", "fcat_richardson_lucy_workspace_bytes",
     "fcat_slit_mtf_workspace_bytes", "fcat_richardson_lucy", "fcat_mlp_param_count",
     "fcat_mlp_workspace_bytes", "fcat_mlp_linear_term", "fcat_mlp_forward", "fcat_mlp_gradients",
@@ -203,6 +203,10 @@ def load() -> C.CDLL:
     L.fcat_fdk_workspace_bytes.restype = sz
     L.fcat_fdk.argtypes = [gp, vp, grp, vp, vp, sz, vp]
     L.fcat_fdk.restype = st
+    L.fcat_image_project.argtypes = [gp, grp, vp, C.c_int32, C.c_int32, vp, vp]
+    L.fcat_image_project.restype = st
+    L.fcat_image_backproject.argtypes = [gp, grp, vp, C.c_int32, C.c_int32, vp, C.c_int32, vp]
+    L.fcat_image_backproject.restype = st
     L.fcat_effective_psf.argtypes = [sp, psp, vp, vp]
     L.fcat_effective_psf.restype = st
     L.fcat_slit_lsf_range.argtypes = [C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32,
@@ -1008,6 +1012,44 @@ def fcat_fdk(geometry: Geometry, proj, grid, volume=None, workspace=None, angles
     wp, wn = _ws(workspace)
     _check(load().fcat_fdk(C.byref(cg), pp, C.byref(cv), _ptr(volume), wp, wn, _stream(stream)))
     return volume
+
+
+# ------------------------------------------------------- image projector pair
+
+@_entry
+def fcat_image_project(geometry: Geometry, grid, image, a_begin: int = 0, a_end: Optional[int] = None, out=None,
+                       stream=None):
+    """(A f)[a][v][u]: line integrals of image [nz][ny][nx] for angles a_begin <= a < a_end."""
+    a_end = geometry.n_angles if a_end is None else a_end
+    cg, cv = geometry.c(), _cgrid(grid)
+    f32 = _torch().float32
+    pi = _arg(image, "image", f32, (grid.nz, grid.ny, grid.nx))
+    if out is not None:
+        _arg(out, "out", f32, (a_end - a_begin, geometry.nv, geometry.nu))
+    torch = _require_gpu()
+    if out is None:
+        out = torch.empty((a_end - a_begin, geometry.nv, geometry.nu), dtype=torch.float32, device=image.device)
+    _check(load().fcat_image_project(C.byref(cg), C.byref(cv), pi, int(a_begin), int(a_end), _ptr(out),
+                                     _stream(stream)))
+    return out
+
+
+@_entry
+def fcat_image_backproject(geometry: Geometry, grid, proj, a_begin: int = 0, image=None, accumulate: bool = False,
+                           stream=None):
+    """(A^T y)[nz][ny][nx] for y = proj [n][nv][nu] of angles a_begin .. a_begin + n - 1."""
+    cg, cv = geometry.c(), _cgrid(grid)
+    f32 = _torch().float32
+    pp = _arg(proj, "proj", f32, (None, geometry.nv, geometry.nu))
+    n = int(proj.shape[0])
+    if image is not None:
+        _arg(image, "image", f32, (grid.nz, grid.ny, grid.nx))
+    torch = _require_gpu()
+    if image is None:
+        image = torch.empty((grid.nz, grid.ny, grid.nx), dtype=torch.float32, device=proj.device)
+    _check(load().fcat_image_backproject(C.byref(cg), C.byref(cv), pp, int(a_begin), int(a_begin) + n,
+                                         _ptr(image), 1 if accumulate else 0, _stream(stream)))
+    return image
 
 
 # ------------------------------------------------------------- detector optics

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfcat.so")
 CEILINGS = os.path.join(HERE, "fcat_ceilings")      # device-ceiling microbenchmark (stand-alone program)
-SOURCES = ["fcat_abi.hip", "fcat_kernels.hip", "fcat_split.hip", "fcat_mlp.hip", "fcat_noise.hip", "fcat_dose.hip", "fcat_fdk.hip", "fcat_optics.hip"]
+SOURCES = ["fcat_abi.hip", "fcat_kernels.hip", "fcat_split.hip", "fcat_mlp.hip", "fcat_noise.hip", "fcat_dose.hip", "fcat_fdk.hip", "fcat_optics.hip", "fcat_adjoint.hip"]
 ARCH = os.environ.get("FCAT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are switched off for all device code.

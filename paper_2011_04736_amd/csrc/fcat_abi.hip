@@ -162,7 +162,7 @@ int tile_log2u_for(const TraceGeom &G)
 
 namespace {
 
-TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
+TraceGeom make_geom_box(const fcat_geometry_t *g, const int (&n)[3], const double (&h)[3], const double (&c)[3])
 {
     TraceGeom G{};
     G.sid = g->sid_mm;
@@ -173,9 +173,6 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
     G.off_v = g->off_v_mm;
     G.cu = 0.5 * (g->nu - 1);
     G.cv = 0.5 * (g->nv - 1);
-    const double h[3] = {p->dx_mm, p->dy_mm, p->dz_mm};
-    const double c[3] = {p->cx_mm, p->cy_mm, p->cz_mm};
-    const int n[3] = {p->nx, p->ny, p->nz};
     for (int ax = 0; ax < 3; ++ax) {
         G.h[ax] = h[ax];
         G.inv_h[ax] = 1.0 / h[ax];
@@ -191,6 +188,14 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
     G.labels_bm = nullptr;
     G.tile_log2u = tile_log2u_for(G);
     return G;
+}
+
+TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
+{
+    const int n[3] = {p->nx, p->ny, p->nz};
+    const double h[3] = {p->dx_mm, p->dy_mm, p->dz_mm};
+    const double c[3] = {p->cx_mm, p->cy_mm, p->cz_mm};
+    return make_geom_box(g, n, h, c);
 }
 
 struct Layout {
@@ -1012,6 +1017,59 @@ fcat_status fcat_fdk(const fcat_geometry_t *geometry, const float *proj, const f
         if (e != hipSuccess) return device_fail(e, "fdk_quads");
         if ((s = fdk_backproject(geometry, nullptr, quads, a0, a0 + n, v, volume, a0 > 0, cs, stream))) return s;
     }
+    return FCAT_OK;
+}
+
+// ------------------------------------------------- image projector pair
+
+static fcat_status image_args(const fcat_geometry_t *geometry, const fcat_grid_t *grid, int32_t a_begin,
+                              int32_t a_end, const void *in, const void *out, TraceGeom &G)
+{
+    fcat_status s;
+    FdkGrid fg;
+    if ((s = check_geometry(geometry)) || (s = check_grid(grid, fg))) return s;
+    if (a_begin < 0 || a_end > geometry->n_angles || a_begin >= a_end)
+        return fail(FCAT_E_INVALID_ARG, "need 0 <= a_begin < a_end <= n_angles");
+    if (!in || !out) return fail(FCAT_E_INVALID_ARG, "input and output must not be NULL");
+    const int n[3] = {grid->nx, grid->ny, grid->nz};
+    const double h[3] = {grid->dx_mm, grid->dy_mm, grid->dz_mm};
+    const double c[3] = {grid->cx_mm, grid->cy_mm, grid->cz_mm};
+    G = make_geom_box(geometry, n, h, c);
+    return check_pending();
+}
+
+fcat_status fcat_image_project(const fcat_geometry_t *geometry, const fcat_grid_t *grid, const float *image,
+                               int32_t a_begin, int32_t a_end, float *proj, void *stream_)
+{
+    g_last_error.clear();
+    TraceGeom G;
+    fcat_status s;
+    if ((s = image_args(geometry, grid, a_begin, a_end, image, proj, G))) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipError_t e;
+    {
+        StageTimer tm(FCAT_STAGE_TRACE, stream);
+        e = launch_image_project(G, image, a_begin, a_end - a_begin, proj, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "image_project");
+    return FCAT_OK;
+}
+
+fcat_status fcat_image_backproject(const fcat_geometry_t *geometry, const fcat_grid_t *grid, const float *proj,
+                                   int32_t a_begin, int32_t a_end, float *image, int32_t accumulate, void *stream_)
+{
+    g_last_error.clear();
+    TraceGeom G;
+    fcat_status s;
+    if ((s = image_args(geometry, grid, a_begin, a_end, proj, image, G))) return s;
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    hipError_t e = hipSuccess;
+    {
+        StageTimer tm(FCAT_STAGE_BACKPROJECT, stream);
+        if (!accumulate) e = launch_fill(image, grid->nx * grid->ny * grid->nz, 0.0f, stream);
+        if (e == hipSuccess) e = launch_image_backproject(G, proj, a_begin, a_end - a_begin, image, stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "image_backproject");
     return FCAT_OK;
 }
 

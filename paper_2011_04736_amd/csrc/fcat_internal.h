@@ -187,6 +187,14 @@ hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_ma
 constexpr int kWalkCounts = 6;
 hipError_t launch_walk_stats(const TraceGeom &g, int a0, int n_ang, unsigned long long *counts, hipStream_t stream);
 
+// Projector of a voxel image and its transpose (fcat_adjoint.hip): the grid
+// is described by g's lo/h/n; proj is [n_ang][nv][nu] for angles a0 ..
+// a0 + n_ang - 1; the back-projection adds into image (zero it first for A^T y).
+hipError_t launch_image_project(const TraceGeom &g, const float *image, int a0, int n_ang, float *proj,
+                                hipStream_t stream);
+hipError_t launch_image_backproject(const TraceGeom &g, const float *proj, int a0, int n_ang, float *image,
+                                    hipStream_t stream);
+
 hipError_t launch_spectral(const float *L, int64_t n, const SpecTables &t, const float *i0,
                            const float *S, float *Y, hipStream_t stream);
 hipError_t launch_spectral_split(const float *L, int64_t n, const SpecTables &t, const SplitTables &sp,
