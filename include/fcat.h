@@ -60,13 +60,23 @@ extern "C" {
 
 #define FCAT_VERSION 1
 
+/* The enumerations below are 32-bit integers at the interface.  C++ gives
+   them that fixed underlying type, so that every value a C caller passes
+   (also one that names no enumerator) is a value of the type and is
+   rejected or reported as unknown, not undefined. */
+#ifdef __cplusplus
+#define FCAT_ENUM_INT : int32_t
+#else
+#define FCAT_ENUM_INT
+#endif
+
 /* Largest supported sizes. */
 #define FCAT_MAX_MATERIALS 32   /* n_mat */
 #define FCAT_MAX_GROUPS 32      /* n_groups */
 #define FCAT_MAX_ENERGIES 4096  /* n_energy */
 #define FCAT_MAX_PSF 31         /* psf k (odd) */
 
-typedef enum fcat_status {
+typedef enum fcat_status FCAT_ENUM_INT {
     FCAT_OK = 0,
     FCAT_E_INVALID_ARG = 1,  /* null pointer, bad size, SDD <= SID, even k, bad group map ... */
     FCAT_E_WORKSPACE = 2,    /* workspace missing, misaligned or too small */
@@ -76,7 +86,7 @@ typedef enum fcat_status {
     FCAT_E_UNSUPPORTED = 6   /* a valid request this library does not implement */
 } fcat_status;
 
-typedef enum fcat_mode {
+typedef enum fcat_mode FCAT_ENUM_INT {
     FCAT_MODE_PLAIN = 0,       /* FP32 traversal and FP32 spectral sum */
     FCAT_MODE_SPLIT_BF16 = 1,  /* L . mu on matrix cores, BF16 hi/lo split, FP32 accumulate */
     FCAT_MODE_SURROGATE = 2    /* learned per-group attenuation with exact fallback */
@@ -637,7 +647,7 @@ fcat_status fcat_mlp_setup(const fcat_spectral_t *spectral, const float *lin, co
 /* ---------------------------------------------------------- kernel timing */
 
 /* Kernel stages whose launches the timing facility tells apart. */
-typedef enum fcat_stage {
+typedef enum fcat_stage FCAT_ENUM_INT {
     FCAT_STAGE_PREP = 0,   /* spectral table preparation */
     FCAT_STAGE_TRACE = 1,  /* fused traversal + contraction + spectral sum (+ scatter) */
     FCAT_STAGE_PSF = 2,    /* optical spread + group sum */

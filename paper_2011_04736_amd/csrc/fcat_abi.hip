@@ -70,8 +70,8 @@ fcat_status check_phantom(const fcat_phantom_t *p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FCAT_E_INVALID_ARG, "nx, ny, nz must be >= 1");
     if ((int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
         return fail(FCAT_E_INVALID_ARG, "phantom larger than 2^31 - 1 voxels");
-    const int64_t bricked = (int64_t)((p->nx + kBrickEdge - 1) / kBrickEdge) * ((p->ny + kBrickEdge - 1) / kBrickEdge) *
-                            ((p->nz + kBrickEdge - 1) / kBrickEdge) * kBrickVox;
+    auto bricks = [](int32_t n) { return ((int64_t)n + kBrickEdge - 1) / kBrickEdge; };   // 64-bit: n may be 2^31 - 1
+    const int64_t bricked = bricks(p->nx) * bricks(p->ny) * bricks(p->nz) * kBrickVox;
     if (bricked + 2 * (int64_t)kLabelPad >= ((int64_t)1 << 31))
         return fail(FCAT_E_INVALID_ARG, "phantom rounded up to 16^3 bricks must hold fewer than 2^31 voxels");
     if (!finite_pos(p->dx_mm) || !finite_pos(p->dy_mm) || !finite_pos(p->dz_mm))
