@@ -47,7 +47,9 @@ PEAK_NOTE = ("peak: published FP32 157.3 TFLOP/s / 2 FLOP per FMA = 78.65e12 lan
              "peak_single_issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12")
 
 # Algorithmic work per unit (vector lane-operations).
-OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk (survey's count)
+OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk: next crossing as the
+                              # min of three, segment length, accumulation, advance of one axis's crossing
+                              # and index, label address and load, exit test
 EXP_SLOTS = 4                 # lane-operations counted for one exp (the hardware exp2 is half rate; the reduction adds more)
 
 WORKLOADS = {
@@ -78,6 +80,8 @@ def parse():
                     help="H of Eq. 5 (flood counts per open pixel) for the noise stage; 0 skips it")
     ap.add_argument("--dose", type=int, default=1, help="1: time the dose estimate of Eqs. 6-7 (0 skips it)")
     ap.add_argument("--fdk", type=int, default=1, help="1: time the FDK reconstruction of the projections (0 skips it)")
+    ap.add_argument("--image-projector", type=int, default=1,
+                    help="1: time the image projector and its transpose on the contrast grid (0 skips them)")
     ap.add_argument("--rl-iterations", type=int, default=10,
                     help="Richardson-Lucy iterations on the detected profiles (0 skips the optics stage)")
     ap.add_argument("--spectral", type=int, default=1, help="1: time steps a3-a4 alone on the hit rays' path lengths")
@@ -294,6 +298,41 @@ def fdk_stage(pb, cfg, args, torch, fc):
     }
 
 
+def image_projector_stage(pb, cfg, args, torch, fc, counts):
+    """The image projector A and its transpose on the workload's grid and
+    detector (every angle): A of the phantom's mean-attenuation image, then
+    A^T of those projections.  Work: the Siddon voxel segments of every ray
+    (fcat_walk_stats), one FMA-accumulation (A) or one atomic add (A^T) each."""
+    import synth
+    g, ph, s = cfg.geometry, cfg.phantom, cfg.spectral
+    grid = synth.Grid(nx=ph.nx, ny=ph.ny, nz=ph.nz, dx=ph.dx, dy=ph.dy, dz=ph.dz, cx=ph.cx, cy=ph.cy, cz=ph.cz)
+    w = (s.phi * s.eta).astype(np.float64)
+    mbar = torch.as_tensor((s.mu @ w / w.sum()).astype(np.float32), device=pb.phantom.labels.device)
+    image = mbar[pb.phantom.labels.long()].contiguous()
+    proj = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=image.device)
+    back = torch.empty_like(image)
+    stream = torch.cuda.current_stream()
+    tf, st_f = timed_steps(lambda: fc.fcat_image_project(pb.geometry, grid, image, out=proj, stream=stream),
+                           1, args.form_steps, torch)
+    tb, st_b = timed_steps(lambda: fc.fcat_image_backproject(pb.geometry, grid, proj, image=back, stream=stream),
+                           1, args.form_steps, torch)
+    K = args.form_steps
+    segs = float(counts["siddon_segments"])
+    f_ms, b_ms = st_f["trace"][0] / K, st_b["backproject"][0] / K
+    finite = bool(torch.isfinite(proj).all().item() and torch.isfinite(back).all().item())
+    del image, proj, back
+    return {
+        "grid": [grid.nx, grid.ny, grid.nz], "angles": g.n_angles, "voxel_segments": segs, "finite": finite,
+        "project": {"ms_per_step": round(1e3 * tf / K, 4), "segments_per_s": segs / (f_ms * 1e-3),
+                    "roofline": alu_roof("k_image_rays<false>", OPS_PER_SEGMENT * segs, f_ms,
+                                         work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment")},
+        "backproject": {"ms_per_step": round(1e3 * tb / K, 4), "segments_per_s": segs / (b_ms * 1e-3),
+                        "roofline": alu_roof("k_image_rays<true>", OPS_PER_SEGMENT * segs, b_ms,
+                                             work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment "
+                                                       "(one atomic add each)")},
+    }
+
+
 def dose_stage(pb, cfg, args, torch, fc, hit_rays):
     """Dose per particle (Eqs. 6-7) over all angles of the workload: the walk
     writes path lengths, k_dose_rays sums 1 - exp(-P) per bin over the rays
@@ -402,8 +441,8 @@ def rel_errors(x, ref, torch):
 
 def walk_work(counts: dict, M: int, E: int) -> tuple[float, float]:
     """(model, executed) lane-operations of the fused walk + spectral kernel:
-    OPS_PER_SEGMENT per Siddon voxel segment (the survey's unit of the
-    method's work) or per step the two-level walk takes (brick steps plus
+    OPS_PER_SEGMENT per Siddon voxel segment (the unit of the method's
+    work) or per step the two-level walk takes (brick steps plus
     voxel steps inside mixed bricks), plus the spectral sum of every hit ray
     (M FMAs, the scale, the weight FMA and an exp of EXP_SLOTS per bin)."""
     spectral = counts["hit_rays"] * E * (M + 2 + EXP_SLOTS)
@@ -426,7 +465,7 @@ def plain_workload(name, pb, cfg, warmup, steps, torch, fc):
     counts = fc.fcat_walk_stats(pb)
     rays = g.n_angles * g.nu * g.nv
     M, E, G, K = s.n_mat, s.n_energy, s.n_groups, cfg.psf.k
-    mp = 8 if M <= 8 else (12 if M <= 12 else (16 if M <= 16 else 32))
+    mp = 8 if M <= 8 else (10 if M <= 10 else (12 if M <= 12 else (16 if M <= 16 else 32)))   # material slots
     model, executed = walk_work(counts, M, E)
     trace_ms, trace_n = (v / steps for v in stages["trace"])
     psf_ms, psf_n = (v / steps for v in stages["psf"])
@@ -565,6 +604,11 @@ def form_surrogate(pb, cfg, plain, args, torch, fc, counts):
 
 # ------------------------------------------------------------------ main
 
+def progress(msg: str):
+    """One line on stderr per finished stage (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -600,6 +644,7 @@ def main():
     pb = fc.upload(cfg, device=dev)
     head, out = plain_workload(args.workload, pb, cfg, args.warmup, args.steps, torch, fc)
     counts = head["walk"]
+    progress(f"{args.workload}: plain form, {head['ms_per_step']:.3f} ms per step")
 
     result = {
         "metric": "rays*energy_bins/s",
@@ -633,9 +678,11 @@ def main():
     if "split_bf16" in forms:
         result["forms"]["split_bf16"] = {args.workload: form_split(args.workload, pb, cfg, out, args.form_steps,
                                                                    torch, fc, counts)}
+        progress(f"{args.workload}: split form")
     if "surrogate" in forms and args.workload == "head":
         result["forms"]["surrogate"] = form_surrogate(pb, cfg, {"out": out, "ms_per_step": head["ms_per_step"]},
                                                       args, torch, fc, counts)
+        progress(f"{args.workload}: surrogate form")
     del pb, out
     torch.cuda.empty_cache()
 
@@ -650,6 +697,7 @@ def main():
         p2 = fc.upload(c2, device=dev)
         entry, o2 = plain_workload(name, p2, c2, 2, args.secondary_steps, torch, fc)
         result["workloads"][name] = entry
+        progress(f"{name}: plain form, {entry['ms_per_step']:.3f} ms per step")
         if name == "contrast":
             if "split_bf16" in forms:
                 result["forms"]["split_bf16"][name] = form_split(name, p2, c2, o2, args.secondary_steps, torch, fc,
@@ -664,8 +712,11 @@ def main():
                 result["next"]["dose"] = dose_stage(p2, c2, args, torch, fc, entry["walk"]["hit_rays"])
             if args.fdk:
                 result["next"]["fdk"] = fdk_stage(p2, c2, args, torch, fc)
+            if args.image_projector:
+                result["next"]["image_projector"] = image_projector_stage(p2, c2, args, torch, fc, entry["walk"])
             if args.rl_iterations > 0:
                 result["next"]["optics"] = optics_stage(p2, c2, args, torch, fc)
+            progress(f"{name}: split form and the stages after the projector")
         del p2
         torch.cuda.empty_cache()
 
@@ -673,6 +724,7 @@ def main():
         add_measured_ceilings(result)
     if args.cpu_angles > 0:
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_angles, head["rays"] * s.n_energy / g.n_angles)
+        progress("oracle on the host cores")
     if args.tiny_oracle:
         result["cpu_tiny_single_thread"] = tiny_oracle()
 
