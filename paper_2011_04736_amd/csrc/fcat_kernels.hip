@@ -297,9 +297,13 @@ __global__ __launch_bounds__(kBlock) void k_psf(const float *__restrict__ Y, int
 
 // The same convolution with a 4 x 4 output block per lane: lane l of
 // wavefront w owns columns 4l .. 4l + 3 and rows 4w .. 4w + 3 of a 256 x (4 * kP4Waves)
-// output tile.  For each input row it reads its K + 3 inputs with aligned
-// 16-byte LDS loads (immediate offsets, no address arithmetic) and feeds
-// each to up to 4 x 4 outputs.  The flipped kernel of the group is staged in
+// output tile.  The LDS tile starts 8 columns left of the outputs, so each
+// 16-byte global load of an aligned column group is one aligned 16-byte LDS
+// store (storing the four values one by one, 4 columns apart across the
+// lanes, met each LDS bank four times: 2% slower on the head workload).
+// For each input row a lane reads the tile columns 4l .. 4l + NX - 1 with
+// aligned 16-byte LDS loads (immediate offsets, no address arithmetic) and
+// feeds its K + 3 inputs, from column 4l + 8 - C on, to up to 4 x 4 outputs.  The flipped kernel of the group is staged in
 // LDS beside the tile and each kernel row is read into vector registers
 // (a broadcast LDS read) where it is used: an FMA whose operands are all
 // vector registers can issue at up to about 1.6 times the rate of one that
@@ -320,7 +324,8 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
                                                      const float *aux, const float *__restrict__ norm)
 {
     constexpr int C = (K - 1) / 2;
-    constexpr int NX = (K + 3 + 3) / 4 * 4;       // inputs read per row, a multiple of 4
+    constexpr int X0 = 8 - C;                     // first tile column a lane uses, past 4 l
+    constexpr int NX = (X0 + K + 3 + 3) / 4 * 4;  // inputs read per row, a multiple of 4
     constexpr int LW = kP4Cols + NX - 4;          // tile width (covers the last lane's reads)
     constexpr int ROWS = 4 * NW;
     constexpr int LH = ROWS + K - 1;
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
             // 16-byte global loads from the aligned columns u0 - 8 + 4m, each
             // value written to tile column u - (u0 - C); with nu a multiple of 4
             // a group is inside the detector or not at all
-            constexpr int G4 = (LW + 8 - C + 3) / 4;
+            constexpr int G4 = LW / 4;
             for (int i = threadIdx.x; i < LH * G4; i += NT) {
                 const int rr = i / G4;
                 const int m = i - rr * G4;
@@ -360,19 +365,14 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
                 float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (v >= 0 && v < nv && u >= 0 && u < nu)
                     y = *reinterpret_cast<const float4 *>(Yg + (int64_t)v * nu + u);
-                float *trw = tile + rr * LW;
-                const int cc = 4 * m + C - 8;
-                if (cc >= 0) trw[cc] = y.x;
-                if (cc + 1 >= 0 && cc + 1 < LW) trw[cc + 1] = y.y;
-                if (cc + 2 >= 0 && cc + 2 < LW) trw[cc + 2] = y.z;
-                if (cc + 3 < LW) trw[cc + 3] = y.w;
+                *reinterpret_cast<float4 *>(tile + rr * LW + 4 * m) = y;
             }
         } else {
             for (int i = threadIdx.x; i < LH * LW; i += NT) {
                 const int rr = i / LW;
                 const int cc = i - rr * LW;
                 const int v = v0 - C + rr;
-                const int u = u0 - C + cc;
+                const int u = u0 - 8 + cc;
                 tile[i] = (v >= 0 && v < nv && u >= 0 && u < nu) ? Yg[(int64_t)v * nu + u] : 0.0f;
             }
         }
@@ -393,6 +393,9 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
                 x[j + 2] = v4.z;
                 x[j + 3] = v4.w;
             }
+            // the end values are not products' operands; using them here
+            // keeps each row read as whole aligned 16-byte LDS loads
+            __asm__ volatile("" ::"v"(x[0]), "v"(x[NX - 1]));
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = rr - r;
@@ -413,7 +416,7 @@ __global__ __launch_bounds__(NW * kWave) void k_psf4(const float *__restrict__ Y
 #pragma unroll
                     for (int j = 0; j < K; ++j)
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(w[j], x[c + j], acc[r][c]);
+                        for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(w[j], x[X0 + c + j], acc[r][c]);
                 }
             }
         }
