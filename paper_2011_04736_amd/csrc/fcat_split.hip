@@ -26,8 +26,30 @@
 namespace fcat {
 namespace {
 
+// One BF16 row of K = 32 NKB values per ray, unpadded; the 16-byte chunk c of
+// row r is stored at chunk c ^ swz(r).  A matrix-core operand read takes 16
+// consecutive rows (lane & 15) and two chunks per row in each half wavefront;
+// with 128 four-byte LDS banks, 16-byte reads by 32 lanes are free of
+// conflicts when those 32 chunks are distinct modulo 512 bytes.  Rows of 64
+// and 96 bytes repeat every 8 rows and rows of 128 bytes every 4 rows, so
+// the swizzle moves the later rows onto other chunks.  (The earlier padded
+// stride of K + 8 left 13-17% of the walk kernel's LDS cycles in conflicts;
+// removing them did not change its time, which the walk decides.)
 template <int NKB>
-constexpr int split_row_stride() { return NKB * 32 + 8; }   // BF16 units; +16 bytes spreads the banks
+constexpr int split_row_stride() { return NKB * 32; }   // BF16 units
+
+template <int NKB>
+__device__ __forceinline__ int split_swz(int r)
+{
+    return NKB == 2 ? ((r >> 2) & 3) << 1 : ((r >> 3) & 1) << 1;
+}
+
+// Offset (BF16 units) of value k of row r.
+template <int NKB>
+__device__ __forceinline__ int split_at(int r, int k)
+{
+    return r * split_row_stride<NKB>() + ((((k >> 3) ^ split_swz<NKB>(r))) << 3) + (k & 7);
+}
 
 // Group sums sum_{e in g} w_e exp(-P_e) of the 64 rays of the calling
 // wavefront (one per lane, path lengths L); emit(g, value) receives the
@@ -36,20 +58,18 @@ template <int MP, int NKB, typename Emit>
 __device__ __forceinline__ void split_group_sums(const float (&L)[MP], int M, int G, const SplitTables &S,
                                                  uint16_t *lds, Emit emit)
 {
-    constexpr int RS = split_row_stride<NKB>();
     constexpr int KW = NKB * 32;
     const int lane = threadIdx.x & (kWave - 1);
-    uint16_t *row = lds + lane * RS;
 #pragma unroll
-    for (int k = 0; k < KW; k += 2) *reinterpret_cast<uint32_t *>(row + k) = 0u;
+    for (int k = 0; k < KW; k += 8) *reinterpret_cast<uint4 *>(lds + split_at<NKB>(lane, k)) = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
         if (m < M) {
             const uint32_t hi = bf16_rne(L[m]);
             const uint32_t lo = bf16_rne(L[m] - bf16_value(hi));
-            row[m] = (uint16_t)hi;
-            row[M + m] = (uint16_t)hi;
-            row[2 * M + m] = (uint16_t)lo;
+            lds[split_at<NKB>(lane, m)] = (uint16_t)hi;
+            lds[split_at<NKB>(lane, M + m)] = (uint16_t)hi;
+            lds[split_at<NKB>(lane, 2 * M + m)] = (uint16_t)lo;
         }
     }
     // the rows are read by other lanes of this wavefront
@@ -63,7 +83,7 @@ __device__ __forceinline__ void split_group_sums(const float (&L)[MP], int M, in
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int kb = 0; kb < NKB; ++kb)
-            bfrag[c][kb] = *reinterpret_cast<const bf16x8 *>(lds + (16 * c + (lane & 15)) * RS + kb * 32 + 8 * q);
+            bfrag[c][kb] = *reinterpret_cast<const bf16x8 *>(lds + split_at<NKB>(16 * c + (lane & 15), kb * 32 + 8 * q));
 
     for (int g = 0; g < G; ++g) {
         float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -107,6 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
     constexpr int kRowBytes = kWave * split_row_stride<NKB>() * 2;
     constexpr int kAccBytes = mat_acc_floats<MP>() * 4;
     constexpr int kWaveBytes = kRowBytes > kAccBytes ? kRowBytes : kAccBytes;
+    static_assert(kWaveBytes % 16 == 0, "16-byte aligned rows in every wavefront's block");
     __shared__ __align__(16) uint8_t lds_raw[(kBlock / kWave) * kWaveBytes];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
