@@ -196,9 +196,10 @@ int fcat_version(void);
 
 /*
  * Workspace needed by fcat_project.  angles_per_chunk = 0 lets the library
- * choose (group signals of at most 1 GiB per chunk); a larger workspace
- * passed to fcat_project lets it process more angles per chunk.  Returns 0 if
- * the descriptors are invalid.
+ * choose: every angle in one chunk if their group signals (and, with the
+ * surrogate, path lengths) fit in 1 GiB, else chunks of at most 384 MiB of
+ * them.  fcat_project processes as many angles per chunk as the workspace
+ * it is given holds.  Returns 0 if the descriptors are invalid.
  */
 size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
                                     const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
