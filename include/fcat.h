@@ -196,9 +196,8 @@ int fcat_version(void);
 
 /*
  * Workspace needed by fcat_project.  angles_per_chunk = 0 lets the library
- * choose: every angle in one chunk if their group signals (and, with the
- * surrogate, path lengths) fit in 1 GiB, else chunks of at most 384 MiB of
- * them.  fcat_project processes as many angles per chunk as the workspace
+ * choose: every angle in one chunk if their group signals fit in 1 GiB,
+ * else chunks of at most 384 MiB of them.  fcat_project processes as many angles per chunk as the workspace
  * it is given holds.  Returns 0 if the descriptors are invalid.
  */
 size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
@@ -209,8 +208,10 @@ size_t fcat_project_workspace_bytes(const fcat_geometry_t *geometry, const fcat_
  * Full projector: out[a][v][u] (DEVICE float [n_angles][nv][nu]) for every
  * angle and pixel.  scatter NULL turns the scatter term off; psf NULL turns
  * the optical spread off (out = sum_g Y_g).  surrogate is required for
- * FCAT_MODE_SURROGATE and ignored otherwise; in that mode the path lengths
- * of each angle chunk pass through the workspace.
+ * FCAT_MODE_SURROGATE and ignored otherwise; in that mode one kernel walks
+ * each ray, evaluates the network on the matrix cores for the rays whose
+ * cell is validated and takes the exact spectral sum for the others (path
+ * lengths stay in registers).
  */
 fcat_status fcat_project(const fcat_geometry_t *geometry, const fcat_phantom_t *phantom,
                          const fcat_spectral_t *spectral, const fcat_scatter_t *scatter,
@@ -650,7 +651,7 @@ fcat_status fcat_mlp_setup(const fcat_spectral_t *spectral, const float *lin, co
 /* Kernel stages whose launches the timing facility tells apart. */
 typedef enum fcat_stage FCAT_ENUM_INT {
     FCAT_STAGE_PREP = 0,   /* spectral table preparation */
-    FCAT_STAGE_TRACE = 1,  /* fused traversal + contraction + spectral sum (+ scatter) */
+    FCAT_STAGE_TRACE = 1,  /* fused traversal + contraction (or network) + spectral sum (+ scatter) */
     FCAT_STAGE_PSF = 2,    /* optical spread + group sum */
     FCAT_STAGE_MLP = 3,    /* surrogate training / inference kernels run on their own */
     FCAT_STAGE_NOISE = 4,  /* Poisson draws */

@@ -199,9 +199,9 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, Y, Lbuf, fixed;
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, Y, fixed;
     size_t scale, unitk, flood, yflood;   // projection stage: c_g, unit kernels, flood, its group signals
-    size_t per_angle;    // bytes of per-angle chunk buffers (group signals, path lengths)
+    size_t per_angle;    // bytes of per-angle chunk buffers (group signals)
     size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
 };
 
@@ -256,10 +256,8 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (proj) o += align_up((size_t)t.G * plane * sizeof(float));
     L.fixed = o;
     L.y_per_angle = (with_psf && g) ? align_up((size_t)t.G * g->nu * g->nv * sizeof(float)) : 0;
-    const size_t l_per_angle = (surrogate && g) ? align_up((size_t)t.M * g->nu * g->nv * sizeof(float)) : 0;
-    L.per_angle = L.y_per_angle + l_per_angle;
-    L.Y = o;       // chunk buffers follow the fixed part: Y [chunk][G][plane], then L [chunk * plane][M]
-    L.Lbuf = o;    // (offset of Lbuf depends on the chunk; see chunk_lbuf)
+    L.per_angle = L.y_per_angle;
+    L.Y = o;       // the chunk buffer follows the fixed part: Y [chunk][G][plane]
     return L;
 }
 
@@ -270,8 +268,6 @@ constexpr size_t kDefaultChunkBytes = (size_t)1 << 30;
 // contrast workload (2 MiB per angle) one launch for all 360 angles is best
 // (2.10 ms; 2.29 ms in chunks of 90).
 constexpr size_t kProjectChunkBytes = (size_t)384 << 20;
-
-size_t chunk_lbuf(const Layout &L, int chunk) { return L.Y + (size_t)chunk * L.y_per_angle; }
 
 // Angles per chunk when the caller leaves the choice to the library: all of
 // them in one launch if their chunk buffers fit in kDefaultChunkBytes, else
@@ -656,6 +652,8 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
         return launch_log_projection(o, flood, n, plane, floor_, o, stream);
     };
     auto rows = [&](int a0, int n, float *Yc, float *outc) {
+        if (sur)
+            return launch_project_rows_mlp(G, t, mt, spectral->flood, S, a0, n, Yc, outc, surrogate->counts, stream);
         return split ? launch_project_rows_split(G, phantom->labels, t, sp, spectral->flood, S, a0, n, Yc, outc, stream)
                      : launch_project_rows(G, phantom->labels, t, spectral->flood, S, a0, n, Yc, outc, stream);
     };
@@ -670,33 +668,10 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     }
     const int chunk = (int)std::min<size_t>((size_t)A, (workspace_bytes - L.fixed) / L.per_angle);
     float *Y = grouped ? at<float>(workspace, L.Y) : nullptr;
-    float *Lbuf = sur ? at<float>(workspace, chunk_lbuf(L, chunk)) : nullptr;
     for (int a0 = 0; a0 < A; a0 += chunk) {
         const int n = std::min(chunk, A - a0);
         float *outc = out + a0 * plane;
-        if (sur) {
-            {
-                StageTimer tm(FCAT_STAGE_TRACE, stream);
-                e = launch_pathlengths(G, phantom->labels, t.M, a0, n, Lbuf, stream);
-            }
-            if (e != hipSuccess) return device_fail(e, "pathlengths");
-            SurrogateIO io{};
-            io.L = Lbuf;
-            io.n = (int64_t)n * plane;
-            io.plane = plane;
-            io.flood = spectral->flood;
-            io.scatter = S ? S + a0 * plane : nullptr;
-            io.Y = Y;
-            io.out = grouped ? nullptr : outc;
-            io.counts = surrogate->counts;
-            io.force_mlp = 0;
-            io.bad = bad;
-            {
-                StageTimer tm(FCAT_STAGE_MLP, stream);
-                e = launch_mlp_spectral(t, mt, io, stream);
-            }
-            if (e != hipSuccess) return device_fail(e, "mlp_spectral");
-        } else {
+        {
             StageTimer tm(FCAT_STAGE_TRACE, stream);
             e = rows(a0, n, Y, grouped ? nullptr : outc);
             if (e != hipSuccess) return device_fail(e, "project_rows");

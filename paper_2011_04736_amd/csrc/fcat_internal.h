@@ -74,6 +74,15 @@ inline int64_t tiles_per_angle_host(const TraceGeom &G)
     return (int64_t)((G.nu + tu - 1) / tu) * ((G.nv + tv - 1) / tv);
 }
 
+// Workgroups of a launch with one wavefront per tile of detector pixels,
+// padded to a multiple of kXcds so that the XCD remap (xcd_block) is a
+// bijection.
+inline int padded_blocks(int64_t waves)
+{
+    const int64_t nblk = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
+    return (int)((nblk + kXcds - 1) / kXcds * kXcds);
+}
+
 // Spectral tables prepared on the device (in the workspace) from mu, phi,
 // eta and s_bin.  gstart is host-derived from the group map.
 struct SpecTables {
@@ -101,7 +110,7 @@ struct SplitTables {
 
 // Surrogate network tables (fcat_mlp.hip).  frag holds the BF16 B-operand
 // fragments of every weight view the forward and backward passes use.
-constexpr int kMlpFrags = 52;
+constexpr int kMlpFrags = 68;
 struct MlpTables {
     const uint4 *frag;             // [kMlpFrags][64]
     const float *params;           // FP32 master parameters (biases read from here)
@@ -143,6 +152,12 @@ hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *
                             int64_t n, float *partial, float *in_scale, float *out_scale, float *tau_max,
                             hipStream_t stream);
 hipError_t launch_mlp_spectral(const SpecTables &t, const MlpTables &m, const SurrogateIO &io, hipStream_t stream);
+// The surrogate projector for angles [a0, a0 + n_ang) in one pass (walk,
+// network where validated, exact sum elsewhere, scatter); Y and out as in
+// launch_project_rows; counts as SurrogateIO::counts.
+hipError_t launch_project_rows_mlp(const TraceGeom &g, const SpecTables &t, const MlpTables &m, const float *flood,
+                                   const float *scatter, int a0, int n_ang, float *Y, float *out, int *counts,
+                                   hipStream_t stream);
 hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n_all,
                            const int32_t *order, int64_t base, int count, float *partial, float *loss_partial,
                            hipStream_t stream);

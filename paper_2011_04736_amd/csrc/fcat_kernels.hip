@@ -547,12 +547,6 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__
             labels_bm[(int64_t)gridDim.x * kBrickVox + i] = (int8_t)-1;
 }
 
-int padded_blocks(int64_t waves)
-{
-    const int64_t nblk = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
-    return (int)((nblk + kXcds - 1) / kXcds * kXcds);
-}
-
 }  // namespace
 
 // ------------------------------------------------------------- launchers

@@ -43,14 +43,24 @@ constexpr int kFragW3 = 24;    // [kb 0..1]          W3_hi[n][32 kb + k], n < n_
 constexpr int kFragW3lo = 26;  // [kb 0..1]          W3_lo
 constexpr int kFragW3b = 28;   // [ht 0..3]          B[o][h2] = W3_hi[o][h2]   (dH2 = dZ3 W3)
 constexpr int kFragW2b = 32;   // [ht 0..3][kb 0..1] B[h2][h1] = W2_hi[h2][h1] (dH1 = dZ2 W2)
-// Inference views with log2(e) folded in (see mlp_infer_wave): W1 scaled by
-// log2(e) and W3 by 1/log2(e) before the hi/lo split.
+// Inference views (see mlp_infer_wave): W1 scaled by log2(e) and W3 by
+// 1/log2(e) before the hi/lo split, and the second- and third-layer weights
+// listed over the hidden units in the order chained_unit gives.
 constexpr int kFragW1i = 40;   // as kFragW1
 constexpr int kFragW1iLo = 44; // as kFragW1lo
-constexpr int kFragW3i = 48;   // as kFragW3
-constexpr int kFragW3iLo = 50; // as kFragW3lo
-static_assert(kFragW3iLo + 2 == kMlpFrags, "fragment table size");
+constexpr int kFragW3i = 48;   // [kb 0..1]          W3_hi[n][chained_unit(kb, q, j)] / log2(e), n < n_out
+constexpr int kFragW3iLo = 50; // [kb 0..1]          lo part
+constexpr int kFragW2c = 52;   // [ht 0..3][kb 0..1] W2_hi[16 ht + r][chained_unit(kb, q, j)]
+constexpr int kFragW2cLo = 60; // [ht 0..3][kb 0..1] lo part
+static_assert(kFragW2cLo + 8 == kMlpFrags, "fragment table size");
 constexpr float kLog2e = 1.4426950408889634f;
+
+// Hidden unit behind k index 8 q + j of the 32-wide block kb when a layer's
+// accumulators feed the next layer in place: after a 16 x 16 x 32 product
+// with the units as rows, lane (q, r) holds units 16 ht + 4 q + i (i < 4)
+// of ray r, and block kb takes ht = 2 kb and 2 kb + 1.  A bijection of the
+// 32 units of each block.
+__device__ __host__ constexpr int chained_unit(int kb, int q, int j) { return 32 * kb + 16 * (j >> 2) + 4 * q + (j & 3); }
 
 struct Offsets {
     int W1, b1, W2, b2, W3, b3, P;
@@ -91,16 +101,34 @@ __device__ __forceinline__ float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// Per-wavefront LDS of the forward pass.  X holds the inputs of the 64 rays,
-// row r = [x_hi (16) | x_lo (16)]; the outputs of ray r later reuse row r
-// (only that ray's tile has read it by then).  Hh/Hl hold the hi/lo parts of
-// one 16-ray tile's hidden activations, [ray][unit].
-constexpr int SOI = SX / 2;            // row stride (FP32) of the outputs in X
-struct InferLds {
-    uint16_t X[kWave * SX];
-    uint16_t Hh[16 * SH];
-    uint16_t Hl[16 * SH];
-};
+// Per-wavefront LDS of the forward pass: one 64-byte row per ray of the
+// wavefront (4 KiB).  Row r first holds ray r's inputs [x_hi (16) | x_lo
+// (16)] as four 16-byte chunks, chunk c at position c ^ ((r >> 2) & 3), so
+// that the 16 rows one operand read touches fall on distinct banks.  Once
+// its tile has been through the first layer, row r holds ray r's outputs,
+// output o at word (o + (r >> 2)) & 15, so that 64 lanes reading the same
+// output of their own rays fall on distinct banks.  The hidden activations
+// never pass through LDS (see mlp_infer_wave).
+constexpr int kInferRowBytes = 64;
+constexpr int kInferLdsBytes = kWave * kInferRowBytes;
+
+__device__ __forceinline__ int infer_chunk(int row, int c) { return row * kInferRowBytes + 16 * (c ^ ((row >> 2) & 3)); }
+__device__ __forceinline__ int infer_out_word(int row, int o) { return row * (kInferRowBytes / 4) + ((o + (row >> 2)) & 15); }
+
+// Output o of the ray of lane `lane`, after mlp_infer_wave.
+__device__ __forceinline__ float mlp_out(const uint8_t *rows, int lane, int o)
+{
+    return reinterpret_cast<const float *>(rows)[infer_out_word(lane, o)];
+}
+
+// Bit ct set where any of lanes 16 ct .. 16 ct + 15 is set in a ballot.
+__device__ __forceinline__ uint32_t tile_mask(uint64_t ballot)
+{
+    uint32_t t = 0;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) t |= ((ballot >> (16 * ct)) & 0xffffu) ? (1u << ct) : 0u;
+    return t;
+}
 
 // With z' = log2(e) z, log2(e) silu(z) = z' / (1 + 2^-z'): one v_exp_f32,
 // one add, one v_rcp_f32 and one multiply.
@@ -109,31 +137,48 @@ __device__ __forceinline__ float silu2(float zs)
     return zs * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-zs));
 }
 
-// SiLU of the 4 units of an output fragment (bias already in the
-// accumulator), split and stored as one 8-byte hi and one 8-byte lo write
-// at Hs[ray][unit0 .. unit0 + 3].
-__device__ __forceinline__ void silu_store4(const floatx4 &acc, uint16_t *Hh, uint16_t *Hl, int at)
+// SiLU of the 16 units a lane holds after one layer (acc[ht][i] = unit
+// 16 ht + 4 q + i of its ray), split into hi/lo BF16 and packed as the next
+// layer's B operands: block kb, element j = unit chained_unit(kb, q, j).
+__device__ __forceinline__ void silu_pack(const floatx4 (&acc)[4], bf16x8 (&bh)[2], bf16x8 (&bl)[2])
 {
-    const float h0 = silu2(acc[0]), h1 = silu2(acc[1]);
-    const float h2 = silu2(acc[2]), h3 = silu2(acc[3]);
-    uint32_t hi01, lo01, hi23, lo23;
-    split_bf16x2(h0, h1, hi01, lo01);
-    split_bf16x2(h2, h3, hi23, lo23);
-    *reinterpret_cast<uint2 *>(Hh + at) = make_uint2(hi01, hi23);
-    *reinterpret_cast<uint2 *>(Hl + at) = make_uint2(lo01, lo23);
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const floatx4 &a = acc[2 * kb + t];
+            split_bf16x2(silu2(a[0]), silu2(a[1]), hi[2 * t], lo[2 * t]);
+            split_bf16x2(silu2(a[2]), silu2(a[3]), hi[2 * t + 1], lo[2 * t + 1]);
+        }
+        bh[kb] = __builtin_bit_cast(bf16x8, make_uint4(hi[0], hi[1], hi[2], hi[3]));
+        bl[kb] = __builtin_bit_cast(bf16x8, make_uint4(lo[0], lo[1], lo[2], lo[3]));
+    }
 }
 
-// Forward pass of the 64 rays of the wavefront, one 16-ray tile at a time.
-// The weights are the A operand (rows = units), the activations the B
-// operand (columns = rays), so each lane ends up with 4 consecutive units of
-// one ray and stores them with one write; the accumulators start at the
-// biases.  The pass runs on z' = log2(e) z: W1 and b1, b2 carry the factor
-// (W2 needs none, since the hidden values are log2(e) silu), and W3 its
-// inverse, which yields the same network output as the unscaled form.
-// x (n_in values per lane, zero beyond) goes in; the n_out outputs of lane
-// l's ray come back in out[].
-__device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTables &M, InferLds &S,
-                                               float (&out)[16])
+__device__ __forceinline__ floatx4 bias4(const float *b, float scale)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(b);
+    return floatx4{scale * v.x, scale * v.y, scale * v.z, scale * v.w};
+}
+
+// Forward pass of the rays of the wavefront, one 16-ray tile (lanes
+// 16 ct .. 16 ct + 15) at a time, tiles whose bit in `tiles` (one per 16
+// lanes) is clear skipped.  The weights are the A operand (rows = units),
+// the activations the B operand (columns = rays), so after each layer lane
+// (q, r) holds units 16 ht + 4 q + i of ray r in its accumulators.  Those
+// registers are the next layer's B operand as they stand: the hidden units
+// are summed in the order chained_unit gives, and the second- and
+// third-layer fragments list their weights in that order.  Only the
+// inputs (to spread each ray's values over the four lane groups) and the
+// outputs (to gather them back) pass through LDS.  The pass runs on
+// z' = log2(e) z: W1 and b1, b2 carry the factor (W2 needs none, since the
+// hidden values are log2(e) silu), and W3 its inverse, which yields the
+// same network output as the unscaled form.  x: n_in values per lane, zero
+// beyond; rows: this wavefront's kInferLdsBytes of LDS; the outputs are
+// read back with mlp_out.
+__device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTables &M, uint8_t *rows,
+                                               uint32_t tiles = 0xfu)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int q = lane >> 4, r16 = lane & 15;
@@ -143,76 +188,65 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
         uint32_t hi[8], lo[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) split_bf16x2(x[2 * k], x[2 * k + 1], hi[k], lo[k]);
-        uint4 *row = reinterpret_cast<uint4 *>(S.X + lane * SX);
-        row[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-        row[1] = make_uint4(hi[4], hi[5], hi[6], hi[7]);
-        row[2] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-        row[3] = make_uint4(lo[4], lo[5], lo[6], lo[7]);
+        *reinterpret_cast<uint4 *>(rows + infer_chunk(lane, 0)) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        *reinterpret_cast<uint4 *>(rows + infer_chunk(lane, 1)) = make_uint4(hi[4], hi[5], hi[6], hi[7]);
+        *reinterpret_cast<uint4 *>(rows + infer_chunk(lane, 2)) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        *reinterpret_cast<uint4 *>(rows + infer_chunk(lane, 3)) = make_uint4(lo[4], lo[5], lo[6], lo[7]);
     }
-    floatx4 b1[4], b2[4], b3;
-#pragma unroll
-    for (int ht = 0; ht < 4; ++ht)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            b1[ht][i] = kLog2e * P[off.b1 + 16 * ht + 4 * q + i];
-            b2[ht][i] = kLog2e * P[off.b2 + 16 * ht + 4 * q + i];
-        }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) b3[i] = 4 * q + i < M.n_out ? P[off.b3 + 4 * q + i] : 0.0f;
     wave_sync_lds();
+#pragma unroll 1
     for (int ct = 0; ct < 4; ++ct) {
+        if (!((tiles >> ct) & 1u)) continue;
+        const int row = 16 * ct + r16;
+        // the fragment table's address, made opaque per tile: otherwise its
+        // loads are hoisted out of the loop and their 112 registers held
+        // through it (and through the walk it is fused with)
+        const uint4 *frag = M.frag;
+        asm volatile("" : "+s"(frag));
         // layer 1: Z1 = W1_hi (x_hi + x_lo) + W1_lo x_hi + b1
-        const bf16x8 bx = lds_frag(S.X, SX, 16 * ct + r16, 8 * q);
+        const bf16x8 bx = *reinterpret_cast<const bf16x8 *>(rows + infer_chunk(row, q));
+        floatx4 acc[4];
 #pragma unroll
         for (int ht = 0; ht < 4; ++ht) {
-            floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW1i + ht, lane), bx, b1[ht],
-                                                                  0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW1iLo + ht, lane), bx, acc, 0, 0, 0);
-            silu_store4(acc, S.Hh, S.Hl, r16 * SH + 16 * ht + 4 * q);
+            acc[ht] = bias4(P + off.b1 + 16 * ht + 4 * q, kLog2e);
+            acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(frag, kFragW1i + ht, lane), bx, acc[ht], 0, 0,
+                                                              0);
+            acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(frag, kFragW1iLo + ht, lane), bx, acc[ht], 0,
+                                                              0, 0);
         }
-        wave_sync_lds();
-        // layer 2 (in place): Z2 = W2_hi (H1_hi + H1_lo) + W2_lo H1_hi
         bf16x8 hh[2], hl[2];
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            hh[kb] = lds_frag(S.Hh, SH, r16, 32 * kb + 8 * q);
-            hl[kb] = lds_frag(S.Hl, SH, r16, 32 * kb + 8 * q);
-        }
-        wave_sync_lds();
+        silu_pack(acc, hh, hl);
+        // layer 2: Z2 = W2_hi (H1_hi + H1_lo) + W2_lo H1_hi + b2
 #pragma unroll
         for (int ht = 0; ht < 4; ++ht) {
-            floatx4 acc = b2[ht];
+            acc[ht] = bias4(P + off.b2 + 16 * ht + 4 * q, kLog2e);
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb) {
-                const bf16x8 wh = frag_of(M.frag, kFragW2 + ht * 2 + kb, lane);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hh[kb], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hl[kb], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW2lo + ht * 2 + kb, lane),
-                                                              hh[kb], acc, 0, 0, 0);
+                const bf16x8 wh = frag_of(frag, kFragW2c + ht * 2 + kb, lane);
+                acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hh[kb], acc[ht], 0, 0, 0);
+                acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hl[kb], acc[ht], 0, 0, 0);
+                acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(frag, kFragW2cLo + ht * 2 + kb, lane),
+                                                                  hh[kb], acc[ht], 0, 0, 0);
             }
-            silu_store4(acc, S.Hh, S.Hl, r16 * SH + 16 * ht + 4 * q);
         }
-        wave_sync_lds();
-        // layer 3: outputs 4q .. 4q+3 of ray 16 ct + r16
-        floatx4 acc = b3;
+        silu_pack(acc, hh, hl);
+        // layer 3: outputs 4 q .. 4 q + 3 of the tile's ray r16
+        floatx4 o = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (4 * q < M.n_out) o = bias4(P + off.b3 + 4 * q, 1.0f);
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 h = lds_frag(S.Hh, SH, r16, 32 * kb + 8 * q);
-            const bf16x8 l = lds_frag(S.Hl, SH, r16, 32 * kb + 8 * q);
-            const bf16x8 wh = frag_of(M.frag, kFragW3i + kb, lane);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, h, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, l, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(M.frag, kFragW3iLo + kb, lane), h, acc, 0, 0, 0);
+            const bf16x8 wh = frag_of(frag, kFragW3i + kb, lane);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hh[kb], o, 0, 0, 0);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, hl[kb], o, 0, 0, 0);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(frag, kFragW3iLo + kb, lane), hh[kb], o, 0, 0, 0);
         }
-        if (4 * q < M.n_out) {
-            float *o = reinterpret_cast<float *>(S.X) + (16 * ct + r16) * SOI + 4 * q;
-            *reinterpret_cast<float4 *>(o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        }
-        wave_sync_lds();
-    }
-    const float *o = reinterpret_cast<const float *>(S.X) + lane * SOI;
+        // row `row` has been read by this tile's first layer only: its words
+        // now take the ray's outputs
+        float *orow = reinterpret_cast<float *>(rows);
 #pragma unroll
-    for (int g = 0; g < 16; ++g) out[g] = g < M.n_out ? o[g] : 0.0f;
+        for (int i = 0; i < 4; ++i)
+            if (4 * q + i < M.n_out) orow[infer_out_word(row, 4 * q + i)] = o[i];
+    }
     wave_sync_lds();
 }
 
@@ -229,22 +263,31 @@ __global__ __launch_bounds__(kBlock) void k_mlp_prep(const float *__restrict__ p
     const int fi = idx / kWave, lane = idx % kWave;
     const int q = lane >> 4, r16 = lane & 15;
     const Offsets off = param_offsets(n_in, n_out);
-    // the inference views are the W1 / W3 views of scaled weights
+    // the first-layer inference views are the W1 views of scaled weights
     int f = fi;
     float scale = 1.0f;
     if (fi >= kFragW1i && fi < kFragW3i) {
         f = kFragW1 + (fi - kFragW1i);
         scale = kLog2e;
-    } else if (fi >= kFragW3i) {
-        f = kFragW3 + (fi - kFragW3i);
-        scale = 1.0f / kLog2e;
     }
     uint32_t h[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int kk = 8 * q + j;
         float v = 0.0f;
-        if (f < kFragW1lo) {                     // [W1_hi | W1_hi]
+        if (f >= kFragW2c) {                     // W2 in chained order, hi or lo
+            const bool lo = f >= kFragW2cLo;
+            const int t = f - (lo ? kFragW2cLo : kFragW2c);
+            const float w = params[off.W2 + (16 * (t / 2) + r16) * H + chained_unit(t % 2, q, j)];
+            v = lo ? w - hi_part(w) : w;
+        } else if (f >= kFragW3i) {              // W3 / log2(e) in chained order, hi or lo
+            const bool lo = f >= kFragW3iLo;
+            const int kb = f - (lo ? kFragW3iLo : kFragW3i);
+            if (r16 < n_out) {
+                const float w = (1.0f / kLog2e) * params[off.W3 + r16 * H + chained_unit(kb, q, j)];
+                v = lo ? w - hi_part(w) : w;
+            }
+        } else if (f < kFragW1lo) {                     // [W1_hi | W1_hi]
             const int n = 16 * (f - kFragW1) + r16, k = kk & 15;
             if (k < n_in) v = hi_part(scale * params[off.W1 + n * n_in + k]);
         } else if (f < kFragW2) {                // [W1_lo | 0]
@@ -332,8 +375,9 @@ __device__ __forceinline__ bool in_domain(const float (&L)[16], const float (&x)
 template <int MP>
 __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables M, SurrogateIO io)
 {
-    __shared__ __align__(16) InferLds lds[kBlock / kWave];
+    __shared__ __align__(16) uint8_t lds[(kBlock / kWave) * kInferLdsBytes];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    uint8_t *rows = lds + wave * kInferLdsBytes;
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = r < io.n;
     float L[16], x[16];
@@ -346,10 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
     }
     const bool hit = valid && tot > 0.0f;
     const bool use = hit && (io.force_mlp || in_domain(L, x, M));
-    float o[16];
-#pragma unroll
-    for (int g = 0; g < 16; ++g) o[g] = 0.0f;
-    if (__ballot(use) != 0) mlp_infer_wave(x, M, lds[wave], o);
+    const uint64_t use_mask = __ballot(use);
+    if (use_mask != 0) mlp_infer_wave(x, M, rows, tile_mask(use_mask));
     if (io.counts && valid) {
         const uint64_t bu = __ballot(use), bh = __ballot(hit);
         if (lane == 0) {
@@ -368,11 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
     for (int g = 0; g < T.G; ++g) {
         float prim;
         if (use) {
-            float og = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k == g) og = o[k];
-            float z = M.out_scale[g] * og;
+            float z = M.out_scale[g] * mlp_out(rows, lane, g);
 #pragma unroll
             for (int m = 0; m < 16; ++m)
                 if (m < T.M) z = fmaf(M.lin[g * T.M + m], L[m], z);
@@ -390,6 +428,108 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
     }
     if (io.out) io.out[r] = total;
     flag_nonfinite(io.bad, i0, sc);
+}
+
+// The surrogate projector in one pass: the walk of k_project_rows, then,
+// for the rays whose cell the held-out validation accepted, the network on
+// the matrix cores, and the exact spectral sum for the rest; scatter and
+// group signals as in k_project_rows.  The path lengths stay in registers.
+// The walk's LDS block of each wavefront is reused for the network's
+// input/output rows once the walk is done, so the network costs the walk
+// no occupancy; its weights are read from the fragment table (L2-resident,
+// 68 KiB), since LDS for a copy per workgroup would cap the walk at four
+// wavefronts per SIMD.
+template <int MP>
+constexpr int fused_wave_floats()
+{
+    constexpr int a = (mat_acc_floats<MP>() + 3) / 4 * 4;
+    return a > kInferLdsBytes / 4 ? a : kInferLdsBytes / 4;
+}
+
+// Wavefronts per SIMD the walk's LDS block allows (8 at most): the fused
+// kernel is compiled to that occupancy, so the network's registers never
+// cost the walk occupancy (a few values spill around the network instead).
+template <int MP>
+constexpr int fused_waves_per_simd()
+{
+    constexpr int per_cu = (160 * 1024) / ((kBlock / kWave) * fused_wave_floats<MP>() * 4) * (kBlock / kWave);
+    return per_cu / 4 < 8 ? per_cu / 4 : 8;
+}
+
+template <int MP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<MP>())))
+void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
+                                                             const float *__restrict__ flood,
+                                                             const float *__restrict__ scatter, int a0, int n_ang,
+                                                             int nblk_pad, float *__restrict__ Y,
+                                                             float *__restrict__ out, int *__restrict__ counts)
+{
+    __shared__ __align__(16) float lds_all[(kBlock / kWave) * fused_wave_floats<MP>()];
+    const int blk = xcd_block(nblk_pad);
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gw = blk * (kBlock / kWave) + wave;
+    if (gw >= n_ang * tiles_per_angle(G)) return;
+    const PixelOf px = pixel_of(G, gw, lane);
+    const int al = px.al, iv = px.iv, iu = px.iu;
+    const int a = a0 + al;
+    const bool valid = px.valid;
+    float *block = lds_all + wave * fused_wave_floats<MP>();
+
+    double st, ct;
+    sincos(angle_of(G, a), &st, &ct);
+    float L[MP];
+    Ray r{};
+    const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
+    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, block, L);
+    const bool any_hit = __ballot(hit) != 0;
+
+    float L16[16], x[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        L16[m] = m < MP ? L[m] : 0.0f;
+        x[m] = m < M.n_in ? __fmul_rn(L16[m], M.in_scale[m]) : 0.0f;
+    }
+    const bool use = hit && in_domain(L16, x, M);
+    const uint64_t use_mask = __ballot(use);
+    uint8_t *rows = reinterpret_cast<uint8_t *>(block);
+    if (use_mask != 0) {
+        wave_sync_lds();      // the walk's sums have been read: the block becomes the network's rows
+        mlp_infer_wave(x, M, rows, tile_mask(use_mask));
+    }
+    if (counts) {
+        const uint64_t hit_mask = __ballot(hit);
+        if (lane == 0) {
+            atomicAdd(counts + 0, (int)__popcll(use_mask));
+            atomicAdd(counts + 1, (int)__popcll(hit_mask & ~use_mask));
+        }
+    }
+    if (!valid) return;
+
+    const int64_t plane = (int64_t)G.nu * G.nv;
+    const int64_t pix = (int64_t)iv * G.nu + iu;
+    const float i0 = flood ? flood[pix] : 1.0f;
+    const float sc = scatter ? scatter[(int64_t)a * plane + pix] : 0.0f;
+    float total = 0.0f;
+    for (int g = 0; g < T.G; ++g) {
+        float prim;
+        if (use) {
+            float z = M.out_scale[g] * mlp_out(rows, lane, g);
+#pragma unroll
+            for (int m = 0; m < MP; ++m)
+                if (m < T.M) z = fmaf(M.lin[g * T.M + m], L[m], z);
+            prim = T.Wg[g] * expf(-z);
+        } else {
+            prim = any_hit ? group_sum<MP>(L, T, T.gstart[g], T.gstart[g + 1]) : T.Wg[g];
+        }
+        const float y = fmaf(i0, prim, T.Wsg[g] * sc);
+        if (Y)
+            Y[((int64_t)al * T.G + g) * plane + pix] = y;
+        else
+            total += y;
+    }
+    if (!Y) out[(int64_t)a * plane + pix] = total;
+    flag_nonfinite(G.bad, i0, sc);
 }
 
 struct TrainLds {
@@ -758,8 +898,9 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(SpecTables T, MlpTables
                                                          unsigned *__restrict__ cell_err_bits,
                                                          int *__restrict__ cell_count)
 {
-    __shared__ __align__(16) InferLds lds[kBlock / kWave];
-    const int wave = threadIdx.x >> 6;
+    __shared__ __align__(16) uint8_t lds[(kBlock / kWave) * kInferLdsBytes];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    uint8_t *rows = lds + wave * kInferLdsBytes;
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = r < n;
     float L[16], x[16];
@@ -770,8 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(SpecTables T, MlpTables
         x[m] = m < M.n_in ? __fmul_rn(L[m], M.in_scale[m]) : 0.0f;
         tot += L[m];
     }
-    float o[16];
-    mlp_infer_wave(x, M, lds[wave], o);
+    mlp_infer_wave(x, M, rows);
     if (!(valid && tot > 0.0f)) return;
     const int cell = cell_of(L, x, M);
     if (cell < 0) return;
@@ -779,11 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(SpecTables T, MlpTables
     for (int g = 0; g < T.G; ++g) ysum += Yin[(int64_t)g * n + r];
     float err = 0.0f;
     for (int g = 0; g < T.G; ++g) {
-        float og = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (k == g) og = o[k];
-        float z = M.out_scale[g] * og;
+        float z = M.out_scale[g] * mlp_out(rows, lane, g);
 #pragma unroll
         for (int m = 0; m < 16; ++m)
             if (m < T.M) z = fmaf(M.lin[g * T.M + m], L[m], z);
@@ -953,6 +1089,26 @@ hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_stats_final, dim3(1), dim3(64), 0, stream, partial, t.M, t.G, in_scale, out_scale,
                        tau_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_rows_mlp(const TraceGeom &g, const SpecTables &t, const MlpTables &m, const float *flood,
+                                   const float *scatter, int a0, int n_ang, float *Y, float *out, int *counts,
+                                   hipStream_t stream)
+{
+    const int64_t waves = (int64_t)n_ang * tiles_per_angle_host(g);
+    const int nblk = padded_blocks(waves);
+#define FCAT_FUSED(MPV)                                                                                          \
+    hipLaunchKernelGGL(k_project_rows_mlp<MPV>, dim3(nblk), dim3(kBlock), 0, stream, g, t, m, flood, scatter, a0, \
+                       n_ang, nblk, Y, out, counts)
+    switch (t.mp) {
+    case 8: FCAT_FUSED(8); break;
+    case 10: FCAT_FUSED(10); break;
+    case 12: FCAT_FUSED(12); break;
+    case 16: FCAT_FUSED(16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef FCAT_FUSED
     return hipGetLastError();
 }
 

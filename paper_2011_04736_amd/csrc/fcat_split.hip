@@ -348,12 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_psf_split(const float *__restrict__ 
     }
 }
 
-int padded_blocks(int64_t waves)
-{
-    const int64_t nblk = (waves + (kBlock / kWave) - 1) / (kBlock / kWave);
-    return (int)((nblk + kXcds - 1) / kXcds * kXcds);
-}
-
 }  // namespace
 
 hipError_t launch_prep_split(const float *mu, const SpecTables &t, const SplitTables &sp, uint4 *afrag,

@@ -181,6 +181,46 @@ def test_training_and_surrogate_projector(fc):
     assert counts[0] > 0 and err.max() <= 1e-3
 
 
+def test_fused_surrogate_projector_matches_stage_calls(fc):
+    """The surrogate projector walks, evaluates the network and sums the
+    groups in one kernel.  With every cell accepted (tiny input scale, one
+    optical-depth bin over everything) each ray that meets the phantom takes
+    the network, so the projection of a sampled angle must equal the sum over
+    groups of fcat_mlp_forward on that angle's fcat_pathlengths (the same
+    walk and the same network on the stage path), and a ray that misses the
+    phantom the unattenuated weight sum."""
+    import torch
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(5)
+    s = cfg.spectral
+    M, G = s.n_mat, s.n_groups
+    pb = fc.upload(cfg, scatter=False, psf=False)
+    rng = np.random.default_rng(5)
+    p = sg.init_params(M, G, 3)
+    p[-G:] = rng.normal(0, 0.05, size=G)
+    sur = fc.Surrogate(params=_t(torch, p), in_scale=_t(torch, np.full(M, 1.0 / 500.0, np.float32)),
+                       out_scale=_t(torch, rng.uniform(0.2, 2.0, size=G).astype(np.float32)),
+                       lin=fc.fcat_mlp_linear_term(pb.spectral), cell_ok=_t(torch, np.ones(M * 16, np.uint8)),
+                       cell_lo=0.0, cell_hi=1e30, counts=torch.zeros(2, dtype=torch.int32, device="cuda"))
+    out = fc.fcat_project(pb, mode="surrogate", surrogate=sur)
+    n_net, n_exact = (int(x) for x in sur.counts.cpu().numpy())
+    sur.counts = None
+    plane = cfg.geometry.nu * cfg.geometry.nv
+    w_all = float(np.sum(s.phi.astype(np.float64) * s.eta.astype(np.float64)))
+    hits = 0
+    for a in (0, 97, 400):
+        L = fc.fcat_pathlengths(pb, M, a, a + 1).reshape(plane, M)
+        yp = fc.fcat_mlp_forward(sur, pb.spectral, L).cpu().numpy().astype(np.float64)    # [G][plane]
+        hit = (L.sum(1) > 0).cpu().numpy()
+        hits += int(hit.sum())
+        o = out[a].reshape(-1).cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(o[hit], yp.sum(0)[hit], rtol=2e-6, atol=0)
+        np.testing.assert_allclose(o[~hit], w_all, rtol=2e-6)
+    assert n_exact == 0 and n_net > 0.5 * cfg.geometry.n_angles * plane
+    print(f"fused surrogate projector: {n_net} rays by the network, {n_exact} by the exact sum; "
+          f"{hits} hit rays on the sampled angles")
+
+
 def test_benchmarked_network_against_the_oracle(fc):
     """The network the benchmark reports (head workload, 4M pairs with 10%
     held out, 120 epochs, the build_surrogate defaults) projects within 1e-3
