@@ -92,6 +92,9 @@ def parse():
     ap.add_argument("--form-steps", type=int, default=3, help="timed steps of the extra forms and stages")
     ap.add_argument("--surrogate-samples", type=int, default=4_000_000)
     ap.add_argument("--surrogate-epochs", type=int, default=120)
+    ap.add_argument("--surrogate-fine", type=int, default=8,
+                    help="also time plain and surrogate projectors on the head spectrum cut into this many times "
+                         "finer bins (0 or 1 skips)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scale reference for HBM counters)")
     return ap.parse_args()
@@ -604,7 +607,54 @@ def form_surrogate(pb, cfg, plain, args, torch, fc, counts):
                      "train_seconds": round(rep.seconds, 2), "setup_seconds": round(t_build, 2),
                      "final_loss": rep.epoch_loss[-1], "validated_cells": int(rep.cell_ok.sum()),
                      "holdout_share_in_validated_cells": rep.holdout_in_ok_cells},
+        "fine_bins": surrogate_fine_bins(pb, cfg, args, torch, fc) if args.surrogate_fine > 1 else None,
     }
+
+
+def surrogate_fine_bins(pb, cfg, args, torch, fc):
+    """Plain and surrogate projectors on the head workload with the same
+    spectrum cut into args.surrogate_fine times finer bins: the exact sum's
+    cost grows with the number of bins, the network's does not.  The network
+    is trained anew on the finer spectrum, with the same sample count and
+    schedule."""
+    import dataclasses
+    import synth
+    from paper_2011_04736_amd import surrogate as sg
+    spec = synth.refine_spectral(cfg.spectral, args.surrogate_fine)
+    dev = pb.phantom.labels.device
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+    sp = fc.Spectral(f32(spec.mu), f32(spec.phi), f32(spec.eta), spec.n_groups, spec.group_of_bin)
+    pbf = dataclasses.replace(pb, spectral=sp)
+    g = cfg.geometry
+    ray_e = g.n_angles * g.nu * g.nv * spec.n_energy
+    K = args.form_steps
+    out_p = torch.empty((g.n_angles, g.nv, g.nu), dtype=torch.float32, device=dev)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pbf, "plain"), dtype=torch.uint8, device=dev)
+    t_plain, st_p = timed_steps(lambda: fc.fcat_project(pbf, mode="plain", out=out_p, workspace=ws), 1, K, torch)
+    del ws
+    sur, rep = sg.build_surrogate(pbf, n_samples=args.surrogate_samples, epochs=args.surrogate_epochs)
+    out = torch.empty_like(out_p)
+    ws = torch.empty(fc.fcat_project_workspace_bytes(pbf, "surrogate"), dtype=torch.uint8, device=dev)
+    sur.counts = torch.zeros(2, dtype=torch.int32, device=dev)
+    fc.fcat_project(pbf, mode="surrogate", surrogate=sur, out=out, workspace=ws)
+    n_net, n_exact = (int(x) for x in sur.counts.cpu().numpy())
+    sur.counts = None
+    t_sur, st_s = timed_steps(lambda: fc.fcat_project(pbf, mode="surrogate", surrogate=sur, out=out, workspace=ws),
+                              0, K, torch)
+    del ws
+    mx, rms = rel_errors(out, out_p, torch)
+    del out, out_p
+    torch.cuda.empty_cache()
+    return {"energy_bins": spec.n_energy, "steps": K,
+            "plain": {"value": ray_e * K / t_plain, "unit": "ray*E/s", "ms_per_step": 1e3 * t_plain / K,
+                      "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st_p.items() if v[1]}},
+            "surrogate": {"value": ray_e * K / t_sur, "unit": "ray*E/s", "ms_per_step": 1e3 * t_sur / K,
+                          "stages_ms_per_step": {k: round(v[0] / K, 3) for k, v in st_s.items() if v[1]},
+                          "max_rel_err_vs_plain": mx, "rms_rel_err_vs_plain": rms,
+                          "rays_by_network": n_net, "rays_by_exact_sum": n_exact,
+                          "validated_cells": int(rep.cell_ok.sum()),
+                          "holdout_share_in_validated_cells": rep.holdout_in_ok_cells},
+            "gain_vs_plain": t_plain / t_sur}
 
 
 # ------------------------------------------------------------------ main

@@ -155,7 +155,10 @@ typedef struct fcat_psf_t {
  * (argmax_m mbar_m L_m) * 16 + floor(16 (tau - cell_lo) / (cell_hi - cell_lo)),
  * tau = sum_m mbar_m L_m its mean optical depth.  The exact spectral sum is
  * used wherever the ray misses, some x_m > 1, tau is outside
- * [cell_lo, cell_hi), or cell_ok[cell] is 0.
+ * [cell_lo, cell_hi), or cell_ok[cell] is 0.  fcat_project takes the network
+ * only for groups of 64 neighbouring rays (one wavefront: an 8 x 8 or 16 x 4
+ * tile of detector pixels of one angle) whose hit rays all lie in the
+ * domain, and the exact sum for every ray of the other groups.
  */
 #define FCAT_MLP_HIDDEN 64
 #define FCAT_MLP_CELLS 16

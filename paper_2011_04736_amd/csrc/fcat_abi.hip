@@ -1663,7 +1663,7 @@ static hipError_t train_one(fcat_mlp_train_t *train, const SpecTables &t, MlpTab
     float *partial = at<float>(workspace, ml.partial);
     float *lp = at<float>(workspace, ml.loss_partial);
     StageTimer tm(FCAT_STAGE_MLP, stream);
-    hipError_t e = launch_mlp_prep(train->params, t.M, t.G, const_cast<uint4 *>(mt.frag), stream);
+    hipError_t e = launch_mlp_prep(train->params, t.M, t.G, const_cast<uint4 *>(mt.frag), stream, true);
     if (e == hipSuccess) e = launch_mlp_grad(t, mt, L, Yprim, n, order, base, count, partial, lp, stream);
     if (e == hipSuccess)
         e = launch_mlp_reduce_adam(partial, (count + kWave - 1) / kWave, ml.P, nullptr, train->params, train->adam_m,

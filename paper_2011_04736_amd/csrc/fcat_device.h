@@ -456,20 +456,34 @@ __device__ __forceinline__ float exp_neg(float P)
     return fmaf(-y * kLn2, c, y);
 }
 
+// A read-only table seen through the constant address space.  The compiler
+// then loads its wave-uniform entries once per wavefront (scalar loads)
+// even after an LDS fence, a wave barrier, an asm statement or a store it
+// cannot prove disjoint from the table, any of which otherwise turns them
+// into one load per lane.  Only for data that no kernel of the launch
+// writes (the spectral tables and the network's terms).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *const_table(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3)
 template <int MP>
 __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTables &T, int e0, int e1)
 {
+    const auto *mu = const_table(T.muT);
+    const auto *w = const_table(T.w);
     float acc = 0.0f;
     // two bins per iteration: their table loads issue together and their
     // chains of FMAs interleave
 #pragma unroll 2
     for (int e = e0; e < e1; ++e) {
-        const float *mrow = T.muT + e * MP;
+        const auto *mrow = mu + e * MP;
         float P = 0.0f;
 #pragma unroll
         for (int m = 0; m < MP; ++m) P = fmaf(mrow[m], L[m], P);
-        acc = fmaf(T.w[e], exp_neg(P), acc);
+        acc = fmaf(w[e], exp_neg(P), acc);
     }
     return acc;
 }

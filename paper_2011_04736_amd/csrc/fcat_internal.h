@@ -110,7 +110,8 @@ struct SplitTables {
 
 // Surrogate network tables (fcat_mlp.hip).  frag holds the BF16 B-operand
 // fragments of every weight view the forward and backward passes use.
-constexpr int kMlpFrags = 68;
+constexpr int kMlpFrags = 69;
+constexpr int kMlpTrainFrags = 40;
 struct MlpTables {
     const uint4 *frag;             // [kMlpFrags][64]
     const float *params;           // FP32 master parameters (biases read from here)
@@ -145,7 +146,10 @@ struct SurrogateIO {
 };
 
 int mlp_param_count(int n_in, int n_out);
-hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag, hipStream_t stream);
+// BF16 fragment views of the network's weights: all kMlpFrags of them, or
+// with training only the first kMlpTrainFrags (those the gradient kernel reads).
+hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag, hipStream_t stream,
+                           bool training = false);
 hipError_t launch_mlp_linear(const float *mu, const SpecTables &t, float *lin, hipStream_t stream);
 hipError_t launch_mlp_mbar(const SpecTables &t, const float *lin, float *mbar, hipStream_t stream);
 hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *mbar, const float *L, const float *Y,

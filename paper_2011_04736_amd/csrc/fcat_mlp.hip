@@ -52,7 +52,12 @@ constexpr int kFragW3i = 48;   // [kb 0..1]          W3_hi[n][chained_unit(kb, q
 constexpr int kFragW3iLo = 50; // [kb 0..1]          lo part
 constexpr int kFragW2c = 52;   // [ht 0..3][kb 0..1] W2_hi[16 ht + r][chained_unit(kb, q, j)]
 constexpr int kFragW2cLo = 60; // [ht 0..3][kb 0..1] lo part
-static_assert(kFragW2cLo + 8 == kMlpFrags, "fragment table size");
+// The biases as the forward pass adds them, FP32: lane l holds entries
+// 4 l .. 4 l + 3 of [log2(e) b1 (64) | log2(e) b2 (64) | b3 (n_out), zeros].
+constexpr int kFragBias = 68;
+constexpr int kBiasB2 = 64, kBiasB3 = 128;
+static_assert(kFragBias + 1 == kMlpFrags, "fragment table size");
+static_assert(kFragW1i == kMlpTrainFrags, "the training kernel reads the views before the inference views");
 constexpr float kLog2e = 1.4426950408889634f;
 
 // Hidden unit behind k index 8 q + j of the 32-wide block kb when a layer's
@@ -156,10 +161,10 @@ __device__ __forceinline__ void silu_pack(const floatx4 (&acc)[4], bf16x8 (&bh)[
     }
 }
 
-__device__ __forceinline__ floatx4 bias4(const float *b, float scale)
+// Four consecutive entries of the bias fragment, from entry i (a multiple of 4).
+__device__ __forceinline__ floatx4 bias4(const uint4 *frag, int i)
 {
-    const float4 v = *reinterpret_cast<const float4 *>(b);
-    return floatx4{scale * v.x, scale * v.y, scale * v.z, scale * v.w};
+    return __builtin_bit_cast(floatx4, frag[kFragBias * kWave + i / 4]);
 }
 
 // Forward pass of the rays of the wavefront, one 16-ray tile (lanes
@@ -182,8 +187,6 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int q = lane >> 4, r16 = lane & 15;
-    const Offsets off = param_offsets(M.n_in, M.n_out);
-    const float *P = M.params;
     {
         uint32_t hi[8], lo[8];
 #pragma unroll
@@ -198,17 +201,19 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
     for (int ct = 0; ct < 4; ++ct) {
         if (!((tiles >> ct) & 1u)) continue;
         const int row = 16 * ct + r16;
-        // the fragment table's address, made opaque per tile: otherwise its
-        // loads are hoisted out of the loop and their 112 registers held
-        // through it (and through the walk it is fused with)
-        const uint4 *frag = M.frag;
-        asm volatile("" : "+s"(frag));
+        // a zero the compiler cannot see through, added to the fragment
+        // table's address per tile: otherwise the table's loads are hoisted
+        // out of the loop and their 112 registers held through it (and
+        // through the walk it is fused with)
+        int opaque = 0;
+        asm volatile("" : "+s"(opaque));
+        const uint4 *frag = M.frag + opaque;
         // layer 1: Z1 = W1_hi (x_hi + x_lo) + W1_lo x_hi + b1
         const bf16x8 bx = *reinterpret_cast<const bf16x8 *>(rows + infer_chunk(row, q));
         floatx4 acc[4];
 #pragma unroll
         for (int ht = 0; ht < 4; ++ht) {
-            acc[ht] = bias4(P + off.b1 + 16 * ht + 4 * q, kLog2e);
+            acc[ht] = bias4(frag, 16 * ht + 4 * q);
             acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(frag, kFragW1i + ht, lane), bx, acc[ht], 0, 0,
                                                               0);
             acc[ht] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag_of(frag, kFragW1iLo + ht, lane), bx, acc[ht], 0,
@@ -219,7 +224,7 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
         // layer 2: Z2 = W2_hi (H1_hi + H1_lo) + W2_lo H1_hi + b2
 #pragma unroll
         for (int ht = 0; ht < 4; ++ht) {
-            acc[ht] = bias4(P + off.b2 + 16 * ht + 4 * q, kLog2e);
+            acc[ht] = bias4(frag, kBiasB2 + 16 * ht + 4 * q);
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb) {
                 const bf16x8 wh = frag_of(frag, kFragW2c + ht * 2 + kb, lane);
@@ -231,8 +236,7 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
         }
         silu_pack(acc, hh, hl);
         // layer 3: outputs 4 q .. 4 q + 3 of the tile's ray r16
-        floatx4 o = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (4 * q < M.n_out) o = bias4(P + off.b3 + 4 * q, 1.0f);
+        floatx4 o = bias4(frag, kBiasB3 + 4 * q);
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
             const bf16x8 wh = frag_of(frag, kFragW3i + kb, lane);
@@ -256,13 +260,26 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
 __device__ __forceinline__ float hi_part(float v) { return bf16_value(bf16_rne(v)); }
 
 __global__ __launch_bounds__(kBlock) void k_mlp_prep(const float *__restrict__ params, int n_in, int n_out,
-                                                     uint4 *__restrict__ frag)
+                                                     uint4 *__restrict__ frag, int n_frags)
 {
     const int idx = blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= kMlpFrags * kWave) return;
+    if (idx >= n_frags * kWave) return;
     const int fi = idx / kWave, lane = idx % kWave;
     const int q = lane >> 4, r16 = lane & 15;
     const Offsets off = param_offsets(n_in, n_out);
+    if (fi == kFragBias) {
+        float b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 4 * lane + c;
+            b[c] = i < kBiasB2 ? kLog2e * params[off.b1 + i]
+                 : i < kBiasB3 ? kLog2e * params[off.b2 + i - kBiasB2]
+                 : i < kBiasB3 + n_out ? params[off.b3 + i - kBiasB3] : 0.0f;
+        }
+        frag[idx] = make_uint4(__float_as_uint(b[0]), __float_as_uint(b[1]), __float_as_uint(b[2]),
+                               __float_as_uint(b[3]));
+        return;
+    }
     // the first-layer inference views are the W1 views of scaled weights
     int f = fi;
     float scale = 1.0f;
@@ -431,13 +448,13 @@ __global__ __launch_bounds__(kBlock) void k_mlp_spectral(SpecTables T, MlpTables
 }
 
 // The surrogate projector in one pass: the walk of k_project_rows, then,
-// for the rays whose cell the held-out validation accepted, the network on
-// the matrix cores, and the exact spectral sum for the rest; scatter and
-// group signals as in k_project_rows.  The path lengths stay in registers.
+// for the wavefronts whose rays all lie in cells the held-out validation
+// accepted, the network on the matrix cores, and the exact spectral sum for
+// the rest; scatter and group signals as in k_project_rows.  The path lengths stay in registers.
 // The walk's LDS block of each wavefront is reused for the network's
-// input/output rows once the walk is done, so the network costs the walk
-// no occupancy; its weights are read from the fragment table (L2-resident,
-// 68 KiB), since LDS for a copy per workgroup would cap the walk at four
+// input/output rows once the walk is done, so the network needs no LDS of
+// its own; its weights are read from the fragment table (L2-resident,
+// 69 KiB), since LDS for a copy per workgroup would cap the walk at four
 // wavefronts per SIMD.
 template <int MP>
 constexpr int fused_wave_floats()
@@ -446,14 +463,17 @@ constexpr int fused_wave_floats()
     return a > kInferLdsBytes / 4 ? a : kInferLdsBytes / 4;
 }
 
-// Wavefronts per SIMD the walk's LDS block allows (8 at most): the fused
-// kernel is compiled to that occupancy, so the network's registers never
-// cost the walk occupancy (a few values spill around the network instead).
+// Occupancy the fused kernel is compiled to: what the walk's LDS block
+// allows, at most 6 wavefronts per SIMD.  On the head workload with every
+// hit ray on the network the kernel took 89.7 ms at 8 (64 registers, a few
+// values spilled around the network), 87.9 at 6, 99.7 at 5 and 111.5 at 4
+// (the plain walk: 66.3): the network's fragment loads wait on L2 one or two
+// at a time whatever the register budget, and more wavefronts hide that.
 template <int MP>
 constexpr int fused_waves_per_simd()
 {
     constexpr int per_cu = (160 * 1024) / ((kBlock / kWave) * fused_wave_floats<MP>() * 4) * (kBlock / kWave);
-    return per_cu / 4 < 8 ? per_cu / 4 : 8;
+    return per_cu / 4 < 6 ? per_cu / 4 : 6;
 }
 
 template <int MP>
@@ -482,7 +502,6 @@ void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
     trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, block, L);
-    const bool any_hit = __ballot(hit) != 0;
 
     float L16[16], x[16];
 #pragma unroll
@@ -490,20 +509,23 @@ void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
         L16[m] = m < MP ? L[m] : 0.0f;
         x[m] = m < M.n_in ? __fmul_rn(L16[m], M.in_scale[m]) : 0.0f;
     }
-    const bool use = hit && in_domain(L16, x, M);
+    // The network is taken wavefront by wavefront: only where every ray of
+    // the wavefront that meets the phantom lies in a validated cell.  A
+    // wavefront with one ray outside them takes the exact sum for all its
+    // rays (never less accurate), since its lanes run in lockstep and would
+    // otherwise pay for both the network and the exact sum.
+    // (both ballots run in every lane: inside a short-circuit && the second
+    // would see only the lanes already accepted)
+    const bool ok = hit && in_domain(L16, x, M);
+    const uint64_t outside = __ballot(hit && !ok);
+    const bool use = ok && outside == 0;
     const uint64_t use_mask = __ballot(use);
     uint8_t *rows = reinterpret_cast<uint8_t *>(block);
     if (use_mask != 0) {
         wave_sync_lds();      // the walk's sums have been read: the block becomes the network's rows
         mlp_infer_wave(x, M, rows, tile_mask(use_mask));
     }
-    if (counts) {
-        const uint64_t hit_mask = __ballot(hit);
-        if (lane == 0) {
-            atomicAdd(counts + 0, (int)__popcll(use_mask));
-            atomicAdd(counts + 1, (int)__popcll(hit_mask & ~use_mask));
-        }
-    }
+    const uint64_t hit_mask = __ballot(hit), valid_mask = __ballot(valid);
     if (!valid) return;
 
     const int64_t plane = (int64_t)G.nu * G.nv;
@@ -511,24 +533,41 @@ void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
     const float i0 = flood ? flood[pix] : 1.0f;
     const float sc = scatter ? scatter[(int64_t)a * plane + pix] : 0.0f;
     float total = 0.0f;
-    for (int g = 0; g < T.G; ++g) {
-        float prim;
-        if (use) {
-            float z = M.out_scale[g] * mlp_out(rows, lane, g);
-#pragma unroll
-            for (int m = 0; m < MP; ++m)
-                if (m < T.M) z = fmaf(M.lin[g * T.M + m], L[m], z);
-            prim = T.Wg[g] * expf(-z);
-        } else {
-            prim = any_hit ? group_sum<MP>(L, T, T.gstart[g], T.gstart[g + 1]) : T.Wg[g];
-        }
-        const float y = fmaf(i0, prim, T.Wsg[g] * sc);
+    const auto *Wg = const_table(T.Wg), *Wsg = const_table(T.Wsg);
+    const auto *lin = const_table(M.lin), *out_scale = const_table(M.out_scale);
+    auto emit = [&](int g, float prim) {
+        const float y = fmaf(i0, prim, Wsg[g] * sc);
         if (Y)
             Y[((int64_t)al * T.G + g) * plane + pix] = y;
         else
             total += y;
+    };
+    // Two loops on a wavefront-uniform choice; the exact one is the plain
+    // projector's.
+    if (use_mask != 0) {
+        for (int g = 0; g < T.G; ++g) {
+            float prim = Wg[g];
+            if (use) {
+                float z = out_scale[g] * mlp_out(rows, lane, g);
+#pragma unroll
+                for (int m = 0; m < MP; ++m)
+                    if (m < T.M) z = fmaf(lin[g * T.M + m], L[m], z);
+                prim *= expf(-z);
+            }
+            emit(g, prim);
+        }
+    } else {
+        const bool any_hit = hit_mask != 0;
+        for (int g = 0; g < T.G; ++g)
+            emit(g, any_hit ? group_sum<MP>(L, T, T.gstart[g], T.gstart[g + 1]) : Wg[g]);
     }
     if (!Y) out[(int64_t)a * plane + pix] = total;
+    // after the last table read, as flag_nonfinite: a store before them would
+    // turn the tables' wave-uniform scalar loads into per-lane vector loads
+    if (counts && lane == __ffsll((unsigned long long)valid_mask) - 1) {
+        atomicAdd(counts + 0, (int)__popcll(use_mask));
+        atomicAdd(counts + 1, (int)__popcll(hit_mask & ~use_mask));
+    }
     flag_nonfinite(G.bad, i0, sc);
 }
 
@@ -862,6 +901,13 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
 // grad[p] = sum_w partial[w][p]; optionally the Adam update of params
 // (Kingma & Ba 2015, Algorithm 1) with bias correction for step t; loss_out
 // (if given) receives sum_w loss_partial[w] * loss_scale.
+// grad[p] = sum over the gradient partials, in a fixed order: wavefront i
+// of a workgroup sums partials i, i + 4, i + 8, ... of the workgroup's 64
+// parameters (coalesced rows), then the four sums are added in wavefront
+// order; an Adam step follows where params is given.  Deterministic, and
+// spread over P / 64 workgroups with chains a quarter as long as one sum
+// per parameter.
+constexpr int kReduceWaves = kBlock / kWave;
 __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float *__restrict__ partial, int nparts, int P,
                                                             float *__restrict__ grad, float *__restrict__ params,
                                                             float *__restrict__ m, float *__restrict__ v, int step,
@@ -869,15 +915,22 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float *__restr
                                                             const float *__restrict__ loss_partial, float loss_scale,
                                                             float *__restrict__ loss_out)
 {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p == 0 && loss_out) {
+    __shared__ float sums[kReduceWaves][kWave];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    const int p = blockIdx.x * kWave + lane;
+    float g = 0.0f;
+    if (p < P)
+        for (int w = wave; w < nparts; w += kReduceWaves) g += partial[(int64_t)w * P + p];
+    sums[wave][lane] = g;
+    __syncthreads();
+    if (wave != 0) return;
+    if (blockIdx.x == 0 && lane == 0 && loss_out) {
         float l = 0.0f;
         for (int w = 0; w < nparts; ++w) l += loss_partial[w];
         *loss_out = l * loss_scale;
     }
     if (p >= P) return;
-    float g = 0.0f;
-    for (int w = 0; w < nparts; ++w) g += partial[(int64_t)w * P + p];
+    g = (sums[0][lane] + sums[1][lane]) + (sums[2][lane] + sums[3][lane]);
     if (grad) grad[p] = g;
     if (params) {
         const float mt = beta1 * m[p] + (1.0f - beta1) * g;
@@ -1061,10 +1114,11 @@ __global__ void k_mlp_cells(const unsigned *__restrict__ err_bits, const int *__
 
 int mlp_param_count(int n_in, int n_out) { return param_offsets(n_in, n_out).P; }
 
-hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag, hipStream_t stream)
+hipError_t launch_mlp_prep(const float *params, int n_in, int n_out, uint4 *frag, hipStream_t stream, bool training)
 {
-    hipLaunchKernelGGL(k_mlp_prep, dim3((kMlpFrags * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, params,
-                       n_in, n_out, frag);
+    const int nf = training ? kMlpTrainFrags : kMlpFrags;
+    hipLaunchKernelGGL(k_mlp_prep, dim3((nf * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, params,
+                       n_in, n_out, frag, nf);
     return hipGetLastError();
 }
 
@@ -1142,7 +1196,8 @@ hipError_t launch_mlp_reduce_adam(const float *partial, int nparts, int P, float
                                   float *v, int step, float lr, float beta1, float beta2, float eps,
                                   const float *loss_partial, float loss_scale, float *loss_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((P + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, partial, nparts, P,
+    static_assert(kReduceWaves == 4, "the four partial sums are added in a fixed order");
+    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((P + kWave - 1) / kWave), dim3(kBlock), 0, stream, partial, nparts, P,
                        grad, params, m, v, step, lr, beta1, beta2, eps, loss_partial, loss_scale, loss_out);
     return hipGetLastError();
 }
