@@ -898,15 +898,13 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
     if (lane == 0) loss_partial[blockIdx.x] = lsum;
 }
 
-// grad[p] = sum_w partial[w][p]; optionally the Adam update of params
-// (Kingma & Ba 2015, Algorithm 1) with bias correction for step t; loss_out
-// (if given) receives sum_w loss_partial[w] * loss_scale.
 // grad[p] = sum over the gradient partials, in a fixed order: wavefront i
 // of a workgroup sums partials i, i + 4, i + 8, ... of the workgroup's 64
 // parameters (coalesced rows), then the four sums are added in wavefront
-// order; an Adam step follows where params is given.  Deterministic, and
-// spread over P / 64 workgroups with chains a quarter as long as one sum
-// per parameter.
+// order.  Deterministic, and spread over P / 64 workgroups with chains a
+// quarter as long as one sum per parameter.  Where params is given, the
+// Adam update (Kingma & Ba 2015, Algorithm 1) with bias correction for step
+// t follows; loss_out (if given) receives sum_w loss_partial[w] * loss_scale.
 constexpr int kReduceWaves = kBlock / kWave;
 __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float *__restrict__ partial, int nparts, int P,
                                                             float *__restrict__ grad, float *__restrict__ params,
