@@ -742,10 +742,32 @@ def main():
     torch.cuda.empty_cache()
 
     # secondary workloads; the contrast one also carries the split form of
-    # its own configuration and the stages after the projector
+    # its own configuration and the stages after the projector (run on it
+    # as well when it is the primary workload)
     result["workloads"] = {}
     result["next"] = {}
     result["stages"] = {}
+
+    def contrast_stages(p2, c2, walk):
+        if args.spectral:
+            result["stages"]["spectral"] = spectral_stage(p2, c2, args, torch, fc)
+        if args.noise_counts > 0:
+            result["next"]["noise_and_projections"] = noise_stage(p2, c2, args, torch, fc)
+        if args.dose:
+            result["next"]["dose"] = dose_stage(p2, c2, args, torch, fc, walk["hit_rays"])
+        if args.fdk:
+            result["next"]["fdk"] = fdk_stage(p2, c2, args, torch, fc)
+        if args.image_projector:
+            result["next"]["image_projector"] = image_projector_stage(p2, c2, args, torch, fc, walk)
+        if args.rl_iterations > 0:
+            result["next"]["optics"] = optics_stage(p2, c2, args, torch, fc)
+
+    if args.workload == "contrast":
+        pb = fc.upload(cfg, device=dev)
+        contrast_stages(pb, cfg, counts)
+        progress("contrast: the stages after the projector")
+        del pb
+        torch.cuda.empty_cache()
     for name in [w for w in args.secondary.split(",") if w and w != args.workload]:
         n2, var2, _ = WORKLOADS[name]
         c2 = synth.make_config(n2, variant=var2)
@@ -759,18 +781,7 @@ def main():
                                                                  entry["walk"])
             del o2
             torch.cuda.empty_cache()
-            if args.spectral:
-                result["stages"]["spectral"] = spectral_stage(p2, c2, args, torch, fc)
-            if args.noise_counts > 0:
-                result["next"]["noise_and_projections"] = noise_stage(p2, c2, args, torch, fc)
-            if args.dose:
-                result["next"]["dose"] = dose_stage(p2, c2, args, torch, fc, entry["walk"]["hit_rays"])
-            if args.fdk:
-                result["next"]["fdk"] = fdk_stage(p2, c2, args, torch, fc)
-            if args.image_projector:
-                result["next"]["image_projector"] = image_projector_stage(p2, c2, args, torch, fc, entry["walk"])
-            if args.rl_iterations > 0:
-                result["next"]["optics"] = optics_stage(p2, c2, args, torch, fc)
+            contrast_stages(p2, c2, entry["walk"])
             progress(f"{name}: split form and the stages after the projector")
         del p2
         torch.cuda.empty_cache()
