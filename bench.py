@@ -142,11 +142,12 @@ def profiled_counters(kernel: str, digest: str, workload: str) -> dict:
     if not os.path.exists(path):
         return {}
     text = open(path).read()
-    m = re.search(r"^sources:\s*(\S+)", text, re.M)
-    if not m or m.group(1) != digest:
-        return {}
     for b in re.split(r"\n(?=\S)", text):
-        if b.startswith(kernel):
+        # the kernel's block: its name, then a template list, a space or an argument list
+        if re.match(re.escape(kernel) + r"[<\s(]", b):
+            m = re.search(r"^\s*sources:\s*(\S+)", b, re.M)
+            if not m or m.group(1) != digest:
+                return {}
             out = {}
             for key, name in (("VALU issue rate", "valu_issue_vs_16_lane_rate"), ("MFMA busy", "mfma_busy"),
                               ("L2 hit rate", "l2_hit"), ("LDS bank-conflict share", "lds_bank_conflict_share"),
