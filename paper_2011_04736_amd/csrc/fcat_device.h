@@ -354,6 +354,14 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
         const float tco = fminf(tc[0], fminf(tc[1], tc[2]));
         const bool last = !(tco < t_end) || --budget < 0;
         const float T_out = last ? t_end : tco;
+        // the next brick and its map entry, loaded here so that the load's
+        // latency passes under this brick's work (after the last brick the
+        // clamped index reads an entry that is not used)
+        const bool bx = (tc[0] == tco);
+        const bool ty = (tc[1] == tco);
+        const int dbyz = ty ? db1 : db2;
+        const int blin_next = blin + (bx ? db0 : dbyz);
+        const int bl_next = bricks[min(max(blin_next, 0), last_brick)];
         if (bl >= 0) {
             if (static_cast<unsigned>(bl) != cur) {
                 acc.add(cur, T_in - run);
@@ -410,12 +418,9 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
         if (last) {
             active = false;
         } else {
-            const bool bx = (tc[0] == tco);
-            const bool ty = (tc[1] == tco);
             const bool by = !bx && ty;
             const bool bz = !bx && !ty;
-            const int dbyz = ty ? db1 : db2;
-            blin += bx ? db0 : dbyz;
+            blin = blin_next;
             bc[0] += bx ? r.sgn[0] : 0;
             bc[1] += by ? r.sgn[1] : 0;
             bc[2] += bz ? r.sgn[2] : 0;
@@ -426,7 +431,7 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
             tc[1] = fmaf(kc[1], r.dtc[1], r.tc0[1]);
             tc[2] = fmaf(kc[2], r.dtc[2], r.tc0[2]);
             T_in = tco;
-            bl = bricks[min(max(blin, 0), last_brick)];
+            bl = bl_next;
         }
     }
     acc.add(cur, t_end - run);
