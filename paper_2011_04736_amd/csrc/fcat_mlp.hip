@@ -584,54 +584,70 @@ struct TrainLds {
     float Wt[kWave * SO];        // loss weights [sample][o]
 };
 
-// Forward + backward of one 64-sample tile per workgroup (one wavefront).
+// Forward + backward of one 64-sample tile per workgroup of four wavefronts.
 // Samples order[base + i], i < count; the loss is the mean over `count`
 // samples and n_out outputs of omega (s f - r)^2, with r the residual
 // target, s = out_scale and omega = min(1, Y_g / (1e-3 sum_g Y_g))^2.  Writes
 // the gradient partial of the tile to partial[blockIdx.x][P] and its loss
 // sum to loss_partial[blockIdx.x].
-__global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, const float *__restrict__ Lin,
-                                                    const float *__restrict__ Yin, int64_t n_all,
-                                                    const int32_t *__restrict__ order, int64_t base, int count,
-                                                    float *__restrict__ partial, float *__restrict__ loss_partial)
+//
+// Wavefront w takes the tile's samples 16 w .. 16 w + 15 (row tile w of
+// every sample-major array) through the three layers and back; the
+// weight gradients, which sum over all 64 samples, are then split by output
+// tile: wavefront w forms tile w of dW3, row tile w of dW2 and of dW1, with
+// the same products in the same order as over the whole tile.  The four
+// wavefronts' bias and loss sums are added in wavefront order, so training
+// stays deterministic.
+constexpr int kGradWaves = 4;
+__global__ __launch_bounds__(kGradWaves * kWave) void k_mlp_grad(SpecTables T, MlpTables M, const float *__restrict__ Lin,
+                                                                 const float *__restrict__ Yin, int64_t n_all,
+                                                                 const int32_t *__restrict__ order, int64_t base,
+                                                                 int count, float *__restrict__ partial,
+                                                                 float *__restrict__ loss_partial)
 {
     __shared__ __align__(16) TrainLds S;
-    const int lane = threadIdx.x;
+    constexpr int kRedB2 = 64, kRedB3 = 128, kRedLoss = 144;
+    __shared__ float red[kGradWaves][kRedLoss + 1];   // per wavefront: db1 [64], db2 [64], db3 [16], loss
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & (kWave - 1);
     const int q = lane >> 4, r16 = lane & 15;
+    const int rt = wave;                 // this wavefront's row tile of samples
     const Offsets off = param_offsets(M.n_in, M.n_out);
     const float *P = M.params;
     const int n_in = M.n_in, n_out = M.n_out;
-    const int local = blockIdx.x * kWave + lane;
-    const bool valid = local < count;
-    const int64_t s = valid ? (int64_t)(order ? order[base + local] : base + local) : 0;
     const float inv_n = 1.0f / ((float)count * (float)n_out);
 
-    // inputs and residual targets r_g = -ln(Y_g / W_g) - sum_m lin[g][m] L_m
-    float L[16], x[16];
+    if (wave == 0) {
+        // inputs and residual targets r_g = -ln(Y_g / W_g) - sum_m lin[g][m] L_m,
+        // one sample per lane
+        const int local = blockIdx.x * kWave + lane;
+        const bool valid = local < count;
+        const int64_t s = valid ? (int64_t)(order ? order[base + local] : base + local) : 0;
+        float L[16], x[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        L[m] = (valid && m < n_in) ? Lin[s * n_in + m] : 0.0f;
-        x[m] = m < n_in ? L[m] * M.in_scale[m] : 0.0f;
-    }
-    float ysum = 0.0f;
-    for (int g = 0; g < n_out; ++g) ysum += valid ? Yin[(int64_t)g * n_all + s] : 0.0f;
-    for (int g = 0; g < 16; ++g) {
-        float t = 0.0f, om = 0.0f;
-        if (valid && g < n_out) {
-            const float y = Yin[(int64_t)g * n_all + s];
-            const float f = fminf(1.0f, y / (kMlpShareFloor * ysum));
-            if (f > 0.0f) {                    // y > 0: the target is finite
-                t = -logf(y / T.Wg[g]);
-#pragma unroll
-                for (int m = 0; m < 16; ++m)
-                    if (m < n_in) t -= M.lin[g * n_in + m] * L[m];
-                om = f * f;
-            }
+        for (int m = 0; m < 16; ++m) {
+            L[m] = (valid && m < n_in) ? Lin[s * n_in + m] : 0.0f;
+            x[m] = m < n_in ? L[m] * M.in_scale[m] : 0.0f;
         }
-        S.Tg[lane * SO + g] = t;
-        S.Wt[lane * SO + g] = om;
-    }
-    {   // row = [x_hi (16) | x_lo (16)]; the transpose keeps x_hi for dW1
+        float ysum = 0.0f;
+        for (int g = 0; g < n_out; ++g) ysum += valid ? Yin[(int64_t)g * n_all + s] : 0.0f;
+        for (int g = 0; g < 16; ++g) {
+            float t = 0.0f, om = 0.0f;
+            if (valid && g < n_out) {
+                const float y = Yin[(int64_t)g * n_all + s];
+                const float f = fminf(1.0f, y / (kMlpShareFloor * ysum));
+                if (f > 0.0f) {                    // y > 0: the target is finite
+                    t = -logf(y / T.Wg[g]);
+#pragma unroll
+                    for (int m = 0; m < 16; ++m)
+                        if (m < n_in) t -= M.lin[g * n_in + m] * L[m];
+                    om = f * f;
+                }
+            }
+            S.Tg[lane * SO + g] = t;
+            S.Wt[lane * SO + g] = om;
+        }
+        // row = [x_hi (16) | x_lo (16)]; the transpose keeps x_hi for dW1
         uint32_t hi[8], lo[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) split_bf16x2(x[2 * k], x[2 * k + 1], hi[k], lo[k]);
@@ -646,92 +662,77 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
             S.XT[(2 * k + 1) * SH + lane] = (uint16_t)(hi[k] >> 16);
         }
     }
-    wave_sync_lds();
+    __syncthreads();
     uint16_t *const Hlo = S.D1T;     // lo parts of H1, then of H2 (D1T is free until the backward pass)
 
-    // ---- forward
-    floatx4 Z1[4][4], Z2[4][4], acc[4][4];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    // ---- forward, samples of row tile rt
+    floatx4 Z1[4], Z2[4], acc[4];
+    {
         const bf16x8 a = lds_frag(S.X, SX, 16 * rt + r16, 8 * q);
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-            Z1[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1 + ct, lane),
-                                                                 floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-            Z1[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1lo + ct, lane),
-                                                                 Z1[rt][ct], 0, 0, 0);
+            Z1[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1 + ct, lane),
+                                                             floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            Z1[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW1lo + ct, lane), Z1[ct], 0, 0, 0);
         }
     }
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const float b = P[off.b1 + 16 * ct + r16];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                Z1[rt][ct][i] += b;
-                const float hv = silu(Z1[rt][ct][i]);
-                const uint32_t hb = bf16_rne(hv);
-                const uint16_t h = (uint16_t)hb;
-                const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
-                S.H1[row * SH + col] = h;
-                S.H1T[col * SH + row] = h;
-                Hlo[row * SH + col] = (uint16_t)bf16_rne(hv - bf16_value(hb));
-            }
+        for (int i = 0; i < 4; ++i) {
+            Z1[ct][i] += b;
+            const float hv = silu(Z1[ct][i]);
+            const uint32_t hb = bf16_rne(hv);
+            const uint16_t h = (uint16_t)hb;
+            const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
+            S.H1[row * SH + col] = h;
+            S.H1T[col * SH + row] = h;
+            Hlo[row * SH + col] = (uint16_t)bf16_rne(hv - bf16_value(hb));
+        }
     }
     wave_sync_lds();
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int ct = 0; ct < 4; ++ct) Z2[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) Z2[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < 2; ++kb) {
+        const bf16x8 a = lds_frag(S.H1, SH, 16 * rt + r16, 32 * kb + 8 * q);
+        const bf16x8 al = lds_frag(Hlo, SH, 16 * rt + r16, 32 * kb + 8 * q);
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 a = lds_frag(S.H1, SH, 16 * rt + r16, 32 * kb + 8 * q);
-            const bf16x8 al = lds_frag(Hlo, SH, 16 * rt + r16, 32 * kb + 8 * q);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
-                const bf16x8 wh = frag_of(M.frag, kFragW2 + ct * 2 + kb, lane);
-                Z2[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wh, Z2[rt][ct], 0, 0, 0);
-                Z2[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, Z2[rt][ct], 0, 0, 0);
-                Z2[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, frag_of(M.frag, kFragW2lo + ct * 2 + kb, lane), Z2[rt][ct], 0, 0, 0);
-            }
+        for (int ct = 0; ct < 4; ++ct) {
+            const bf16x8 wh = frag_of(M.frag, kFragW2 + ct * 2 + kb, lane);
+            Z2[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wh, Z2[ct], 0, 0, 0);
+            Z2[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, Z2[ct], 0, 0, 0);
+            Z2[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW2lo + ct * 2 + kb, lane), Z2[ct],
+                                                             0, 0, 0);
         }
+    }
     wave_sync_lds();
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const float b = P[off.b2 + 16 * ct + r16];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                Z2[rt][ct][i] += b;
-                const float hv = silu(Z2[rt][ct][i]);
-                const uint32_t hb = bf16_rne(hv);
-                const uint16_t h = (uint16_t)hb;
-                const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
-                S.H2[row * SH + col] = h;
-                S.H2T[col * SH + row] = h;
-                Hlo[row * SH + col] = (uint16_t)bf16_rne(hv - bf16_value(hb));
-            }
+        for (int i = 0; i < 4; ++i) {
+            Z2[ct][i] += b;
+            const float hv = silu(Z2[ct][i]);
+            const uint32_t hb = bf16_rne(hv);
+            const uint16_t h = (uint16_t)hb;
+            const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
+            S.H2[row * SH + col] = h;
+            S.H2T[col * SH + row] = h;
+            Hlo[row * SH + col] = (uint16_t)bf16_rne(hv - bf16_value(hb));
+        }
     }
     wave_sync_lds();
-    floatx4 o3[4];
+    floatx4 o3 = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        o3[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 a = lds_frag(S.H2, SH, 16 * rt + r16, 32 * kb + 8 * q);
-            const bf16x8 al = lds_frag(Hlo, SH, 16 * rt + r16, 32 * kb + 8 * q);
-            const bf16x8 wh = frag_of(M.frag, kFragW3 + kb, lane);
-            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wh, o3[rt], 0, 0, 0);
-            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, o3[rt], 0, 0, 0);
-            o3[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW3lo + kb, lane), o3[rt], 0, 0,
-                                                             0);
-        }
+    for (int kb = 0; kb < 2; ++kb) {
+        const bf16x8 a = lds_frag(S.H2, SH, 16 * rt + r16, 32 * kb + 8 * q);
+        const bf16x8 al = lds_frag(Hlo, SH, 16 * rt + r16, 32 * kb + 8 * q);
+        const bf16x8 wh = frag_of(M.frag, kFragW3 + kb, lane);
+        o3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wh, o3, 0, 0, 0);
+        o3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, wh, o3, 0, 0, 0);
+        o3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW3lo + kb, lane), o3, 0, 0, 0);
     }
     wave_sync_lds();
 
@@ -740,141 +741,68 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
     const float osc = r16 < n_out ? M.out_scale[r16] : 0.0f;
     float lsum = 0.0f, db3 = 0.0f;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 16 * rt + 4 * q + i;
-            const bool live = r16 < n_out && (int)(blockIdx.x * kWave + row) < count;
-            const float om = live ? S.Wt[row * SO + r16] : 0.0f;
-            const float d = live ? osc * (o3[rt][i] + b3) - S.Tg[row * SO + r16] : 0.0f;
-            lsum += om * d * d;
-            const float g = 2.0f * om * d * osc * inv_n;
-            db3 += g;
-            const uint16_t gb = (uint16_t)bf16_rne(g);
-            S.X[row * SX + r16] = gb;            // dZ3 [sample][o], o < 16
-            S.X[row * SX + 16 + r16] = 0;        // K padding up to 32
-            S.D3T[r16 * SH + row] = gb;          // dZ3 transposed [o][sample]
-        }
+    for (int i = 0; i < 4; ++i) {
+        const int row = 16 * rt + 4 * q + i;
+        const bool live = r16 < n_out && (int)(blockIdx.x * kWave + row) < count;
+        const float om = live ? S.Wt[row * SO + r16] : 0.0f;
+        const float d = live ? osc * (o3[i] + b3) - S.Tg[row * SO + r16] : 0.0f;
+        lsum += om * d * d;
+        const float g = 2.0f * om * d * osc * inv_n;
+        db3 += g;
+        const uint16_t gb = (uint16_t)bf16_rne(g);
+        S.X[row * SX + r16] = gb;            // dZ3 [sample][o], o < 16
+        S.X[row * SX + 16 + r16] = 0;        // K padding up to 32
+        S.D3T[r16 * SH + row] = gb;          // dZ3 transposed [o][sample]
+    }
     wave_sync_lds();
 
     // ---- dH2 = dZ3 W3 ; dZ2 = dH2 * silu'(Z2)
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    {
         const bf16x8 a = lds_frag(S.X, SX, 16 * rt + r16, 8 * q);
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
-            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW3b + ct, lane),
-                                                                  floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW3b + ct, lane),
+                                                              floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     }
+    // H2 (read by every wavefront's third layer) and the lo parts are
+    // overwritten below by other wavefronts' samples: all must be past it
+    __syncthreads();
     float db2[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float g = acc[rt][ct][i] * dsilu(Z2[rt][ct][i]);
-                db2[ct] += g;
-                const uint16_t gb = (uint16_t)bf16_rne(g);
-                const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
-                S.H1[row * SH + col] = gb;       // dZ2 [sample][h2]
-                S.H2[col * SH + row] = gb;       // dZ2 transposed [h2][sample]
-            }
+        for (int i = 0; i < 4; ++i) {
+            const float g = acc[ct][i] * dsilu(Z2[ct][i]);
+            db2[ct] += g;
+            const uint16_t gb = (uint16_t)bf16_rne(g);
+            const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
+            S.H1[row * SH + col] = gb;       // dZ2 [sample][h2]
+            S.H2[col * SH + row] = gb;       // dZ2 transposed [h2][sample]
+        }
     wave_sync_lds();
 
     // ---- dH1 = dZ2 W2 ; dZ1 = dH1 * silu'(Z1)
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < 2; ++kb) {
+        const bf16x8 a = lds_frag(S.H1, SH, 16 * rt + r16, 32 * kb + 8 * q);
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 a = lds_frag(S.H1, SH, 16 * rt + r16, 32 * kb + 8 * q);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, frag_of(M.frag, kFragW2b + ct * 2 + kb, lane), acc[rt][ct], 0, 0, 0);
-        }
+        for (int ct = 0; ct < 4; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, frag_of(M.frag, kFragW2b + ct * 2 + kb, lane), acc[ct],
+                                                              0, 0, 0);
+    }
     float db1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float g = acc[rt][ct][i] * dsilu(Z1[rt][ct][i]);
-                db1[ct] += g;
-                const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
-                S.D1T[col * SH + row] = (uint16_t)bf16_rne(g);   // dZ1 transposed [h1][sample]
-            }
-    wave_sync_lds();
-
-    float *out = partial + (int64_t)blockIdx.x * off.P;
-    // ---- dW3[o][h2] = sum_s dZ3[s][o] H2[s][h2]
-    {
-        floatx4 w3[4];
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) w3[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 a = lds_frag(S.D3T, SH, r16, 32 * kb + 8 * q);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                w3[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, lds_frag(S.H2T, SH, 16 * ct + r16, 32 * kb + 8 * q), w3[ct], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+            const float g = acc[ct][i] * dsilu(Z1[ct][i]);
+            db1[ct] += g;
+            const int row = 16 * rt + 4 * q + i, col = 16 * ct + r16;
+            S.D1T[col * SH + row] = (uint16_t)bf16_rne(g);   // dZ1 transposed [h1][sample]
         }
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int o = 4 * q + i;
-                if (o < n_out) out[off.W3 + o * H + 16 * ct + r16] = w3[ct][i];
-            }
-    }
-    // ---- dW2[h2][h1] = sum_s dZ2[s][h2] H1[s][h1]
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const bf16x8 a = lds_frag(S.H2, SH, 16 * rt + r16, 32 * kb + 8 * q);
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, lds_frag(S.H1T, SH, 16 * ct + r16, 32 * kb + 8 * q), acc[rt][ct], 0, 0, 0);
-        }
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                out[off.W2 + (16 * rt + 4 * q + i) * H + 16 * ct + r16] = acc[rt][ct][i];
-    // ---- dW1[h1][m] = sum_s dZ1[s][h1] X[s][m]
-    {
-        floatx4 w1[4];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            w1[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb)
-                w1[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_frag(S.D1T, SH, 16 * rt + r16, 32 * kb + 8 * q),
-                                                                 lds_frag(S.XT, SH, r16, 32 * kb + 8 * q), w1[rt],
-                                                                 0, 0, 0);
-        }
-        if (r16 < n_in) {
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) out[off.W1 + (16 * rt + 4 * q + i) * n_in + r16] = w1[rt][i];
-        }
-    }
-    // ---- biases: column sums over the 64 samples (reduce the 4 lane quarters)
+    // bias and loss sums of this wavefront's samples (reduce the 4 lane quarters)
     db3 += __shfl_xor(db3, 16);
     db3 += __shfl_xor(db3, 32);
 #pragma unroll
@@ -884,18 +812,75 @@ __global__ __launch_bounds__(kWave) void k_mlp_grad(SpecTables T, MlpTables M, c
         db1[ct] += __shfl_xor(db1[ct], 16);
         db1[ct] += __shfl_xor(db1[ct], 32);
     }
-    if (q == 0) {
-        if (r16 < n_out) out[off.b3 + r16] = db3;
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            out[off.b2 + 16 * ct + r16] = db2[ct];
-            out[off.b1 + 16 * ct + r16] = db1[ct];
-        }
-    }
-    // ---- loss sum of the tile
 #pragma unroll
     for (int sh = 32; sh >= 1; sh >>= 1) lsum += __shfl_xor(lsum, sh);
-    if (lane == 0) loss_partial[blockIdx.x] = lsum;
+    if (q == 0) {
+        red[wave][kRedB3 + r16] = db3;
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            red[wave][kRedB2 + 16 * ct + r16] = db2[ct];
+            red[wave][16 * ct + r16] = db1[ct];
+        }
+    }
+    if (lane == 0) red[wave][kRedLoss] = lsum;
+    __syncthreads();
+
+    float *out = partial + (int64_t)blockIdx.x * off.P;
+    // ---- dW3[o][h2] = sum_s dZ3[s][o] H2[s][h2], output tile ct = wave
+    {
+        const int ct = wave;
+        floatx4 w3 = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            w3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_frag(S.D3T, SH, r16, 32 * kb + 8 * q),
+                                                         lds_frag(S.H2T, SH, 16 * ct + r16, 32 * kb + 8 * q), w3, 0, 0,
+                                                         0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = 4 * q + i;
+            if (o < n_out) out[off.W3 + o * H + 16 * ct + r16] = w3[i];
+        }
+    }
+    // ---- dW2[h2][h1] = sum_s dZ2[s][h2] H1[s][h1], row tile rt = wave
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        const bf16x8 a = lds_frag(S.H2, SH, 16 * rt + r16, 32 * kb + 8 * q);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, lds_frag(S.H1T, SH, 16 * ct + r16, 32 * kb + 8 * q),
+                                                              acc[ct], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[off.W2 + (16 * rt + 4 * q + i) * H + 16 * ct + r16] = acc[ct][i];
+    // ---- dW1[h1][m] = sum_s dZ1[s][h1] X[s][m], row tile rt = wave
+    {
+        floatx4 w1 = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            w1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_frag(S.D1T, SH, 16 * rt + r16, 32 * kb + 8 * q),
+                                                         lds_frag(S.XT, SH, r16, 32 * kb + 8 * q), w1, 0, 0, 0);
+        if (r16 < n_in) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[off.W1 + (16 * rt + 4 * q + i) * n_in + r16] = w1[i];
+        }
+    }
+    // ---- biases and loss: the wavefronts' sums in wavefront order
+    if (wave == 0) {
+        const float s1 = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        const float s2 = ((red[0][kRedB2 + lane] + red[1][kRedB2 + lane]) + red[2][kRedB2 + lane]) + red[3][kRedB2 + lane];
+        out[off.b1 + lane] = s1;
+        out[off.b2 + lane] = s2;
+        if (lane < n_out)
+            out[off.b3 + lane] =
+                ((red[0][kRedB3 + lane] + red[1][kRedB3 + lane]) + red[2][kRedB3 + lane]) + red[3][kRedB3 + lane];
+        if (lane == 0)
+            loss_partial[blockIdx.x] =
+                ((red[0][kRedLoss] + red[1][kRedLoss]) + red[2][kRedLoss]) + red[3][kRedLoss];
+    }
 }
 
 // grad[p] = sum over the gradient partials, in a fixed order: wavefront i
@@ -1185,8 +1170,8 @@ hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float 
                            hipStream_t stream)
 {
     const unsigned nblk = (unsigned)((count + kWave - 1) / kWave);
-    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(kWave), 0, stream, t, m, L, Y, n_all, order, base, count, partial,
-                       loss_partial);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(kGradWaves * kWave), 0, stream, t, m, L, Y, n_all, order, base,
+                       count, partial, loss_partial);
     return hipGetLastError();
 }
 
