@@ -50,7 +50,16 @@ PEAK_NOTE = ("peak: published FP32 157.3 TFLOP/s / 2 FLOP per FMA = 78.65e12 lan
 OPS_PER_SEGMENT = 12          # one voxel segment of the incremental Siddon walk: next crossing as the
                               # min of three, segment length, accumulation, advance of one axis's crossing
                               # and index, label address and load, exit test
-EXP_SLOTS = 4                 # lane-operations counted for one exp (the hardware exp2 is half rate; the reduction adds more)
+EXP_SLOTS = 4                 # lane-operations counted for the dose sum's 1 - exp(-P) (a half-rate exp2 plus its
+                              # argument reduction)
+EXP2_SLOTS = 2                # the spectral sum's exponential: one hardware exp2, half rate
+
+
+def spectral_ops_per_bin(M: int) -> int:
+    """Lane-operations of the spectral sum per hit ray and bin: M FMAs of the
+    base-2 optical depth (mu log2 e tabulated), one exp2 at half rate and the
+    weight FMA."""
+    return M + 1 + EXP2_SLOTS
 
 WORKLOADS = {
     "head": (3, "", "head phantom 512x512x256 @0.5 mm, 10 materials, 120 bins 1-120 keV, 1024x768 detector "
@@ -234,7 +243,7 @@ def spectral_stage(pb, cfg, args, torch, fc):
                                   1, args.form_steps, torch)
     t = stages["trace"][0] / args.form_steps
     exps = float(n) * E
-    ops = exps * (M + 2 + EXP_SLOTS)
+    ops = exps * spectral_ops_per_bin(M)
     ach = ops / (t * 1e-3)
     del Lh, Y, ws
     return {
@@ -246,8 +255,8 @@ def spectral_stage(pb, cfg, args, torch, fc):
         "roofline": {"kernel": "k_spectral", "bound": "alu", "achieved": round(ach / 1e12, 3),
                      "peak": round(PEAK_LANE_OPS / 1e12, 2), "unit": "Top/s", "frac": round(ach / PEAK_LANE_OPS, 4),
                      "frac_single_issue": round(ach / SINGLE_ISSUE_LANE_OPS, 4),
-                     "note": "per hit ray and bin M FMAs, the weight FMA, the scale and an exp counted as "
-                             "EXP_SLOTS lane-operations; the exp unit itself is far from busy (exp_rate_frac)"},
+                     "note": "per hit ray and bin M FMAs, the weight FMA and an exp2 counted as "
+                             "EXP2_SLOTS lane-operations; the exp unit itself is far from busy (exp_rate_frac)"},
     }
 
 
@@ -448,8 +457,8 @@ def walk_work(counts: dict, M: int, E: int) -> tuple[float, float]:
     OPS_PER_SEGMENT per Siddon voxel segment (the unit of the method's
     work) or per step the two-level walk takes (brick steps plus
     voxel steps inside mixed bricks), plus the spectral sum of every hit ray
-    (M FMAs, the scale, the weight FMA and an exp of EXP_SLOTS per bin)."""
-    spectral = counts["hit_rays"] * E * (M + 2 + EXP_SLOTS)
+    (spectral_ops_per_bin: M FMAs, the weight FMA and an exp2 per bin)."""
+    spectral = counts["hit_rays"] * E * spectral_ops_per_bin(M)
     model = OPS_PER_SEGMENT * counts["siddon_segments"] + spectral
     executed = OPS_PER_SEGMENT * (counts["brick_steps"] + counts["voxel_steps"]) + spectral
     return float(model), float(executed)
@@ -476,7 +485,7 @@ def plain_workload(name, pb, cfg, warmup, steps, torch, fc):
     digest = source_digest(TRACE_SOURCES)
     walk = alu_roof(f"k_project_rows<{mp}>", model, trace_ms, trace_n,
                     traffic=profiled_traffic("k_project_rows", digest, name),
-                    work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment + {M + 2 + EXP_SLOTS} per hit "
+                    work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment + {spectral_ops_per_bin(M)} per hit "
                               f"ray and bin",
                     executed=alu_roof("same launches", executed, trace_ms, trace_n,
                                       work_unit=f"{OPS_PER_SEGMENT} lane-ops per walk step taken (brick steps + voxel "
@@ -585,9 +594,9 @@ def form_surrogate(pb, cfg, plain, args, torch, fc, counts):
     net_flops = 2.0 * 3 * macs * n_net
     net_ach = net_flops / (trace_ms * 1e-3) / 1e12
     # the fused kernel's vector work: the walk, and the exact spectral sum of the rays that fall back
-    model = float(OPS_PER_SEGMENT * counts["siddon_segments"] + n_exact * E * (M + 2 + EXP_SLOTS))
+    model = float(OPS_PER_SEGMENT * counts["siddon_segments"] + n_exact * E * spectral_ops_per_bin(M))
     fused = alu_roof(f"k_project_rows_mlp<{mp}>", model, trace_ms, trace_n,
-                     work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment + {M + 2 + EXP_SLOTS} per bin "
+                     work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel segment + {spectral_ops_per_bin(M)} per bin "
                                f"of each ray that falls back to the exact sum",
                      network={"bound": "mfma", "achieved": round(net_ach, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
                               "unit": "TFLOP/s", "frac": round(net_ach / PEAK_BF16_MFMA_TFLOPS, 5),

@@ -226,7 +226,7 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     L.flags = o;
     o += align_up(64 * sizeof(int));
     L.muT = o;
-    o += align_up((size_t)t.E * t.mp * sizeof(float));
+    o += align_up(2 * (size_t)t.E * t.mp * sizeof(float));   // mu, then mu log2(e)
     L.w = o;
     o += align_up((size_t)t.E * sizeof(float));
     L.Wg = o;
@@ -377,6 +377,7 @@ fcat_status prep_tables(const fcat_spectral_t *s, const float *s_bin, SpecTables
     }
     if (e != hipSuccess) return device_fail(e, "prep_tables");
     t.muT = muT;
+    t.mu2T = muT + (size_t)t.E * t.mp;
     t.w = w;
     t.Wg = Wg;
     t.Wsg = Wsg;

@@ -438,29 +438,6 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
     acc.read(L);
 }
 
-// exp(-P) for the spectral sum, as 2^-x with x = P log2(e) split into two
-// FP32 parts: x = fl(P log2e) and the rest c = P log2(e) - x, found exactly
-// by an FMA (the product's own rounding error) plus P times the tail of
-// log2(e) beyond FP32.  Then exp(-P) = 2^-x 2^-c = 2^-x (1 - c ln 2 + ...),
-// with |c ln 2| below 2^-25 |x|, so the dropped terms are below 1e-11
-// relative.  2^-x is the hardware base-2 exponential (v_exp_f32, accurate to
-// about one ulp over its whole range).  Six vector instructions.  P is a
-// non-negative optical depth; a result below the smallest normal FP32 number
-// (P > 87.3) may come out as 0, a NaN P gives NaN, and non-finite or
-// negative P below -88 (only from non-finite or negative inputs) is not
-// defined.
-__device__ __forceinline__ float exp_neg(float P)
-{
-    constexpr float kLog2e = 1.44269502162933349609375f;   // log2(e) rounded to FP32
-    constexpr float kLog2eLo = 1.925963033500011e-08f;      // log2(e) - kLog2e, rounded
-    constexpr float kLn2 = 0.693147182464599609375f;
-    const float x = P * kLog2e;
-    float c = fmaf(P, kLog2e, -x);
-    c = fmaf(P, kLog2eLo, c);
-    const float y = __builtin_amdgcn_exp2f(-x);
-    return fmaf(-y * kLn2, c, y);
-}
-
 // A read-only table seen through the constant address space.  The compiler
 // then loads its wave-uniform entries once per wavefront (scalar loads)
 // even after an LDS fence, a wave barrier, an asm statement or a store it
@@ -473,22 +450,28 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *const_tabl
     return (const __attribute__((address_space(4))) T *)p;
 }
 
-// sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3)
+// sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3),
+// evaluated as w_e 2^-x with x = sum_m (mu[e][m] log2 e) L_m from the
+// base-2 table.  Scaling the table instead of each optical depth costs one
+// more rounding per table entry (a relative 2^-24 of each mu, as if the
+// input had been rounded once more) and leaves x with the rounding error of
+// its own FMA chain, the same as that of the base-e sum it replaces; 2^-x is
+// the hardware base-2 exponential (about one ulp).
 template <int MP>
 __device__ __forceinline__ float group_sum(const float (&L)[MP], const SpecTables &T, int e0, int e1)
 {
-    const auto *mu = const_table(T.muT);
+    const auto *mu2 = const_table(T.mu2T);
     const auto *w = const_table(T.w);
     float acc = 0.0f;
     // two bins per iteration: their table loads issue together and their
     // chains of FMAs interleave
 #pragma unroll 2
     for (int e = e0; e < e1; ++e) {
-        const auto *mrow = mu + e * MP;
-        float P = 0.0f;
+        const auto *mrow = mu2 + e * MP;
+        float x = 0.0f;
 #pragma unroll
-        for (int m = 0; m < MP; ++m) P = fmaf(mrow[m], L[m], P);
-        acc = fmaf(w[e], exp_neg(P), acc);
+        for (int m = 0; m < MP; ++m) x = fmaf(mrow[m], L[m], x);
+        acc = fmaf(w[e], __builtin_amdgcn_exp2f(-x), acc);
     }
     return acc;
 }

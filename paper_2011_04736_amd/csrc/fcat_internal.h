@@ -87,6 +87,7 @@ inline int padded_blocks(int64_t waves)
 // eta and s_bin.  gstart is host-derived from the group map.
 struct SpecTables {
     const float *muT;              // [E][mp]  (mp = padded material count, zeros past n_mat)
+    const float *mu2T;             // [E][mp]  mu * log2(e), rounded once (optical depth in bits)
     const float *w;                // [E]      phi * eta
     const float *Wg;               // [G]      sum of w over the group
     const float *Wsg;              // [G]      sum of w * s_bin over the group

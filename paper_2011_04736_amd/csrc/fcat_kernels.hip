@@ -186,6 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_prep_tables(const float *__restrict_
             const float v = m < T.M ? mu[(int64_t)m * T.E + e] : 0.0f;
             nonfinite = nonfinite || !isfinite(v);
             muT[e * T.mp + m] = v;
+            // the same table in base 2 follows it: exp(-mu L) = 2^-(mu log2(e) L)
+            muT[(T.E + e) * T.mp + m] = (float)((double)v * 1.44269504088896340736);
         }
     }
     if (bad) {

@@ -104,7 +104,14 @@ def test_exp_accuracy_over_the_optical_depth_range(fc):
     over the results below the smallest normal number (which may be flushed
     to 0), negative depths, large finite depths and NaN.  Infinite depths,
     depths beyond 2e38 and negative ones below -88 come only from non-finite
-    or negative inputs and are not defined."""
+    or negative inputs and are not defined.
+
+    Bound: the sum forms its exponent in base 2, x = fl(mu log2 e) L, two
+    roundings of relative 2^-24 each, so x is off by at most 2^-23 x, which
+    moves 2^-x by a relative ln 2 * 2^-23 x = 2^-23 P; the hardware 2^-x adds
+    about one ulp (2.5e-7 allowed).  An FP32 optical depth is itself only
+    known to half an ulp, a relative 2^-24 P in exp(-P), so the bound is
+    twice what the input's own rounding gives."""
     import torch
     P = np.linspace(0.0, 87.0, 400001).astype(np.float32)
     L = torch.as_tensor(P[:, None].copy()).cuda()
@@ -113,8 +120,9 @@ def test_exp_accuracy_over_the_optical_depth_range(fc):
     Y = fc.fcat_spectral(L, sp).cpu().numpy()[0].astype(np.float64)
     ref = np.exp(-P.astype(np.float64))
     rel = np.abs(Y - ref) / ref
-    print(f"exp(-P), P in [0, 87]: max rel err {rel.max():.2e}")
-    assert rel.max() <= 1e-6
+    bound = 2.5e-7 + P.astype(np.float64) * 2.0 ** -23
+    print(f"exp(-P), P in [0, 87]: max rel err {rel.max():.2e}, max share of the bound {(rel / bound).max():.3f}")
+    assert (rel <= bound).all()
     # below the normal range, negative depths, large finite depths, NaN
     P = np.concatenate([np.linspace(87.0, 105.0, 20001), np.linspace(-88.5, 0.0, 2001),
                         [110.0, 1e3, 1e5, 1e6, 1e7, 1e30, np.nan]]).astype(np.float32)
@@ -124,5 +132,6 @@ def test_exp_accuracy_over_the_optical_depth_range(fc):
         ref = np.exp(-P.astype(np.float64))
     fin = np.isfinite(P)
     err = np.abs(Y[fin].astype(np.float64) - ref[fin])
-    assert np.all(err <= np.maximum(1e-6 * ref[fin], 2.0 ** -126))
+    bound = (2.5e-7 + np.abs(P[fin].astype(np.float64)) * 2.0 ** -23) * ref[fin]
+    assert np.all(err <= np.maximum(bound, 2.0 ** -126))
     assert np.all(Y[-7:-1] == 0.0) and np.isnan(Y[-1])
