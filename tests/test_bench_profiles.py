@@ -55,3 +55,19 @@ def test_traffic_line(tmp_path, monkeypatch):
     assert bench.profiled_traffic("k_psf", "cccc", "head") == 3.25e10
     assert bench.profiled_traffic("k_psf", "dddd", "head") is None
     assert bench.profiled_traffic("k_project_rows", "cccc", "head") is None
+
+
+def test_measured_ceilings_price_walks_by_the_steps_taken():
+    """A walk priced by the model count (every Siddon segment) gets no rate
+    against the measured ceilings, since it crosses uniform bricks in one step
+    and can outrun them; its executed-steps entry, and every other entry, does."""
+    walk = bench.alu_roof("k_project_rows<8>", 60e12, 1000.0,
+                          executed=bench.alu_roof("same launches", 20e12, 1000.0))
+    psf = {"kernel": "k_psf4", "bound": "alu", "achieved": 100.0, "unit": "TFLOP/s", "peak": 157.3, "frac": 0.64}
+    result = {"roofline": {"kernel": "k_project_rows<8>", "bound": "alu", "achieved": 60.0, "unit": "Top/s",
+                           "peak": 78.65, "frac": 0.76, "frac_executed": 0.25},
+              "kernels": {"k_project_rows": walk, "k_psf": psf}}
+    bench.apply_measured_ceilings(result, {"fma_f32_TFLOPs": 120.0, "copy_GBps": 5000.0, "mfma_bf16_TFLOPs": 2000.0})
+    assert "frac_measured" not in result["roofline"] and "frac_measured" not in walk
+    assert walk["executed"]["measured_peak"] == 60.0 and walk["executed"]["frac_measured"] == round(20.0 / 60.0, 4)
+    assert psf["measured_peak"] == 120.0 and psf["frac_measured"] == round(100.0 / 120.0, 4)
