@@ -183,6 +183,7 @@ TraceGeom make_geom_box(const fcat_geometry_t *g, const int (&n)[3], const doubl
     G.nv = g->nv;
     G.n_angles = g->n_angles;
     G.angles = g->angles_rad;
+    G.trig = nullptr;
     for (int ax = 0; ax < 3; ++ax) G.nb[ax] = (n[ax] + kBrickEdge - 1) / kBrickEdge;
     G.bricks = nullptr;
     G.labels_bm = nullptr;
@@ -199,7 +200,7 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, Y, fixed;
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, trig, Y, fixed;
     size_t scale, unitk, flood, yflood;   // projection stage: c_g, unit kernels, flood, its group signals
     size_t per_angle;    // bytes of per-angle chunk buffers (group signals)
     size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
@@ -245,6 +246,8 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (surrogate) o += align_up((size_t)FCAT_MLP_MAX_IO * sizeof(float));
     L.bricks = o;
     o += align_up(nbricks);
+    L.trig = o;   // cosine and sine of every angle
+    if (g) o += align_up((size_t)g->n_angles * 2 * sizeof(double));
     const size_t plane = g ? (size_t)g->nu * g->nv : 0;
     L.scale = o;
     if (proj) o += align_up((size_t)t.G * sizeof(float));
@@ -620,6 +623,9 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
                                             const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm),
                                             stream, t.M, bad);
         if (e0 != hipSuccess) return device_fail(e0, "build_bricks");
+        e0 = launch_trig_table(G, at<double>(workspace, L.trig), stream);
+        if (e0 != hipSuccess) return device_fail(e0, "trig_table");
+        G.trig = at<double>(workspace, L.trig);
     }
     const float *S = scatter ? scatter->maps : nullptr;
     const int A = geometry->n_angles;

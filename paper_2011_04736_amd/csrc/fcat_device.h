@@ -165,7 +165,10 @@ __device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double 
             const double step = G.h[ax] * len * fabs(inv[ax]);
             r.t0[ax] = (float)fmax((ap - amin) * len, 0.0);
             r.dt[ax] = (float)step;
-            r.inv_dt[ax] = (float)(1.0 / step);
+            // only the first estimate of a crossing count uses it (the count
+            // is then corrected by up to one), so a reciprocal of about one
+            // ulp suffices
+            r.inv_dt[ax] = __builtin_amdgcn_rcpf(r.dt[ax]);
             const int b = i / kBrickEdge;
             const int bplane = (d[ax] > 0.0 ? b + 1 : b) * kBrickEdge;
             const double bp = (G.lo[ax] + bplane * G.h[ax] - s[ax]) * inv[ax];
@@ -489,6 +492,19 @@ __device__ __forceinline__ void flag_nonfinite(int *bad, float i0, float sc)
 __device__ __forceinline__ double angle_of(const TraceGeom &G, int a)
 {
     return G.angles ? G.angles[a] : (2.0 * M_PI) * (double)a / (double)G.n_angles;
+}
+
+// Sine and cosine of angle a (wave-uniform): from the table when the caller
+// prepared one (scalar loads), else evaluated here.
+__device__ __forceinline__ void angle_trig(const TraceGeom &G, int a, double &st, double &ct)
+{
+    if (G.trig) {
+        const auto *t = const_table(G.trig);
+        ct = t[2 * a];
+        st = t[2 * a + 1];
+    } else {
+        sincos(angle_of(G, a), &st, &ct);
+    }
 }
 
 }  // namespace fcat

@@ -35,6 +35,7 @@ struct TraceGeom {
     int n[3];
     int nu, nv, n_angles;
     const double *angles;          // device, or null for 2 pi a / A
+    const double *trig;            // device [n_angles][2]: cos, sin of each angle, or null
     // Brick map of the labels: kBrickEdge^3 bricks, nb[] per axis; bricks[]
     // ([nb2][nb1][nb0]) holds the common label of a uniform brick or -1, and
     // labels_bm[brick][z][y][x] is the brick-major copy of the labels, with
@@ -186,6 +187,9 @@ hipError_t launch_prep_tables(const float *mu, const float *phi, const float *et
 hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const SpecTables &t,
                                const float *flood, const float *scatter, int a0, int n_ang,
                                float *Y, float *out, hipStream_t stream);
+
+// Fills trig[2 a], trig[2 a + 1] with the cosine and sine of every angle of g.
+hipError_t launch_trig_table(const TraceGeom &g, double *trig, hipStream_t stream);
 
 // Builds SplitTables::afrag and ::wtile from mu and the prepared w.
 hipError_t launch_prep_split(const float *mu, const SpecTables &t, const SplitTables &sp, uint4 *afrag,

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows(TraceGeom G, const int8
     const bool valid = px.valid;
 
     double st, ct;
-    sincos(angle_of(G, a), &st, &ct);
+    angle_trig(G, a, st, ct);
     float L[MP];
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_pathlengths(TraceGeom G, const int8_
     const int al = px.al, iv = px.iv, iu = px.iu;
     const bool valid = px.valid;
     double st, ct;
-    sincos(angle_of(G, a0 + al), &st, &ct);
+    angle_trig(G, a0 + al, st, ct);
     float L[MP];
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_stats(TraceGeom G, int a0, int 
     if (gw >= n_ang * tiles_per_angle(G)) return;
     const PixelOf px = pixel_of(G, gw, lane);
     double st, ct;
-    sincos(angle_of(G, a0 + px.al), &st, &ct);
+    angle_trig(G, a0 + px.al, st, ct);
     float L[MP];
     Ray r{};
     const bool hit = px.valid && setup_ray(G, ct, st, px.iv, px.iu, r);
@@ -549,9 +549,27 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__
             labels_bm[(int64_t)gridDim.x * kBrickVox + i] = (int8_t)-1;
 }
 
+// Cosine and sine of every angle, once per projector call (the walk kernels
+// read them per wavefront instead of evaluating them per lane).
+__global__ __launch_bounds__(kBlock) void k_trig_table(TraceGeom G, double *__restrict__ trig)
+{
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= G.n_angles) return;
+    double st, ct;
+    sincos(angle_of(G, a), &st, &ct);
+    trig[2 * a] = ct;
+    trig[2 * a + 1] = st;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
+
+hipError_t launch_trig_table(const TraceGeom &g, double *trig, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_trig_table, dim3((g.n_angles + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, g, trig);
+    return hipGetLastError();
+}
 
 hipError_t launch_prep_tables(const float *mu, const float *phi, const float *eta, const float *s_bin,
                               const SpecTables &t, float *muT, float *w, float *Wg, float *Wsg,

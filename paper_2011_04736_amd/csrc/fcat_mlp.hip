@@ -497,7 +497,7 @@ void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
     float *block = lds_all + wave * fused_wave_floats<MP>();
 
     double st, ct;
-    sincos(angle_of(G, a), &st, &ct);
+    angle_trig(G, a, st, ct);
     float L[MP];
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);

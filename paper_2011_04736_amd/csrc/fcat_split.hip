@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_project_rows_split(TraceGeom G, Spec
     const bool valid = px.valid;
 
     double st, ct;
-    sincos(angle_of(G, a), &st, &ct);
+    angle_trig(G, a, st, ct);
     float L[MP];
     Ray r{};
     const bool hit = valid && setup_ray(G, ct, st, iv, iu, r);
