@@ -451,7 +451,7 @@ fcat_status prep_mlp(const fcat_surrogate_t *u, const float *params, const SpecT
 // gradient partials and loss sums, and the validation cells.
 struct MlpLayout {
     Layout base;
-    size_t partial, loss_partial, cells, stats, total;
+    size_t partial, loss_partial, cells, stats, fcnt, finv, total;
     int nparts, P;
 };
 
@@ -470,6 +470,10 @@ MlpLayout mlp_layout(const SpecTables &t, int64_t batch)
     o += align_up((size_t)2 * FCAT_MLP_MAX_IO * FCAT_MLP_CELLS * sizeof(int));
     m.stats = o;
     o += align_up((size_t)kStatBlocks * kStatStride * sizeof(float));
+    m.fcnt = o;   // fragment elements per parameter (training)
+    o += align_up((size_t)m.P * sizeof(int));
+    m.finv = o;
+    o += align_up((size_t)m.P * kMlpViews * sizeof(uint32_t));
     m.total = o;
     return m;
 }
@@ -1670,14 +1674,24 @@ static hipError_t train_one(fcat_mlp_train_t *train, const SpecTables &t, MlpTab
     float *partial = at<float>(workspace, ml.partial);
     float *lp = at<float>(workspace, ml.loss_partial);
     StageTimer tm(FCAT_STAGE_MLP, stream);
-    hipError_t e = launch_mlp_prep(train->params, t.M, t.G, const_cast<uint4 *>(mt.frag), stream, true);
-    if (e == hipSuccess) e = launch_mlp_grad(t, mt, L, Yprim, n, order, base, count, partial, lp, stream);
+    hipError_t e = launch_mlp_grad(t, mt, L, Yprim, n, order, base, count, partial, lp, stream);
     if (e == hipSuccess)
         e = launch_mlp_reduce_adam(partial, (count + kWave - 1) / kWave, ml.P, nullptr, train->params, train->adam_m,
                                    train->adam_v, train->step + 1, train->lr, train->beta1, train->beta2, train->eps,
-                                   lp, 1.0f / ((float)count * (float)t.G), loss, stream);
+                                   lp, 1.0f / ((float)count * (float)t.G), loss, stream, at<int>(workspace, ml.fcnt),
+                                   at<uint32_t>(workspace, ml.finv), const_cast<uint4 *>(mt.frag));
     if (e == hipSuccess) train->step += 1;
     return e;
+}
+
+// Before the first train_one of a call: mlp_begin has built the fragment
+// views of the current parameters; each Adam step then rewrites the
+// training views of the parameters it updates, through the table of
+// fragment elements per parameter built here.
+static hipError_t train_begin(const SpecTables &t, const MlpLayout &ml, void *workspace, hipStream_t stream)
+{
+    StageTimer tm(FCAT_STAGE_MLP, stream);
+    return launch_mlp_frag_inverse(t.M, t.G, at<int>(workspace, ml.fcnt), at<uint32_t>(workspace, ml.finv), stream);
 }
 
 fcat_status fcat_mlp_train_step(fcat_mlp_train_t *train, const fcat_surrogate_t *surrogate,
@@ -1697,7 +1711,8 @@ fcat_status fcat_mlp_train_step(fcat_mlp_train_t *train, const fcat_surrogate_t 
     MlpTables mt{};
     if ((s = mlp_begin(surrogate, spectral, train->params, count, workspace, workspace_bytes, stream, t, ml, mt)))
         return s;
-    hipError_t e = train_one(train, t, mt, ml, workspace, L, Yprim, n, order, base, count, loss, stream);
+    hipError_t e = train_begin(t, ml, workspace, stream);
+    if (e == hipSuccess) e = train_one(train, t, mt, ml, workspace, L, Yprim, n, order, base, count, loss, stream);
     if (e != hipSuccess) return device_fail(e, "mlp_train_step");
     return FCAT_OK;
 }
@@ -1718,6 +1733,8 @@ fcat_status fcat_mlp_train_epoch(fcat_mlp_train_t *train, const fcat_surrogate_t
     MlpTables mt{};
     if ((s = mlp_begin(surrogate, spectral, train->params, batch, workspace, workspace_bytes, stream, t, ml, mt)))
         return s;
+    hipError_t e0 = train_begin(t, ml, workspace, stream);
+    if (e0 != hipSuccess) return device_fail(e0, "mlp_train_epoch");
     int64_t b = 0;
     for (int64_t base = 0; base < n; base += batch, ++b) {
         const int count = (int)std::min<int64_t>(batch, n - base);

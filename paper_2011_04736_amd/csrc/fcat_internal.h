@@ -167,9 +167,16 @@ hipError_t launch_project_rows_mlp(const TraceGeom &g, const SpecTables &t, cons
 hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n_all,
                            const int32_t *order, int64_t base, int count, float *partial, float *loss_partial,
                            hipStream_t stream);
+// With cnt and inv (from launch_mlp_frag_inverse) the Adam step also rewrites, in
+// frag, the training fragment elements of every parameter it updates.
 hipError_t launch_mlp_reduce_adam(const float *partial, int nparts, int P, float *grad, float *params, float *m,
                                   float *v, int step, float lr, float beta1, float beta2, float eps,
-                                  const float *loss_partial, float loss_scale, float *loss_out, hipStream_t stream);
+                                  const float *loss_partial, float loss_scale, float *loss_out, hipStream_t stream,
+                                  const int *cnt = nullptr, const uint32_t *inv = nullptr, uint4 *frag = nullptr);
+// Elements of the training fragments per parameter: up to kMlpViews entries
+// per parameter in inv ([P][kMlpViews]), their number in cnt ([P] ints).
+constexpr int kMlpViews = 4;
+hipError_t launch_mlp_frag_inverse(int n_in, int n_out, int *cnt, uint32_t *inv, hipStream_t stream);
 hipError_t launch_mlp_validate(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n,
                                unsigned *err_bits, int *count, hipStream_t stream);
 hipError_t launch_mlp_cells(const unsigned *err_bits, const int *count, int ncell, float threshold, int min_count,

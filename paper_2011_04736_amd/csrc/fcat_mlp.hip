@@ -259,6 +259,57 @@ __device__ __forceinline__ void mlp_infer_wave(const float (&x)[16], const MlpTa
 // Fragments of every weight view (FP32 master -> BF16 hi or lo part).
 __device__ __forceinline__ float hi_part(float v) { return bf16_value(bf16_rne(v)); }
 
+// The parameter whose BF16 hi (lo = false) or lo part fills element j of
+// lane `lane` of training fragment f (f < kMlpTrainFrags), or -1 for a zero
+// element; the same views k_mlp_prep builds.
+__device__ int train_frag_source(int f, int lane, int j, int n_in, int n_out, bool &lo)
+{
+    const Offsets off = param_offsets(n_in, n_out);
+    const int q = lane >> 4, r16 = lane & 15, kk = 8 * q + j;
+    lo = false;
+    if (f < kFragW1lo) {                        // [W1_hi | W1_hi]
+        const int n = 16 * (f - kFragW1) + r16, k = kk & 15;
+        return k < n_in ? off.W1 + n * n_in + k : -1;
+    }
+    if (f < kFragW2) {                          // [W1_lo | 0]
+        lo = true;
+        const int n = 16 * (f - kFragW1lo) + r16;
+        return kk < n_in ? off.W1 + n * n_in + kk : -1;
+    }
+    if (f < kFragW3) {                          // W2_hi, W2_lo
+        lo = f >= kFragW2lo;
+        const int t = f - (lo ? kFragW2lo : kFragW2);
+        return off.W2 + (16 * (t / 2) + r16) * H + 32 * (t % 2) + kk;
+    }
+    if (f < kFragW3b) {                         // W3_hi, W3_lo
+        lo = f >= kFragW3lo;
+        const int kb = f - (lo ? kFragW3lo : kFragW3);
+        return r16 < n_out ? off.W3 + r16 * H + 32 * kb + kk : -1;
+    }
+    if (f < kFragW2b)                           // B[k = o][n = h2] = W3[o][h2]
+        return kk < n_out ? off.W3 + kk * H + 16 * (f - kFragW3b) + r16 : -1;
+    const int ct = (f - kFragW2b) / 2, kb = (f - kFragW2b) % 2;   // B[k = h2][n = h1] = W2[h2][h1]
+    return off.W2 + (32 * kb + kk) * H + 16 * ct + r16;
+}
+
+// Inverse of train_frag_source: for each parameter p, the BF16 elements of
+// the training fragments that hold a part of it, inv[kMlpViews p + i] =
+// element index (fragment f, lane, j: (64 f + lane) 8 + j) | lo << 31 for
+// i < cnt[p]; cnt [P] must start at zero.  Every parameter fills at
+// most three elements (a W1 weight its hi part twice and its lo part once,
+// a W2 or W3 weight its hi and lo parts and one transposed hi part).
+__global__ __launch_bounds__(kBlock) void k_mlp_frag_inverse(int n_in, int n_out, int *__restrict__ cnt,
+                                                            uint32_t *__restrict__ inv)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= kMlpTrainFrags * kWave * 8) return;
+    bool lo;
+    const int p = train_frag_source(s / (8 * kWave), (s / 8) % kWave, s % 8, n_in, n_out, lo);
+    if (p < 0) return;
+    const int i = atomicAdd(cnt + p, 1);
+    if (i < kMlpViews) inv[kMlpViews * p + i] = (uint32_t)s | (lo ? 0x80000000u : 0u);
+}
+
 __global__ __launch_bounds__(kBlock) void k_mlp_prep(const float *__restrict__ params, int n_in, int n_out,
                                                      uint4 *__restrict__ frag, int n_frags)
 {
@@ -896,7 +947,9 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float *__restr
                                                             float *__restrict__ m, float *__restrict__ v, int step,
                                                             float lr, float beta1, float beta2, float eps,
                                                             const float *__restrict__ loss_partial, float loss_scale,
-                                                            float *__restrict__ loss_out)
+                                                            float *__restrict__ loss_out, const int *__restrict__ cnt,
+                                                            const uint32_t *__restrict__ inv,
+                                                            uint16_t *__restrict__ frag16)
 {
     __shared__ float sums[kReduceWaves][kWave];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
@@ -922,7 +975,17 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float *__restr
         v[p] = vt;
         const float mhat = mt / (1.0f - powf(beta1, (float)step));
         const float vhat = vt / (1.0f - powf(beta2, (float)step));
-        params[p] -= lr * mhat / (sqrtf(vhat) + eps);
+        const float w = params[p] - lr * mhat / (sqrtf(vhat) + eps);
+        params[p] = w;
+        if (inv) {
+            // the next step's training fragments: this parameter's BF16 parts,
+            // as k_mlp_prep would build them from w
+            const int n = min(cnt[p], kMlpViews);
+            for (int i = 0; i < n; ++i) {
+                const uint32_t e = inv[kMlpViews * p + i];
+                frag16[e & 0x7fffffffu] = (uint16_t)((e >> 31) ? bf16_rne(w - hi_part(w)) : bf16_rne(w));
+            }
+        }
     }
 }
 
@@ -1177,11 +1240,24 @@ hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float 
 
 hipError_t launch_mlp_reduce_adam(const float *partial, int nparts, int P, float *grad, float *params, float *m,
                                   float *v, int step, float lr, float beta1, float beta2, float eps,
-                                  const float *loss_partial, float loss_scale, float *loss_out, hipStream_t stream)
+                                  const float *loss_partial, float loss_scale, float *loss_out, hipStream_t stream,
+                                  const int *cnt, const uint32_t *inv, uint4 *frag)
 {
     static_assert(kReduceWaves == 4, "the four partial sums are added in a fixed order");
     hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((P + kWave - 1) / kWave), dim3(kBlock), 0, stream, partial, nparts, P,
-                       grad, params, m, v, step, lr, beta1, beta2, eps, loss_partial, loss_scale, loss_out);
+                       grad, params, m, v, step, lr, beta1, beta2, eps, loss_partial, loss_scale, loss_out, cnt, inv,
+                       reinterpret_cast<uint16_t *>(frag));
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_frag_inverse(int n_in, int n_out, int *cnt, uint32_t *inv, hipStream_t stream)
+{
+    const int P = mlp_param_count(n_in, n_out);
+    hipError_t e = launch_zero_ints(cnt, P, stream);
+    if (e != hipSuccess) return e;
+    const int n = kMlpTrainFrags * kWave * 8;
+    hipLaunchKernelGGL(k_mlp_frag_inverse, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, n_in, n_out, cnt,
+                       inv);
     return hipGetLastError();
 }
 
