@@ -153,8 +153,10 @@ def build_surrogate(pb: Problem, n_samples: int = 4_000_000, holdout: float = 0.
     t0 = time.perf_counter()
     for ep in range(first, last):
         train.lr = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * ep / max(epochs - 1, 1)))
-        g = torch.Generator().manual_seed(seed * 1000 + ep)
-        order = torch.randperm(n_train, generator=g).to(torch.int32).to(dev)
+        # the epoch's sample order, drawn on the device (a host permutation of
+        # millions of samples took longer than the epoch's training)
+        g = torch.Generator(device=dev).manual_seed(seed * 1000 + ep)
+        order = torch.randperm(n_train, generator=g, device=dev).to(torch.int32)
         fcat_mlp_train_epoch(train, sur, sp, Lt, Yt, order, batch, batch_loss=batch_loss)
         report.epoch_loss.append(float(batch_loss.mean().item()))
         if checkpoint:
