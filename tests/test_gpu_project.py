@@ -76,12 +76,15 @@ def test_contrast_thick_slab_sampled(fc):
 
 
 def test_head_full_size_sampled(fc):
-    """512x512x256 phantom, 120 bins, 1024x768 detector, 720 angles, scatter + PSF."""
+    """512x512x256 phantom, 120 bins, 1024x768 detector, 720 angles, scatter + PSF;
+    eight full projections compared: the axis-parallel (0, 90 degrees) and
+    diagonal (45, 135 degrees) directions, where crossings of two axes tie,
+    and five others spread over the circle."""
     import torch
     cfg = synth.make_config(3)
     pb = fc.upload(cfg)
     out = fc.fcat_project(pb)
-    sample = [0, 333, 719]
+    sample = [0, 90, 180, 270, 333, 451, 600, 719]
     out_s = out[sample].cpu().numpy()
     del out, pb
     torch.cuda.empty_cache()
