@@ -139,12 +139,20 @@ size_t brick_count(const fcat_phantom_t *p)
 }
 
 // brick map + brick-major label copy with its padding
+// The brick region of a workspace: brick map, background box (int[8]), padding,
+// brick-major labels, padding.
+constexpr size_t kClipBytes = 256;
 size_t brick_bytes(const fcat_phantom_t *p)
 {
-    return align_up(brick_count(p)) + brick_count(p) * kBrickVox + 2 * (size_t)kLabelPad;
+    return align_up(brick_count(p)) + kClipBytes + brick_count(p) * kBrickVox + 2 * (size_t)kLabelPad;
 }
-// brick 0 of the brick-major labels, in a workspace whose brick map starts at `bricks`
-int8_t *labels_bm_at(int8_t *bricks, const fcat_phantom_t *p) { return bricks + align_up(brick_count(p)) + kLabelPad; }
+// the background box, in a workspace whose brick map starts at `bricks`
+int *clip_at(int8_t *bricks, const fcat_phantom_t *p) { return reinterpret_cast<int *>(bricks + align_up(brick_count(p))); }
+// brick 0 of the brick-major labels
+int8_t *labels_bm_at(int8_t *bricks, const fcat_phantom_t *p)
+{
+    return bricks + align_up(brick_count(p)) + kClipBytes + kLabelPad;
+}
 
 }  // namespace
 
@@ -187,6 +195,7 @@ TraceGeom make_geom_box(const fcat_geometry_t *g, const int (&n)[3], const doubl
     for (int ax = 0; ax < 3; ++ax) G.nb[ax] = (n[ax] + kBrickEdge - 1) / kBrickEdge;
     G.bricks = nullptr;
     G.labels_bm = nullptr;
+    G.clip = nullptr;
     G.tile_log2u = tile_log2u_for(G);
     return G;
 }
@@ -623,9 +632,11 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     G.bad = bad;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
+        int *clip = clip_at(const_cast<int8_t *>(G.bricks), phantom);
         hipError_t e0 = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz,
-                                            const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm),
+                                            const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm), clip,
                                             stream, t.M, bad);
+        G.clip = clip;
         if (e0 != hipSuccess) return device_fail(e0, "build_bricks");
         e0 = launch_trig_table(G, at<double>(workspace, L.trig), stream);
         if (e0 != hipSuccess) return device_fail(e0, "trig_table");
@@ -795,8 +806,10 @@ fcat_status fcat_dose(const fcat_geometry_t *geometry, const fcat_phantom_t *pha
     hipError_t e;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
+        G.clip = clip_at(const_cast<int8_t *>(G.bricks), phantom);
         e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz,
-                                const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm), stream);
+                                const_cast<int8_t *>(G.bricks), const_cast<int8_t *>(G.labels_bm),
+                                const_cast<int *>(G.clip), stream);
         if (e == hipSuccess) e = launch_zero_doubles(S, t.E, stream);
     }
     if (e != hipSuccess) return device_fail(e, "dose set-up");
@@ -1382,7 +1395,9 @@ fcat_status fcat_pathlengths(const fcat_geometry_t *geometry, const fcat_phantom
     hipError_t e;
     {
         StageTimer tm(FCAT_STAGE_PREP, stream);
-        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks, labels_bm, stream);
+        G.clip = clip_at(bricks, phantom);
+        e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks, labels_bm,
+                                clip_at(bricks, phantom), stream);
     }
     if (e != hipSuccess) return device_fail(e, "build_bricks");
     {
@@ -1411,8 +1426,9 @@ fcat_status fcat_walk_stats(const fcat_geometry_t *geometry, const fcat_phantom_
     G.labels_bm = labels_bm_at(bricks, phantom);
     hipError_t e = launch_zero_ints(reinterpret_cast<int *>(counts), 2 * kWalkCounts, stream);
     if (e == hipSuccess)
+        G.clip = clip_at(bricks, phantom);
         e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks,
-                                const_cast<int8_t *>(G.labels_bm), stream);
+                                const_cast<int8_t *>(G.labels_bm), clip_at(bricks, phantom), stream);
     if (e == hipSuccess)
         e = launch_walk_stats(G, a_begin, a_end - a_begin, reinterpret_cast<unsigned long long *>(counts), stream);
     if (e != hipSuccess) return device_fail(e, "walk_stats");

@@ -107,6 +107,18 @@ __device__ __forceinline__ PixelOf pixel_of(const TraceGeom &G, int gw, int lane
     return p;
 }
 
+// A read-only table seen through the constant address space.  The compiler
+// then loads its wave-uniform entries once per wavefront (scalar loads)
+// even after an LDS fence, a wave barrier, an asm statement or a store it
+// cannot prove disjoint from the table, any of which otherwise turns them
+// into one load per lane.  Only for data that no kernel of the launch
+// writes (the spectral tables and the network's terms).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *const_table(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // Per-ray constants of the two-level walk.  Distances t are measured in mm
 // from the point where the ray enters the grid.
 struct Ray {
@@ -119,6 +131,8 @@ struct Ray {
                         // k * dtc + tc0 stays inf without a test)
     int i0[3];          // entry voxel
     int sgn[3];         // direction of travel per axis: +1, -1, or 0 if parallel
+    float t_bg;         // length outside the background box (TraceGeom::clip), all of it background
+    bool walk;          // the ray meets the background box: the walk runs over [0, t_end)
 };
 
 // FP64 set-up of the ray from the source to the centre of pixel (iv, iu):
@@ -151,13 +165,49 @@ __device__ __forceinline__ bool setup_ray(const TraceGeom &G, double ct, double 
     }
     if (!inside || !(amax > amin)) return false;
     const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    // the walk covers the background box only; the rest of the ray is
+    // background and is charged in one sum
+    int clo[3] = {0, 0, 0}, chi[3] = {G.n[0], G.n[1], G.n[2]};
+    r.t_bg = 0.0f;
+    r.walk = true;
+    const auto *c = const_table(G.clip);
+    // (wave-uniform: a box that is the whole grid clips nothing)
+    if (G.clip && !(c[7] != 0 && c[1] == 0 && c[2] == 0 && c[3] == 0 && c[4] == G.n[0] && c[5] == G.n[1] &&
+                    c[6] == G.n[2])) {
+        double bmin = amin, bmax = amax;
+        bool meets = c[7] != 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            clo[ax] = c[1 + ax];
+            chi[ax] = c[4 + ax];
+            const double lo = G.lo[ax] + clo[ax] * G.h[ax];
+            const double hi = G.lo[ax] + chi[ax] * G.h[ax];
+            if (d[ax] == 0.0) {
+                meets = meets && s[ax] >= lo && s[ax] < hi;
+            } else {
+                const double a0 = (lo - s[ax]) * inv[ax];
+                const double a1 = (hi - s[ax]) * inv[ax];
+                bmin = fmax(bmin, fmin(a0, a1));
+                bmax = fmin(bmax, fmax(a0, a1));
+            }
+        }
+        if (!meets || !(bmax > bmin)) {
+            r.t_bg = (float)((amax - amin) * len);
+            r.t_end = 0.0f;
+            r.walk = false;
+            return true;
+        }
+        r.t_bg = (float)(((bmin - amin) + (amax - bmax)) * len);
+        amin = bmin;
+        amax = bmax;
+    }
     r.t_end = (float)((amax - amin) * len);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const double q = (s[ax] + amin * d[ax] - G.lo[ax]) * G.inv_h[ax];
         // entering through a plane: the voxel beyond it in the direction of travel
         int i = d[ax] < 0.0 ? (int)ceil(q) - 1 : (int)floor(q);
-        i = min(max(i, 0), G.n[ax] - 1);
+        i = min(max(i, clo[ax]), chi[ax] - 1);
         r.i0[ax] = i;
         if (d[ax] != 0.0) {
             const int plane = d[ax] > 0.0 ? i + 1 : i;
@@ -326,9 +376,11 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
 {
     MatAcc<MP> acc(acc_wave, threadIdx.x & (kWave - 1));
     acc.clear();
-    if (!hit) {
+    const int bg = G.clip ? const_table(G.clip)[0] : 0;
+    if (!hit || !r.walk) {
+        // a ray that misses the background box is background all along
 #pragma unroll
-        for (int m = 0; m < MP; ++m) L[m] = 0.0f;
+        for (int m = 0; m < MP; ++m) L[m] = (hit && m == bg) ? r.t_bg : 0.0f;
         return;
     }
     const float t_end = r.t_end;
@@ -438,20 +490,10 @@ __device__ __forceinline__ void trace_bricks(const Ray &r, bool hit, const Trace
         }
     }
     acc.add(cur, t_end - run);
+    if (r.t_bg > 0.0f) acc.add(static_cast<unsigned>(bg), r.t_bg);
     acc.read(L);
 }
 
-// A read-only table seen through the constant address space.  The compiler
-// then loads its wave-uniform entries once per wavefront (scalar loads)
-// even after an LDS fence, a wave barrier, an asm statement or a store it
-// cannot prove disjoint from the table, any of which otherwise turns them
-// into one load per lane.  Only for data that no kernel of the launch
-// writes (the spectral tables and the network's terms).
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T *const_table(const T *p)
-{
-    return (const __attribute__((address_space(4))) T *)p;
-}
 
 // sum over the bins of one group of w_e exp(-sum_m mu[e][m] L_m)   (Eq. 3),
 // evaluated as w_e 2^-x with x = sum_m (mu[e][m] log2 e) L_m from the

@@ -43,6 +43,11 @@ struct TraceGeom {
     int nb[3];
     const int8_t *bricks;
     const int8_t *labels_bm;
+    // The background box (device int[8], or null): every voxel outside the
+    // voxel box [clip[1..3], clip[4..6]) holds label clip[0]; clip[7] is 0 when
+    // the box is empty (the whole grid holds clip[0]).  The walk starts and
+    // ends at this box and charges the rest of the ray to clip[0] in one sum.
+    const int *clip;
     // Detector pixels of one wavefront: a (1 << tile_log2u) x (64 >> tile_log2u)
     // tile (columns x rows) of one angle.  Compact tiles keep the 64 rays of a
     // wavefront close in space, so they cross the same bricks at nearly the
@@ -209,8 +214,9 @@ hipError_t launch_project_rows_split(const TraceGeom &g, const int8_t *labels, c
                                      int n_ang, float *Y, float *out, hipStream_t stream);
 
 // Brick map and brick-major label copy (see TraceGeom::bricks).
+// Also writes the background box (see TraceGeom::clip) to clip (int[8]).
 hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int8_t *bricks, int8_t *labels_bm,
-                               hipStream_t stream, int n_mat = 0, int *bad = nullptr);
+                               int *clip, hipStream_t stream, int n_mat = 0, int *bad = nullptr);
 
 hipError_t launch_pathlengths(const TraceGeom &g, const int8_t *labels, int n_mat, int a0,
                               int n_ang, float *L, hipStream_t stream);

@@ -4,6 +4,8 @@
 // input checks.  The shared device functions live in fcat_device.h.
 #include "fcat_device.h"
 
+#include <climits>
+
 namespace fcat {
 namespace {
 
@@ -549,6 +551,44 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_bricks(const int8_t *__
             labels_bm[(int64_t)gridDim.x * kBrickVox + i] = (int8_t)-1;
 }
 
+// The background box (TraceGeom::clip) from the brick map: the label of
+// brick 0 when that brick is uniform, and the brick-aligned box of every
+// brick that is not uniform with it.  One workgroup.
+__global__ __launch_bounds__(kBlock) void k_clip_box(const int8_t *__restrict__ bricks, int nbx, int nby, int nbz,
+                                                     int nx, int ny, int nz, int *__restrict__ clip)
+{
+    __shared__ int box[6];
+    if (threadIdx.x < 3) box[threadIdx.x] = INT_MAX;
+    else if (threadIdx.x < 6) box[threadIdx.x] = -1;
+    __syncthreads();
+    const int bg = bricks[0];   // -1 if brick 0 is mixed: then every brick is in the box
+    const int nb = nbx * nby * nbz;
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        if (bg >= 0 && bricks[b] == bg) continue;
+        const int c[3] = {b % nbx, (b / nbx) % nby, b / (nbx * nby)};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], c[a]);
+            hi[a] = max(hi[a], c[a]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        atomicMin(&box[a], lo[a]);
+        atomicMax(&box[3 + a], hi[a]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int n[3] = {nx, ny, nz};
+        const bool any = box[3] >= 0;
+        clip[0] = bg;
+        for (int a = 0; a < 3; ++a) {
+            clip[1 + a] = any ? box[a] * kBrickEdge : 0;
+            clip[4 + a] = any ? min((box[3 + a] + 1) * kBrickEdge, n[a]) : 0;
+        }
+        clip[7] = any ? 1 : 0;
+    }
+}
+
 // Cosine and sine of every angle, once per projector call (the walk kernels
 // read them per wavefront instead of evaluating them per lane).
 __global__ __launch_bounds__(kBlock) void k_trig_table(TraceGeom G, double *__restrict__ trig)
@@ -614,12 +654,13 @@ hipError_t launch_project_rows(const TraceGeom &g, const int8_t *labels, const S
 }
 
 hipError_t launch_build_bricks(const int8_t *labels, int nx, int ny, int nz, int8_t *bricks, int8_t *labels_bm,
-                               hipStream_t stream, int n_mat, int *bad)
+                               int *clip, hipStream_t stream, int n_mat, int *bad)
 {
     const int nbx = (nx + kBrickEdge - 1) / kBrickEdge, nby = (ny + kBrickEdge - 1) / kBrickEdge;
     const int nbz = (nz + kBrickEdge - 1) / kBrickEdge;
     hipLaunchKernelGGL(k_build_bricks, dim3(nbx * nby * nbz), dim3(kBuildThreads), 0, stream, labels, nx, ny, nz, nbx,
                        nby, bricks, labels_bm, n_mat, bad);
+    hipLaunchKernelGGL(k_clip_box, dim3(1), dim3(kBlock), 0, stream, bricks, nbx, nby, nbz, nx, ny, nz, clip);
     return hipGetLastError();
 }
 

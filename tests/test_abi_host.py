@@ -119,8 +119,9 @@ def test_other_entry_points_reject_bad_args(fc):
     assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 0, 0, 1, 0x1000, W, 4096, None) == 1
     assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 1, None, W, 4096, None) == 1
     assert lib.fcat_pathlengths(C.byref(geo), C.byref(ph), 3, 0, 1, 0x1000, None, 0, None) == 2
-    # brick map + one 16^3 brick + 16 KiB of padding on each side of the brick-major labels
-    assert lib.fcat_pathlengths_workspace_bytes(C.byref(ph)) == 256 + 4096 + 2 * 16384
+    # brick map + background box + one 16^3 brick + 16 KiB of padding on each side of the
+    # brick-major labels
+    assert lib.fcat_pathlengths_workspace_bytes(C.byref(ph)) == 256 + 256 + 4096 + 2 * 16384
     assert lib.fcat_spectral(0x1000, -1, C.byref(sp), None, None, None, 0, 0x2000, 0x10000, 1 << 20, None) == 1
     assert lib.fcat_spectral(0x1000, 10, C.byref(sp), None, None, None, 2, 0x2000, 0x10000, 1 << 20, None) == 1
     assert lib.fcat_spectral(0x1000, 10, C.byref(sp), None, None, None, 0, 0x2000, 0, 0, None) == 2
