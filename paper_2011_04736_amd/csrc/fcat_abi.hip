@@ -276,7 +276,8 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
 constexpr size_t kDefaultChunkBytes = (size_t)1 << 30;
 // Projector chunks when the job does not fit in one: measured on the head
 // workload (25 MB of group signals per angle), 16 angles per launch took
-// 87.5 ms per step, 32 took 89.0, 40 (1 GiB) 92.0 and 8 88.3.  On the
+// 87.5 ms per step, 32 took 89.0, 40 (1 GiB) 92.0 and 8 88.3 (later, with a
+// faster walk: 16 and 8 84.6 and 84.7, 24 86.0).  On the
 // contrast workload (2 MiB per angle) one launch for all 360 angles is best
 // (2.10 ms; 2.29 ms in chunks of 90).
 constexpr size_t kProjectChunkBytes = (size_t)384 << 20;
@@ -289,6 +290,10 @@ int default_chunk(const Layout &L, int n_angles)
     if (L.per_angle == 0) return n_angles;
     if ((size_t)n_angles * L.per_angle <= kDefaultChunkBytes) return n_angles;
     size_t c = kProjectChunkBytes / L.per_angle;
+    // a multiple of the XCD count when there is room: on the head workload
+    // 8 and 16 angles per launch took 84.7 and 84.6 ms per step, 10, 12 and
+    // 20 took 96.5, 88.3 and 87.0
+    if (c >= (size_t)kXcds) c -= c % kXcds;
     if (c < 1) c = 1;
     if (c > (size_t)n_angles) c = (size_t)n_angles;
     return (int)c;
