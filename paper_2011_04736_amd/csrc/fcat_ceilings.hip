@@ -4,7 +4,8 @@
 // FP32) once with every operand in a vector register and once with one
 // operand in a scalar register (the second form cannot pair instructions
 // and stays near the 16-lane rate), FP64 FMA chains, the hardware base-2 exponential,
-// and BF16 matrix-core products.  Each loop keeps enough independent chains
+// BF16 matrix-core products and FP32 atomic adds to global memory.  Each
+// arithmetic loop keeps enough independent chains
 // per lane, and enough waves per SIMD, to hide latency, and stores a value
 // that depends on every step.
 //
@@ -189,6 +190,22 @@ __global__ void __launch_bounds__(kBlock) k_mfma(float seed, float *__restrict__
     out[blockIdx.x * kBlock + threadIdx.x] = s;
 }
 
+// FP32 atomic adds to global memory (no return value), as the image
+// back-projector issues them: each wavefront instruction adds to 64
+// consecutive floats, and successive instructions of a wavefront move on
+// through a 64 MiB region (every address stays below kAtomWords).
+constexpr int kAtomIters = 64;
+constexpr uint32_t kAtomWords = 1u << 24;
+__global__ void __launch_bounds__(kBlock) k_atomic(float *__restrict__ buf)
+{
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t w = t >> 6, l = t & 63u;
+    for (int i = 0; i < kAtomIters; ++i) {
+        const uint32_t idx = ((w * (uint32_t)kAtomIters + (uint32_t)i) * 64u * 7u + l) & (kAtomWords - 1u);
+        unsafeAtomicAdd(buf + idx, 1.0f);
+    }
+}
+
 // Best (shortest) duration in ms of kTimed launches after two untimed ones.
 template <typename F>
 float best_ms(F launch, hipStream_t s)
@@ -235,20 +252,24 @@ int main()
     const float t_f64 = best_ms([&] { hipLaunchKernelGGL(k_fma64, dim3(kBlocks), dim3(kBlock), 0, s, 1.0, (double *)buf); }, s);
     const float t_exp = best_ms([&] { hipLaunchKernelGGL(k_exp2, dim3(kBlocks), dim3(kBlock), 0, s, 0.5f, (float *)buf); }, s);
     const float t_mma = best_ms([&] { hipLaunchKernelGGL(k_mfma, dim3(kBlocks), dim3(kBlock), 0, s, 0.5f, (float *)buf); }, s);
+    static_assert((int64_t)kAtomWords * 4 <= 2 * kCopyBytes, "atomic region must fit the buffer");
+    const float t_atom = best_ms([&] { hipLaunchKernelGGL(k_atomic, dim3(kBlocks), dim3(kBlock), 0, s, (float *)buf); }, s);
 
     const double lanes = (double)kBlocks * kBlock;
     const double copy_bytes = 2.0 * (double)kCopyBytes;
     const double fma_flop = 2.0 * lanes * kChains * kIters;
     const double exps = lanes * kChains * kIters;
     const double mfma_flop = 2.0 * 32 * 32 * 16 * ((double)kBlocks * (kBlock / kWave)) * kMfmaChains * kMfmaIters;
+    const double atomics = lanes * kAtomIters;
 
     std::printf("{\"copy_GBps\": %.1f, \"fma_f32_TFLOPs\": %.2f, \"fma_f32_scalar_operand_TFLOPs\": %.2f, "
                 "\"fma_f64_TFLOPs\": %.2f, \"exp2_f32_Gps\": %.1f, \"mfma_bf16_TFLOPs\": %.1f, "
+                "\"atomic_add_f32_Gps\": %.1f, "
                 "\"ms\": {\"copy\": %.4f, \"fma_f32\": %.4f, \"fma_f32_scalar_operand\": %.4f, \"fma_f64\": %.4f, "
-                "\"exp2_f32\": %.4f, \"mfma_bf16\": %.4f}}\n",
+                "\"exp2_f32\": %.4f, \"mfma_bf16\": %.4f, \"atomic_add_f32\": %.4f}}\n",
                 copy_bytes / (t_copy * 1e-3) / 1e9, fma_flop / (t_f32 * 1e-3) / 1e12, fma_flop / (t_f32s * 1e-3) / 1e12,
-                fma_flop / (t_f64 * 1e-3) / 1e12, exps / (t_exp * 1e-3) / 1e9, mfma_flop / (t_mma * 1e-3) / 1e12, t_copy,
-                t_f32, t_f32s, t_f64, t_exp, t_mma);
+                fma_flop / (t_f64 * 1e-3) / 1e12, exps / (t_exp * 1e-3) / 1e9, mfma_flop / (t_mma * 1e-3) / 1e12,
+                atomics / (t_atom * 1e-3) / 1e9, t_copy, t_f32, t_f32s, t_f64, t_exp, t_mma, t_atom);
     CHECK(hipFree(buf));
     CHECK(hipStreamDestroy(s));
     return 0;

@@ -71,3 +71,12 @@ def test_measured_ceilings_price_walks_by_the_steps_taken():
     assert "frac_measured" not in result["roofline"] and "frac_measured" not in walk
     assert walk["executed"]["measured_peak"] == 60.0 and walk["executed"]["frac_measured"] == round(20.0 / 60.0, 4)
     assert psf["measured_peak"] == 120.0 and psf["frac_measured"] == round(100.0 / 120.0, 4)
+
+
+def test_atomic_rows_take_the_measured_ceiling_as_peak():
+    e = {"kernel": "k_image_rays<true>", "bound": "atomic", "achieved": 30.0, "peak": None, "unit": "Gatomic/s",
+         "frac": None}
+    result = {"next": {"image_projector": {"backproject": {"roofline": e}}}}
+    bench.apply_measured_ceilings(result, {"fma_f32_TFLOPs": 120.0, "copy_GBps": 5000.0, "mfma_bf16_TFLOPs": 2000.0,
+                                           "atomic_add_f32_Gps": 120.0})
+    assert e["measured_peak"] == 120.0 and e["peak"] == 120.0 and e["frac"] == 0.25
