@@ -105,6 +105,40 @@ def test_adam_step_matches_oracle(fc):
     np.testing.assert_allclose(tr.adam_m.cpu().numpy(), m, rtol=1e-5, atol=1e-12)
 
 
+def test_epoch_matches_separate_steps(fc):
+    """Within an epoch each Adam step rewrites, in place, the BF16 views of
+    the weights that the next step's gradient kernel reads; a separate
+    fcat_mlp_train_step call instead builds every view afresh from the FP32
+    weights.  One epoch of three batches (a ragged last one) in a shuffled
+    order must therefore give bit-identical weights, Adam moments and batch
+    losses to three single steps over the same samples: a view element the
+    in-place rewrite missed would leave a stale weight in the later steps."""
+    import torch
+    cfg, s, L, Y, sp, sur, p, in_scale, osc = _setup(fc, torch, n=1000, seed=13, scale=2.0)
+    Lt, Yt = _t(torch, L), _t(torch, Y)
+    order = torch.as_tensor(np.random.default_rng(13).permutation(1000).astype(np.int32), device="cuda")
+    batch = 384
+
+    def fresh():
+        q = sur.params.clone()
+        return fc.MlpTrain(params=q, adam_m=torch.zeros_like(q), adam_v=torch.zeros_like(q), lr=3e-3)
+
+    ta = fresh()
+    la = torch.zeros(3, dtype=torch.float32, device="cuda")
+    fc.fcat_mlp_train_epoch(ta, sur, sp, Lt, Yt, order, batch, batch_loss=la)
+    tb = fresh()
+    lb = torch.zeros(3, dtype=torch.float32, device="cuda")
+    for b, base in enumerate(range(0, 1000, batch)):
+        fc.fcat_mlp_train_step(tb, sur, sp, Lt, Yt, order=order, base=base, count=min(batch, 1000 - base),
+                               loss=lb[b:b + 1])
+    assert ta.step == tb.step == 3
+    moved = (ta.params != sur.params).float().mean().item()
+    print(f"epoch vs steps: losses {la.cpu().numpy()}, share of weights moved {moved:.3f}")
+    assert moved > 0.9
+    for a, b in ((ta.params, tb.params), (ta.adam_m, tb.adam_m), (ta.adam_v, tb.adam_v), (la, lb)):
+        assert torch.equal(a, b)
+
+
 def test_setup_stats_match_oracle(fc):
     import torch
     cfg, s, L, Y, sp, sur, p, in_scale, osc = _setup(fc, torch, n=5000, seed=7)
