@@ -352,7 +352,12 @@ def image_projector_stage(pb, cfg, args, torch, fc, counts):
                                      "work_unit": "one FP32 atomic add per Siddon voxel segment",
                                      "alu_view": alu_roof("k_image_rays<true>", OPS_PER_SEGMENT * segs, b_ms,
                                                           work_unit=f"{OPS_PER_SEGMENT} lane-ops per Siddon voxel "
-                                                                    "segment")}},
+                                                                    "segment"),
+                                     # the same adds against the ceiling of adds whose lanes
+                                     # each fall on a line of their own
+                                     "scattered_view": {"kernel": "k_image_rays<true>", "bound": "atomic_scattered",
+                                                        "achieved": round(segs / (b_ms * 1e-3) / 1e9, 2),
+                                                        "peak": None, "unit": "Gatomic/s", "frac": None}}},
     }
 
 
@@ -839,6 +844,8 @@ def measured_ceiling(entry: dict, ceil: dict):
         return ceil["mfma_bf16_TFLOPs"]
     if bound == "atomic" and unit == "Gatomic/s":
         return ceil.get("atomic_add_f32_Gps")
+    if bound == "atomic_scattered" and unit == "Gatomic/s":
+        return ceil.get("atomic_add_f32_scattered_Gps")
     return None
 
 

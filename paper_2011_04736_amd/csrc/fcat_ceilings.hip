@@ -4,7 +4,8 @@
 // FP32) once with every operand in a vector register and once with one
 // operand in a scalar register (the second form cannot pair instructions
 // and stays near the 16-lane rate), FP64 FMA chains, the hardware base-2 exponential,
-// BF16 matrix-core products and FP32 atomic adds to global memory.  Each
+// BF16 matrix-core products and FP32 atomic adds to global memory (lane-
+// contiguous and scattered).  Each
 // arithmetic loop keeps enough independent chains
 // per lane, and enough waves per SIMD, to hide latency, and stores a value
 // that depends on every step.
@@ -206,6 +207,30 @@ __global__ void __launch_bounds__(kBlock) k_atomic(float *__restrict__ buf)
     }
 }
 
+// The same adds with each lane on a line of its own: lane l of instruction
+// i adds to a word picked by an integer hash of (wavefront, i, l) (a
+// multiply-xorshift mix with the constants of Wellons' lowbias32), so one wavefront instruction touches 64 scattered
+// 128-byte lines of the 64 MiB region, as the image back-projector's do
+// where neighbouring rays sit in different voxels.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void __launch_bounds__(kBlock) k_atomic_scattered(float *__restrict__ buf)
+{
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    for (int i = 0; i < kAtomIters; ++i) {
+        const uint32_t idx = mix32(t * (uint32_t)kAtomIters + (uint32_t)i) & (kAtomWords - 1u);
+        unsafeAtomicAdd(buf + idx, 1.0f);
+    }
+}
+
 // Best (shortest) duration in ms of kTimed launches after two untimed ones.
 template <typename F>
 float best_ms(F launch, hipStream_t s)
@@ -254,6 +279,7 @@ int main()
     const float t_mma = best_ms([&] { hipLaunchKernelGGL(k_mfma, dim3(kBlocks), dim3(kBlock), 0, s, 0.5f, (float *)buf); }, s);
     static_assert((int64_t)kAtomWords * 4 <= 2 * kCopyBytes, "atomic region must fit the buffer");
     const float t_atom = best_ms([&] { hipLaunchKernelGGL(k_atomic, dim3(kBlocks), dim3(kBlock), 0, s, (float *)buf); }, s);
+    const float t_atom_sc = best_ms([&] { hipLaunchKernelGGL(k_atomic_scattered, dim3(kBlocks), dim3(kBlock), 0, s, (float *)buf); }, s);
 
     const double lanes = (double)kBlocks * kBlock;
     const double copy_bytes = 2.0 * (double)kCopyBytes;
@@ -264,12 +290,14 @@ int main()
 
     std::printf("{\"copy_GBps\": %.1f, \"fma_f32_TFLOPs\": %.2f, \"fma_f32_scalar_operand_TFLOPs\": %.2f, "
                 "\"fma_f64_TFLOPs\": %.2f, \"exp2_f32_Gps\": %.1f, \"mfma_bf16_TFLOPs\": %.1f, "
-                "\"atomic_add_f32_Gps\": %.1f, "
+                "\"atomic_add_f32_Gps\": %.1f, \"atomic_add_f32_scattered_Gps\": %.1f, "
                 "\"ms\": {\"copy\": %.4f, \"fma_f32\": %.4f, \"fma_f32_scalar_operand\": %.4f, \"fma_f64\": %.4f, "
-                "\"exp2_f32\": %.4f, \"mfma_bf16\": %.4f, \"atomic_add_f32\": %.4f}}\n",
+                "\"exp2_f32\": %.4f, \"mfma_bf16\": %.4f, \"atomic_add_f32\": %.4f, "
+                "\"atomic_add_f32_scattered\": %.4f}}\n",
                 copy_bytes / (t_copy * 1e-3) / 1e9, fma_flop / (t_f32 * 1e-3) / 1e12, fma_flop / (t_f32s * 1e-3) / 1e12,
                 fma_flop / (t_f64 * 1e-3) / 1e12, exps / (t_exp * 1e-3) / 1e9, mfma_flop / (t_mma * 1e-3) / 1e12,
-                atomics / (t_atom * 1e-3) / 1e9, t_copy, t_f32, t_f32s, t_f64, t_exp, t_mma, t_atom);
+                atomics / (t_atom * 1e-3) / 1e9, atomics / (t_atom_sc * 1e-3) / 1e9, t_copy, t_f32, t_f32s, t_f64,
+                t_exp, t_mma, t_atom, t_atom_sc);
     CHECK(hipFree(buf));
     CHECK(hipStreamDestroy(s));
     return 0;

@@ -80,3 +80,15 @@ def test_atomic_rows_take_the_measured_ceiling_as_peak():
     bench.apply_measured_ceilings(result, {"fma_f32_TFLOPs": 120.0, "copy_GBps": 5000.0, "mfma_bf16_TFLOPs": 2000.0,
                                            "atomic_add_f32_Gps": 120.0})
     assert e["measured_peak"] == 120.0 and e["peak"] == 120.0 and e["frac"] == 0.25
+
+
+def test_scattered_atomic_view_takes_its_own_ceiling():
+    v = {"kernel": "k_image_rays<true>", "bound": "atomic_scattered", "achieved": 30.0, "peak": None,
+         "unit": "Gatomic/s", "frac": None}
+    e = {"kernel": "k_image_rays<true>", "bound": "atomic", "achieved": 30.0, "peak": None, "unit": "Gatomic/s",
+         "frac": None, "scattered_view": v}
+    result = {"next": {"image_projector": {"backproject": {"roofline": e}}}}
+    bench.apply_measured_ceilings(result, {"fma_f32_TFLOPs": 120.0, "copy_GBps": 5000.0, "mfma_bf16_TFLOPs": 2000.0,
+                                           "atomic_add_f32_Gps": 300.0, "atomic_add_f32_scattered_Gps": 40.0})
+    assert e["peak"] == 300.0 and e["frac"] == 0.1
+    assert v["peak"] == 40.0 and v["frac"] == 0.75
