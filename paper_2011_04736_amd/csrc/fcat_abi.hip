@@ -209,7 +209,7 @@ TraceGeom make_geom(const fcat_geometry_t *g, const fcat_phantom_t *p)
 }
 
 struct Layout {
-    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, bricks, trig, Y, fixed;
+    size_t flags, muT, w, Wg, Wsg, afrag, wtile, pfrag, frag, mbar, cslots, bricks, trig, Y, fixed;
     size_t scale, unitk, flood, yflood;   // projection stage: c_g, unit kernels, flood, its group signals
     size_t per_angle;    // bytes of per-angle chunk buffers (group signals)
     size_t y_per_angle;  // bytes of group signal per angle (0 without psf)
@@ -253,6 +253,8 @@ Layout layout(const SpecTables &t, const fcat_geometry_t *g, bool with_psf, size
     if (surrogate) o += align_up((size_t)kMlpFrags * kWave * 16);
     L.mbar = o;
     if (surrogate) o += align_up((size_t)FCAT_MLP_MAX_IO * sizeof(float));
+    L.cslots = o;   // ray counts of the surrogate projector, spread over slots
+    if (surrogate) o += align_up((size_t)kCountSlots * kCountSlotInts * sizeof(int));
     L.bricks = o;
     o += align_up(nbricks);
     L.trig = o;   // cosine and sine of every angle
@@ -650,6 +652,17 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     const float *S = scatter ? scatter->maps : nullptr;
     const int A = geometry->n_angles;
     hipError_t e;
+    int *cslots = (sur && surrogate->counts) ? at<int>(workspace, L.cslots) : nullptr;
+    if (cslots) {
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        e = launch_zero_ints(cslots, kCountSlots * kCountSlotInts, stream);
+        if (e != hipSuccess) return device_fail(e, "clear count slots");
+    }
+    // the slots' totals into the caller's counters, after the last walk
+    auto add_counts = [&]() {
+        StageTimer tm(FCAT_STAGE_TRACE, stream);
+        return cslots ? launch_count_slots_sum(cslots, surrogate->counts, stream) : hipSuccess;
+    };
     float *unitk = at<float>(workspace, L.unitk);
     // optical spread and group sum of n angles of group signals (unit kernels without psf)
     auto spread = [&](const float *Yc, int n, float *dst) {
@@ -680,7 +693,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
     };
     auto rows = [&](int a0, int n, float *Yc, float *outc) {
         if (sur)
-            return launch_project_rows_mlp(G, t, mt, spectral->flood, S, a0, n, Yc, outc, surrogate->counts, stream);
+            return launch_project_rows_mlp(G, t, mt, spectral->flood, S, a0, n, Yc, outc, cslots, stream);
         return split ? launch_project_rows_split(G, phantom->labels, t, sp, spectral->flood, S, a0, n, Yc, outc, stream)
                      : launch_project_rows(G, phantom->labels, t, spectral->flood, S, a0, n, Yc, outc, stream);
     };
@@ -690,6 +703,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
             e = rows(0, A, nullptr, out);
         }
         if (e != hipSuccess) return device_fail(e, "project_rows");
+        if ((e = add_counts()) != hipSuccess) return device_fail(e, "count_slots_sum");
         if (proj && (e = to_projections(out, A)) != hipSuccess) return device_fail(e, "log_projection");
         return FCAT_OK;
     }
@@ -711,6 +725,7 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
         if (grouped && (e = spread(Y, n, outc)) != hipSuccess) return device_fail(e, "psf");
         if (proj && (e = to_projections(outc, n)) != hipSuccess) return device_fail(e, "log_projection");
     }
+    if ((e = add_counts()) != hipSuccess) return device_fail(e, "count_slots_sum");
     return FCAT_OK;
 }
 
@@ -1430,10 +1445,11 @@ fcat_status fcat_walk_stats(const fcat_geometry_t *geometry, const fcat_phantom_
     G.bricks = bricks;
     G.labels_bm = labels_bm_at(bricks, phantom);
     hipError_t e = launch_zero_ints(reinterpret_cast<int *>(counts), 2 * kWalkCounts, stream);
+    int *clip = clip_at(bricks, phantom);
+    G.clip = clip;
     if (e == hipSuccess)
-        G.clip = clip_at(bricks, phantom);
         e = launch_build_bricks(phantom->labels, phantom->nx, phantom->ny, phantom->nz, bricks,
-                                const_cast<int8_t *>(G.labels_bm), clip_at(bricks, phantom), stream);
+                                const_cast<int8_t *>(G.labels_bm), clip, stream);
     if (e == hipSuccess)
         e = launch_walk_stats(G, a_begin, a_end - a_begin, reinterpret_cast<unsigned long long *>(counts), stream);
     if (e != hipSuccess) return device_fail(e, "walk_stats");

@@ -163,12 +163,22 @@ hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *
                             int64_t n, float *partial, float *in_scale, float *out_scale, float *tau_max,
                             hipStream_t stream);
 hipError_t launch_mlp_spectral(const SpecTables &t, const MlpTables &m, const SurrogateIO &io, hipStream_t stream);
+// Ray counts of the surrogate projector: wavefront gw adds its two counts
+// (rays by the network, rays by the exact sum) to the first two ints of slot
+// gw % kCountSlots, one 64-byte line per slot, so that no address takes more
+// than a small share of the adds (adds from every wavefront to one address
+// took 3 ms per launch of 16 head angles); launch_count_slots_sum adds the
+// slots' totals to the caller's two counters.
+constexpr int kCountSlots = 512;
+constexpr int kCountSlotInts = 16;
 // The surrogate projector for angles [a0, a0 + n_ang) in one pass (walk,
 // network where validated, exact sum elsewhere, scatter); Y and out as in
-// launch_project_rows; counts as SurrogateIO::counts.
+// launch_project_rows; slots: kCountSlots * kCountSlotInts ints, zero before
+// the first launch of a call, or null.
 hipError_t launch_project_rows_mlp(const TraceGeom &g, const SpecTables &t, const MlpTables &m, const float *flood,
-                                   const float *scatter, int a0, int n_ang, float *Y, float *out, int *counts,
+                                   const float *scatter, int a0, int n_ang, float *Y, float *out, int *slots,
                                    hipStream_t stream);
+hipError_t launch_count_slots_sum(const int *slots, int *counts, hipStream_t stream);
 hipError_t launch_mlp_grad(const SpecTables &t, const MlpTables &m, const float *L, const float *Y, int64_t n_all,
                            const int32_t *order, int64_t base, int count, float *partial, float *loss_partial,
                            hipStream_t stream);

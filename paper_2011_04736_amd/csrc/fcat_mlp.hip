@@ -533,7 +533,7 @@ void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
                                                              const float *__restrict__ flood,
                                                              const float *__restrict__ scatter, int a0, int n_ang,
                                                              int nblk_pad, float *__restrict__ Y,
-                                                             float *__restrict__ out, int *__restrict__ counts)
+                                                             float *__restrict__ out, int *__restrict__ slots)
 {
     __shared__ __align__(16) float lds_all[(kBlock / kWave) * fused_wave_floats<MP>()];
     const int blk = xcd_block(nblk_pad);
@@ -617,11 +617,40 @@ void k_project_rows_mlp(TraceGeom G, SpecTables T, MlpTables M,
     if (!Y) out[(int64_t)a * plane + pix] = total;
     // after the last table read, as flag_nonfinite: a store before them would
     // turn the tables' wave-uniform scalar loads into per-lane vector loads
-    if (counts && lane == __ffsll((unsigned long long)valid_mask) - 1) {
-        atomicAdd(counts + 0, (int)__popcll(use_mask));
-        atomicAdd(counts + 1, (int)__popcll(hit_mask & ~use_mask));
+    if (slots && lane == __ffsll((unsigned long long)valid_mask) - 1) {
+        int *slot = slots + (gw % kCountSlots) * kCountSlotInts;
+        atomicAdd(slot + 0, (int)__popcll(use_mask));
+        atomicAdd(slot + 1, (int)__popcll(hit_mask & ~use_mask));
     }
     flag_nonfinite(G.bad, i0, sc);
+}
+
+// Totals of the count slots (see kCountSlots), added to counts[0] and counts[1].
+__global__ __launch_bounds__(kCountSlots) void k_count_slots_sum(const int *__restrict__ slots,
+                                                                 int *__restrict__ counts)
+{
+    __shared__ int part[2][kCountSlots / kWave];
+    const int t = threadIdx.x;
+    int a = slots[t * kCountSlotInts + 0], b = slots[t * kCountSlotInts + 1];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_down(a, off);
+        b += __shfl_down(b, off);
+    }
+    if ((t & (kWave - 1)) == 0) {
+        part[0][t / kWave] = a;
+        part[1][t / kWave] = b;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int sa = 0, sb = 0;
+        for (int w = 0; w < kCountSlots / kWave; ++w) {
+            sa += part[0][w];
+            sb += part[1][w];
+        }
+        atomicAdd(counts + 0, sa);
+        atomicAdd(counts + 1, sb);
+    }
 }
 
 struct TrainLds {
@@ -1194,15 +1223,21 @@ hipError_t launch_mlp_stats(const SpecTables &t, const float *lin, const float *
     return hipGetLastError();
 }
 
+hipError_t launch_count_slots_sum(const int *slots, int *counts, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_count_slots_sum, dim3(1), dim3(kCountSlots), 0, stream, slots, counts);
+    return hipGetLastError();
+}
+
 hipError_t launch_project_rows_mlp(const TraceGeom &g, const SpecTables &t, const MlpTables &m, const float *flood,
-                                   const float *scatter, int a0, int n_ang, float *Y, float *out, int *counts,
+                                   const float *scatter, int a0, int n_ang, float *Y, float *out, int *slots,
                                    hipStream_t stream)
 {
     const int64_t waves = (int64_t)n_ang * tiles_per_angle_host(g);
     const int nblk = padded_blocks(waves);
 #define FCAT_FUSED(MPV)                                                                                          \
     hipLaunchKernelGGL(k_project_rows_mlp<MPV>, dim3(nblk), dim3(kBlock), 0, stream, g, t, m, flood, scatter, a0, \
-                       n_ang, nblk, Y, out, counts)
+                       n_ang, nblk, Y, out, slots)
     switch (t.mp) {
     case 8: FCAT_FUSED(8); break;
     case 10: FCAT_FUSED(10); break;
