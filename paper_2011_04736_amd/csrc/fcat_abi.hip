@@ -658,10 +658,12 @@ static fcat_status project_impl(const fcat_geometry_t *geometry, const fcat_phan
         e = launch_zero_ints(cslots, kCountSlots * kCountSlotInts, stream);
         if (e != hipSuccess) return device_fail(e, "clear count slots");
     }
-    // the slots' totals into the caller's counters, after the last walk
-    auto add_counts = [&]() {
-        StageTimer tm(FCAT_STAGE_TRACE, stream);
-        return cslots ? launch_count_slots_sum(cslots, surrogate->counts, stream) : hipSuccess;
+    // the slots' totals into the caller's counters, after the last walk (timed
+    // with the set-up, so that the walk's stage holds one launch per chunk)
+    auto add_counts = [&]() -> hipError_t {
+        if (!cslots) return hipSuccess;
+        StageTimer tm(FCAT_STAGE_PREP, stream);
+        return launch_count_slots_sum(cslots, surrogate->counts, stream);
     };
     float *unitk = at<float>(workspace, L.unitk);
     // optical spread and group sum of n angles of group signals (unit kernels without psf)

@@ -297,3 +297,39 @@ def test_training_resumes_from_a_checkpoint(fc, tmp_path):
     np.testing.assert_array_equal(rep_b.cell_ok, rep_a.cell_ok)
     with np.load(ck, allow_pickle=False) as z:
         assert int(z["epoch"]) == 3 and int(z["step"]) > 0
+
+
+def test_stage_timer_counts_one_walk_launch_per_chunk(fc):
+    """The benchmark divides the walk stage's time by its launch count: every
+    mode must record exactly one walk launch per angle chunk, a surrogate
+    call with ray counts included (its count total is set-up work), and the
+    counts must cover every valid ray of the detector."""
+    import torch
+    from paper_2011_04736_amd import surrogate as sg
+    cfg = synth.make_config(2)                     # with a PSF: group signals pass through angle chunks
+    s = cfg.spectral
+    M, G = s.n_mat, s.n_groups
+    pb = fc.upload(cfg)
+    rng = np.random.default_rng(8)
+    p = sg.init_params(M, G, 2)
+    sur = fc.Surrogate(params=_t(torch, p), in_scale=_t(torch, np.full(M, 1.0 / 500.0, np.float32)),
+                       out_scale=_t(torch, rng.uniform(0.2, 2.0, size=G).astype(np.float32)),
+                       lin=fc.fcat_mlp_linear_term(pb.spectral), cell_ok=_t(torch, np.ones(M * 16, np.uint8)),
+                       cell_lo=0.0, cell_hi=1e30, counts=torch.zeros(2, dtype=torch.int32, device="cuda"))
+    A = cfg.geometry.n_angles
+    chunk = 100                                    # 360 angles: three chunks of 100 and one of 60
+    fc.fcat_timing_enable(True)
+    try:
+        for mode in ("plain", "split_bf16", "surrogate"):
+            fc.fcat_timing_read(reset=True)
+            fc.fcat_project(pb, mode=mode, surrogate=sur if mode == "surrogate" else None, angles_per_chunk=chunk)
+            torch.cuda.synchronize()
+            st = fc.fcat_timing_read(reset=True)
+            assert st["trace"][1] == -(-A // chunk), (mode, st)
+    finally:
+        fc.fcat_timing_enable(False)
+    n_net, n_exact = (int(x) for x in sur.counts.cpu().numpy())
+    print(f"{A} angles in chunks of {chunk}: rays by the network {n_net}, by the exact sum {n_exact}")
+    assert n_exact == 0 and 0 < n_net <= A * cfg.geometry.nu * cfg.geometry.nv
+    del pb
+    torch.cuda.empty_cache()
