@@ -120,32 +120,52 @@ __device__ uint32_t siddon_segments(const TraceGeom &G, double ct, double st, in
 // meet the grid, [1] brick steps, [2] mixed bricks entered, [3] voxel steps,
 // [4] wavefront iterations of the voxel loop times 64 (lane slots), [5]
 // Siddon voxel segments.  Per-lane counts are summed over the wavefront with
-// shuffles, then one 64-bit atomic per wavefront and counter.
+// shuffles and over the workgroup in LDS, then one 64-bit atomic per
+// workgroup and counter (every add goes to one of six words, so their
+// number sets much of the call's time).
 template <int MP>
 __global__ __launch_bounds__(kBlock) void k_walk_stats(TraceGeom G, int a0, int n_ang, int nblk_pad,
                                                        unsigned long long *__restrict__ counts)
 {
     __shared__ float acc_all[(kBlock / kWave) * mat_acc_floats<MP>()];
+    __shared__ unsigned long long part[kBlock / kWave][kWalkCounts];
     const int blk = xcd_block(nblk_pad);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & (kWave - 1);
     const int gw = blk * (kBlock / kWave) + wave;
-    if (gw >= n_ang * tiles_per_angle(G)) return;
-    const PixelOf px = pixel_of(G, gw, lane);
-    double st, ct;
-    angle_trig(G, a0 + px.al, st, ct);
-    float L[MP];
-    Ray r{};
-    const bool hit = px.valid && setup_ray(G, ct, st, px.iv, px.iu, r);
-    StepCount c;
-    trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, acc_all + wave * mat_acc_floats<MP>(), L, c);
-    const uint32_t segs = px.valid ? siddon_segments(G, ct, st, px.iv, px.iu) : 0u;
-    unsigned long long v[kWalkCounts] = {hit ? 1ull : 0ull, hit ? (unsigned long long)c.bricks : 0ull,
-                                         c.mixed_bricks, c.voxels, 64ull * c.wave_voxel_iters, segs};
+    unsigned long long v[kWalkCounts] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    // wave-uniform: a wavefront past the last tile adds zeros but still
+    // reaches the workgroup barrier below
+    if (gw < n_ang * tiles_per_angle(G)) {
+        const PixelOf px = pixel_of(G, gw, lane);
+        double st, ct;
+        angle_trig(G, a0 + px.al, st, ct);
+        float L[MP];
+        Ray r{};
+        const bool hit = px.valid && setup_ray(G, ct, st, px.iv, px.iu, r);
+        StepCount c;
+        trace_bricks<MP>(r, hit, G, G.labels_bm, G.bricks, acc_all + wave * mat_acc_floats<MP>(), L, c);
+        const uint32_t segs = px.valid ? siddon_segments(G, ct, st, px.iv, px.iu) : 0u;
+        v[0] = hit ? 1ull : 0ull;
+        v[1] = hit ? (unsigned long long)c.bricks : 0ull;
+        v[2] = c.mixed_bricks;
+        v[3] = c.voxels;
+        v[4] = 64ull * c.wave_voxel_iters;
+        v[5] = segs;
 #pragma unroll
-    for (int k = 0; k < kWalkCounts; ++k) {
-        for (int off = kWave / 2; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
-        if (lane == 0 && v[k]) atomicAdd(counts + k, v[k]);
+        for (int k = 0; k < kWalkCounts; ++k)
+            for (int off = kWave / 2; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kWalkCounts; ++k) part[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kWalkCounts) {
+        unsigned long long sum = 0ull;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) sum += part[w][threadIdx.x];
+        if (sum) atomicAdd(counts + threadIdx.x, sum);
     }
 }
 
